@@ -1,0 +1,191 @@
+/*
+ * momenti.h -- C ABI of an MI355X (gfx950) implementation of the MOMENTI
+ * top-k multidimensional motif search (Ceccarello, Monaco, Silvestri,
+ * "MOMENTI: Scalable Motif Mining in Multidimensional Time Series", PVLDB 18(10), 2025).
+ *
+ * Problem (section 3.1, definition "top-k multidimensional motifs"): given a
+ * D-dimensional series of length n, a window length w, a motif dimensionality
+ * d and a count k, return the k pairs of windows (a, b) with the smallest
+ * d-dimensional distance dist_d (definition "d-dimensional distance": the sum
+ * of the d smallest per-dimension z-normalised Euclidean distances, Eq. zned),
+ * no two of them overlapping.
+ *
+ * Method (Algorithm 1 with Algorithm 2 and sections 6.1-6.2): every window of
+ * every dimension is hashed with K concatenated discretised random projections
+ * (Eq. drp) in L tensored repetitions; rounds i = K..1 scan the pairs whose
+ * hash prefixes of length i collide in at least d dimensions, verify them
+ * under dist_d, and stop as soon as the probability of having missed a better
+ * pair is at most delta (Lemma 6.1 / Eq. probnotcolliding).
+ *
+ * Conventions
+ *   - Windows are 0-based: window a covers series[f][a .. a+w-1], a in [0, n-w].
+ *   - The series is [D][n], row-major, each dimension contiguous, float64 or
+ *     float32, in host or device memory (momenti_opts.series_on_device). The
+ *     caller owns it; the library only reads it during momenti_hash (or copies
+ *     it when it is on the host).
+ *   - Every function returns a status code (MOMENTI_OK ... MOMENTI_E_*); no
+ *     exception crosses the boundary. On error momenti_last_error() returns a
+ *     thread-local message.
+ *   - A plan is not thread-safe; distinct plans may be used from distinct threads.
+ *   - All GPU work runs on opts.stream (a hipStream_t; NULL = the default stream).
+ */
+#ifndef MOMENTI_H
+#define MOMENTI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define MOMENTI_OK 0             /* the search stopped under the stopping rule */
+#define MOMENTI_OK_FALLBACK 1    /* no round stopped: the exact all-pairs answer was returned */
+#define MOMENTI_E_ARG (-1)       /* invalid argument (see each function) */
+#define MOMENTI_E_NOMEM (-2)     /* mem_limit too small for the smallest index, or a device allocation failed */
+#define MOMENTI_E_DEVICE (-3)    /* a HIP runtime call failed */
+#define MOMENTI_E_STATE (-4)     /* call out of order (e.g. search before hash) */
+#define MOMENTI_E_UNSUPPORTED (-5) /* exact fallback needed but the input is too large for it */
+
+/* Series element type. */
+#define MOMENTI_F64 0
+#define MOMENTI_F32 1
+
+/* Arithmetic of the projection a . x of Eq. drp (the hash). Statistics and
+ * the dist_d verification are always float64. FP64 and F32 are the plain
+ * method; BF16 and FP8 (e4m3, the z-normalisation being the per-window
+ * scaling) change the hash function itself and are reported against FP64. */
+#define MOMENTI_PROJ_F64 0
+#define MOMENTI_PROJ_F32 1
+#define MOMENTI_PROJ_BF16 2
+#define MOMENTI_PROJ_FP8 3
+
+/* Stopping rule. TENSOR: Lemma 6.1 (the bound for the tensored index, as
+ * printed: P_t(i', J') = (1 - p^ceil(i'))^(J' div m) (1 - p^floor(i'))^(J' mod m)).
+ * LEMMA52: Eq. probnotcolliding of Lemma 5.2 ((1 - p^i)^J (1 - p^(i+1))^(L-J)). */
+#define MOMENTI_STOP_TENSOR 0
+#define MOMENTI_STOP_LEMMA52 1
+
+typedef struct momenti_plan momenti_plan;   /* opaque, owned by the library */
+
+typedef struct {
+    uint64_t seed;            /* seed of the random projections (Philox4x32-10 streams) */
+    int32_t K;                /* maximum concatenations: even, 2..8 (default 8, section 7 defaults) */
+    int32_t L;                /* maximum repetitions, 1..1024 (default 200) */
+    double r;                 /* quantisation width of Eq. drp; <= 0 estimates it (section 6.1) */
+    int32_t proj;             /* MOMENTI_PROJ_* (default F32) */
+    int32_t stop_rule;        /* MOMENTI_STOP_* (default TENSOR) */
+    int32_t series_on_device; /* 1: the series pointer passed to momenti_hash is device memory */
+    int32_t pool_size;        /* verified pairs kept on the device; 0 = max(4096, 64 k) */
+    int32_t batch_reps;       /* repetitions traversed per launch; 0 = chosen from mem_limit */
+    int32_t reserved;
+    void* stream;             /* hipStream_t, NULL = default stream */
+} momenti_opts;
+
+typedef struct {
+    int64_t a, b;             /* window starts, a < b, 2 (b - a) > w */
+    double dist_d;            /* definition "d-dimensional distance" */
+    double dist_max;          /* Eq. distdmax: largest distance among the chosen dimensions */
+    uint64_t dims[2];         /* bit f set for each chosen dimension (D <= 128) */
+} momenti_motif;
+
+typedef struct {
+    double t_hash_ms;         /* device time of statistics + projection (+ r estimate) */
+    double t_search_ms;       /* wall time of the traversal */
+    int32_t i_stop, j_stop;   /* round (prefix length) and repetition (1-based) at which STOP held; 0 on fallback */
+    int32_t L_used, K;        /* repetitions after the memory cap; concatenations */
+    double r;                 /* quantisation width in use */
+    int64_t n_steps;          /* (round, repetition) steps traversed */
+    int64_t n_collisions;     /* non-trivial one-dimensional colliding pairs scanned */
+    int64_t n_cand;           /* candidate pairs emitted (W >= d, first time at this repetition) */
+    int64_t n_verified;       /* dist_d evaluations */
+    uint64_t peak_bytes;      /* device bytes held by the plan at its peak */
+    int32_t fallback;         /* 1 when the exact all-pairs answer was returned */
+    int32_t pool_overflow;    /* times the verified-pair pool had to be enlarged */
+    int32_t batch_reps;       /* repetitions per launch actually used */
+    int32_t reserved;
+} momenti_report;
+
+/* Fill *o with the defaults (K = 8, L = 200, r estimated, F32 projection,
+ * TENSOR rule, delta-independent; seed 0x5EED). */
+void momenti_default_opts(momenti_opts* o);
+
+/* Plan a search over series of length n (>= w + 1) with D (1..128) dimensions
+ * and window w (4..8192). mem_limit bounds the device bytes the plan may hold
+ * (series copy, statistics, index, traversal buffers); the number of
+ * repetitions is the largest L' <= opts.L whose index fits (index size
+ * O(K L D n), Theorem "space"):
+ *   fixed = n D s + 16 n_s D + 32 n_s D + 64 MiB   (s = 8 for float64, 4 for float32 series)
+ *   index(L') = 4 n_s D (ceil(L'/m') + min(L', m')),  m' = ceil(sqrt(L'))
+ * L_used = max{L' : fixed + index(L') <= mem_limit}, E_NOMEM when L' = 1 does
+ * not fit. dtype (MOMENTI_F64 / MOMENTI_F32) is the element type of the
+ * series later passed to momenti_hash. Draws the random projections on the
+ * host (Philox4x32-10 streams of opts.seed). *out receives a new plan.
+ * Errors: E_ARG (bad sizes or options), E_NOMEM, E_DEVICE. */
+int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t dtype,
+                    uint64_t mem_limit, const momenti_opts* opts /* NULL = defaults */);
+
+/* Index construction (Algorithm 1 first loop, section 6.1): rolling window
+ * statistics, the r estimate (unless fixed by opts.r), and the tensored hash
+ * index of every window of every dimension. series: [D][n] of the plan's
+ * dtype, host or device memory per opts.series_on_device (device memory is
+ * borrowed until momenti_destroy). May be called again with new data.
+ * Errors: E_ARG (null series), E_NOMEM, E_DEVICE. */
+int momenti_hash(momenti_plan* p, const void* series);
+
+/* Index traversal (Algorithm 1 rounds i = K..1, repetitions j = 1..L, with
+ * Algorithm 2): writes up to k motifs to out (caller-owned, capacity >= k) in
+ * increasing (dist_d, a, b) order and their count to *n_out (< k only when
+ * fewer non-overlapping non-trivial pairs exist). rep may be NULL.
+ * d in [1, D], k in [1, 4096], delta in (0, 1).
+ * Returns MOMENTI_OK, MOMENTI_OK_FALLBACK (exact answer, no step stopped),
+ * or E_ARG, E_STATE (momenti_hash not called), E_NOMEM, E_DEVICE, E_UNSUPPORTED
+ * (the exact fallback is limited to n - w + 1 <= 65536 windows). */
+int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
+                   int32_t* n_out, momenti_report* rep);
+
+/* One call: prepare + hash + search + destroy. Arguments as above. */
+int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_t w, int32_t d,
+                 int32_t k, double delta, uint64_t mem_limit, const momenti_opts* opts,
+                 momenti_motif* out, int32_t* n_out, momenti_report* rep);
+
+/* Release every resource of the plan (NULL is ignored). */
+void momenti_destroy(momenti_plan* p);
+
+/* Message of the last error on this thread ("" when none). */
+const char* momenti_last_error(void);
+
+/* ---- inspection (used by tests and tools; all copies are synchronous) ---- */
+
+/* Quantisation width, repetitions in use, left/right half-functions. */
+int momenti_get_params(const momenti_plan* p, double* r, int32_t* L_used, int32_t* n_left,
+                       int32_t* n_right);
+
+/* Window statistics [D][n_s] (float64): mean and 1/sigma (0 for a flat window,
+ * sigma <= 1e-8 |mean|). Host buffers of `count` = D * n_s elements. */
+int momenti_get_stats(momenti_plan* p, double* mu, double* inv_sigma, size_t count);
+
+/* The index: hash words [D][n_left + n_right][n_s] (uint32), one word per
+ * half-function holding its K/2 one-byte symbols, position 0 most significant
+ * (symbol = (floor((a.x + b)/r) + 128) mod 256, Eq. drp). Host buffer. */
+int momenti_get_hashes(momenti_plan* p, uint32_t* dst, size_t count);
+
+/* Replace the index by words computed elsewhere (same layout), e.g. to
+ * traverse a reference index. Host buffer. Marks the plan hashed; the
+ * statistics must already exist (momenti_hash called once). */
+int momenti_set_hashes(momenti_plan* p, const uint32_t* src, size_t count);
+
+/* Record the traversal of the next momenti_search in host buffers (NULL
+ * disables): cand receives triples (step, a, b) of every emitted candidate,
+ * step = (K - i) L + (J - 1); top_size[step] the size of TOP after the step
+ * (-1 if not reached); top_pairs[step][k][2] its pairs. cand_count receives
+ * the number of candidates (may exceed cand_cap: the trace is then cut). */
+int momenti_set_trace(momenti_plan* p, int64_t* cand, int64_t cand_cap, int64_t* cand_count,
+                      int32_t* top_size, int64_t* top_pairs, int64_t steps_cap, int32_t k_cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOMENTI_H */

@@ -1,0 +1,98 @@
+// Internal declarations shared by the translation units of libmomenti.
+// Kernels live in k_hash.hip (index construction) and k_search.hip (index
+// traversal); the C ABI and the host-side orchestration in momenti.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+// A repetition-tagged candidate pair (a < b) emitted by the traversal.
+struct Cand {
+    uint32_t a, b, j, pad;
+};
+
+// A verified pair: dist_d (definition "d-dimensional distance"), dist_max
+// (Eq. distdmax), the chosen dimensions and the repetition that produced it.
+struct VRec {
+    double dist_d, dist_max;
+    uint32_t a, b, j, pad;
+    uint64_t dims[2];
+};
+static_assert(sizeof(VRec) == 48, "VRec layout");
+
+// State of the device-side pool of verified pairs and of TOP.
+struct PoolState {
+    int32_t n_pool;      // entries in the pool (sorted by (dist_d, a, b))
+    int32_t top_n;       // |TOP|
+    int32_t truncated;   // the pool dropped entries at some point (it holds the best P only)
+    int32_t cur;         // which of the two pool buffers is current
+    int32_t skipped;     // the pool step was skipped because candidates overflowed
+    int32_t pad[3];
+};
+
+// Per-repetition result of one traversal step.
+struct Snap {
+    int32_t top_n;
+    int32_t truncated;
+    double dist_max;     // dist_max of TOP[k-1] when top_n == k
+};
+
+// Device counters of one batch of traversal steps.
+struct Counters {
+    uint32_t n_cand;             // candidates emitted (may exceed the buffer)
+    uint32_t n_keep;             // verified candidates kept by the pool filter
+    unsigned long long n_coll;   // non-trivial one-dimensional collisions scanned
+};
+
+constexpr int kMaxD = 128;
+constexpr int kMaxW = 8192;
+constexpr double kFlatRel = 1e-8;      // sigma <= kFlatRel * |mu|: flat window
+
+// ---- index construction (k_hash.hip) ----
+hipError_t launch_stats(const void* x, int dtype, int64_t n, int64_t ns, int D, int w,
+                        double* mu, double* isig, hipStream_t s);
+hipError_t launch_rsample(const void* x, int dtype, int64_t n, int D, int w, const int64_t* win,
+                          int S, const double* vec, int nvec, double* dots, hipStream_t s);
+// proj: 0 f64, 1 f32, 2 bf16, 3 fp8. R/U in the layout and type of that path.
+hipError_t launch_proj(int proj, const void* x, int dtype, int64_t n, int64_t ns, int D, int w,
+                       const double* mu, const double* isig, const void* R, const void* U,
+                       int Cpad, int wpad, int NF, int K, double inv_r, uint32_t* H, hipStream_t s);
+
+// ---- index traversal (k_search.hip) ----
+struct SortBufs {
+    void* keys[2];
+    uint32_t* idx[2];
+    uint32_t* hist;
+    int64_t tiles;
+};
+struct StepGeom {
+    int64_t ns;
+    int D, NF, NL, m;
+    int j0, nseg;        // first repetition of the batch, segments = reps * D
+    int i, K;
+};
+constexpr int kSortTile = 4096;
+
+// Sort every segment of the batch by its length-i hash prefix; returns which
+// buffer (0/1) holds the result.
+hipError_t sort_prefixes(const StepGeom& g, const uint32_t* H, SortBufs& b, int* out_buf,
+                         hipStream_t s);
+hipError_t launch_enum(const StepGeom& g, const uint32_t* H, const SortBufs& b, int buf, int d,
+                       int w, Cand* cand, uint32_t cap, Counters* cnt, hipStream_t s);
+hipError_t launch_verify(const Cand* cand, uint32_t cap, const Counters* cnt, const void* x,
+                         int dtype, int64_t n, int64_t ns, int D, int w, int d, const double* mu,
+                         const double* isig, VRec* out, hipStream_t s);
+hipError_t launch_filter(const VRec* rec, uint32_t cap, const Counters* cnt,
+                         const PoolState* ps, const VRec* pools, int P, uint32_t* keep,
+                         Counters* cnt_out, hipStream_t s);
+hipError_t launch_pool(const VRec* rec, const uint32_t* keep, uint32_t cap, Counters* cnt,
+                       PoolState* ps, VRec* pools, int P, VRec* top, int k, int w, int j0, int B,
+                       Snap* snaps, VRec* snap_tops, hipStream_t s);
+hipError_t launch_pool_reset(PoolState* ps, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_allpairs(int64_t ns, int w, int64_t row_lo, int64_t row_hi, int64_t base,
+                           Cand* cand, Counters* cnt, hipStream_t s);
+
+}  // namespace mm

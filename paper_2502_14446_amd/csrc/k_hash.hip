@@ -1,0 +1,414 @@
+// Index construction on gfx950 (Algorithm 1, first loop; section 6.1).
+//
+//  * k_stats     rolling mean / population standard deviation of every window
+//                (Eq. zned needs mu and sigma of each subsequence), FP64.
+//  * k_rsample   projections of sampled z-normalised windows on random vectors,
+//                the input of the r heuristic (section 6.1), FP64, sequential
+//                per window so that every value is reproducible bit for bit.
+//  * k_proj_*    the random projections a . x_hat of Eq. drp for every window
+//                and every hash column, as one contraction per dimension:
+//                V[c][a] = sum_t R[t][c] * x_hat_a[t]. The right operand is a
+//                Hankel matrix (x_hat_a[t] comes from x[a + t]), staged once
+//                per tile in LDS and normalised on load; the contraction runs
+//                on MFMA; the epilogue quantises floor(v / r + U) and packs the
+//                four one-byte symbols of a half-function into one word.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace mm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Rolling statistics. Each thread owns kStatsChunk consecutive windows: the
+// first by a direct two-pass sum, the rest by the sliding update
+//   mu'  = mu + (x_in - x_out) / w
+//   M2'  = M2 + (x_in - x_out) * ((x_in - mu') + (x_out - mu)).
+// Windows whose sliding sigma is near zero relative to |mu|, or whose M2 fell
+// far below the chunk's peak (cancellation), are recomputed directly with the
+// plain two-pass definition, so the flat-window decision (sigma <= 1e-8 |mu|,
+// normal form all zeros) is taken on exactly the definition's value.
+// ---------------------------------------------------------------------------
+constexpr int kStatsChunk = 15;   // odd: conflict-free strided LDS reads
+constexpr int kStatsThreads = 256;
+
+template <typename T>
+__device__ inline void direct_stats(const T* xl, int w, double& mu, double& m2, double& sigma)
+{
+    double s = 0.0;
+    for (int t = 0; t < w; ++t) s = s + (double)xl[t];
+    mu = s / (double)w;
+    double q = 0.0;
+    for (int t = 0; t < w; ++t) {
+        double dl = (double)xl[t] - mu;
+        q = q + dl * dl;
+    }
+    m2 = q;
+    sigma = sqrt(q / (double)w);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kStatsThreads) void k_stats(const T* __restrict__ x, int64_t n,
+                                                         int64_t ns, int w,
+                                                         double* __restrict__ mu_out,
+                                                         double* __restrict__ isig_out)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);
+    const int f = blockIdx.y;
+    const int64_t a_blk = (int64_t)blockIdx.x * (kStatsThreads * kStatsChunk);
+    const int nx = kStatsThreads * kStatsChunk + w - 1;
+    const T* xf = x + (int64_t)f * n;
+    for (int q = threadIdx.x; q < nx; q += kStatsThreads) {
+        int64_t g = a_blk + q;
+        xs[q] = g < n ? xf[g] : T(0);
+    }
+    __syncthreads();
+    const int64_t a0 = a_blk + (int64_t)threadIdx.x * kStatsChunk;
+    if (a0 >= ns) return;
+    const T* xl = xs + threadIdx.x * kStatsChunk;
+    double mu, m2, sigma;
+    direct_stats(xl, w, mu, m2, sigma);
+    double peak = m2;
+    const double inv_w = 1.0 / (double)w;
+    for (int c = 0; c < kStatsChunk; ++c) {
+        const int64_t a = a0 + c;
+        if (a >= ns) break;
+        if (c > 0) {
+            double xo = (double)xl[c - 1], xi = (double)xl[c - 1 + w];
+            double dl = xi - xo;
+            double mn = mu + dl * inv_w;
+            m2 = m2 + dl * ((xi - mn) + (xo - mu));
+            mu = mn;
+            peak = fmax(peak, m2);
+            double var = m2 * inv_w;
+            sigma = var > 0.0 ? sqrt(var) : 0.0;
+            if (!(sigma > 1e-6 * fabs(mu)) || m2 < 1e-9 * peak) {
+                direct_stats(xl + c, w, mu, m2, sigma);
+                peak = m2;
+            }
+        }
+        const bool flat = sigma <= kFlatRel * fabs(mu);
+        mu_out[(int64_t)f * ns + a] = mu;
+        isig_out[(int64_t)f * ns + a] = flat ? 0.0 : 1.0 / sigma;
+    }
+}
+
+hipError_t launch_stats(const void* x, int dtype, int64_t n, int64_t ns, int D, int w, double* mu,
+                        double* isig, hipStream_t s)
+{
+    const int per = kStatsThreads * kStatsChunk;
+    dim3 grid((unsigned)((ns + per - 1) / per), (unsigned)D);
+    if (dtype == 0) {
+        size_t lds = (size_t)(per + w - 1) * sizeof(double);
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void*)k_stats<double>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_stats<double>, grid, dim3(kStatsThreads), lds, s, (const double*)x, n,
+                           ns, w, mu, isig);
+    } else {
+        size_t lds = (size_t)(per + w - 1) * sizeof(float);
+        hipLaunchKernelGGL(k_stats<float>, grid, dim3(kStatsThreads), lds, s, (const float*)x, n,
+                           ns, w, mu, isig);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// r heuristic input: for sampled windows (f, a) compute mu, sigma by the
+// two-pass definition, the normal form (x - mu) / sigma (zeros if flat), and
+// its dot product with each sample vector, all sequential in t, without
+// fused multiply-add (the library is built with -ffp-contract=off).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_rsample(const T* __restrict__ x, int64_t n, int D, int w,
+                          const int64_t* __restrict__ win, int S, const double* __restrict__ vec,
+                          int nvec, double* __restrict__ dots)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)D * S) return;
+    const int f = (int)(id / S);
+    const T* xa = x + (int64_t)f * n + win[id];
+    double mu, m2, sigma;
+    direct_stats(xa, w, mu, m2, sigma);
+    const bool flat = sigma <= kFlatRel * fabs(mu);
+    for (int v = 0; v < nvec; ++v) {
+        double dot = 0.0;
+        for (int t = 0; t < w; ++t) {
+            double z = flat ? 0.0 : ((double)xa[t] - mu) / sigma;
+            dot = dot + vec[(int64_t)v * w + t] * z;
+        }
+        dots[id * nvec + v] = dot;
+    }
+}
+
+hipError_t launch_rsample(const void* x, int dtype, int64_t n, int D, int w, const int64_t* win,
+                          int S, const double* vec, int nvec, double* dots, hipStream_t s)
+{
+    const int64_t total = (int64_t)D * S;
+    dim3 grid((unsigned)((total + 127) / 128));
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_rsample<double>, grid, dim3(128), 0, s, (const double*)x, n, D, w,
+                           win, S, vec, nvec, dots);
+    else
+        hipLaunchKernelGGL(k_rsample<float>, grid, dim3(128), 0, s, (const float*)x, n, D, w,
+                           win, S, vec, nvec, dots);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Quantise-and-pack epilogue: symbol = (floor(v / r + U) + 128) mod 256, four
+// positions of one half-function in one word, position 0 most significant.
+// (v / r + U equals (v + b) / r of Eq. drp with b = r U.)
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t sym_of(float u)
+{
+    float h = floorf(fminf(fmaxf(u, -1.0e9f), 1.0e9f));
+    return (uint32_t)(((int)h + 128) & 255);
+}
+__device__ inline uint32_t sym_of(double u)
+{
+    double h = floor(fmin(fmax(u, -1.0e9), 1.0e9));
+    return (uint32_t)(((int)h + 128) & 255);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 projection: v_mfma_f64_16x16x4f64. A (16 x 4): lane l holds
+// A[l % 16][l / 16]; B (4 x 16) = x_hat^T: lane l holds B[l / 16][l % 16];
+// D (16 x 16): lane l holds rows (l / 16) + 4 q, q = 0..3, of column l % 16
+// (measured on gfx950). Row i of A therefore carries hash column
+// 4 (i % 4) + i / 4, so that the four accumulators of a lane are the four
+// positions of hash function (c0 + 4 (l / 16)) / 4 of window l % 16 and
+// packing needs no data movement.
+// Wave tile: all Cpad = 16 MB16 columns x 16 NB windows; block: 4 waves.
+// ---------------------------------------------------------------------------
+template <typename T, int MB16, int NB>
+__global__ __launch_bounds__(256) void k_proj_f64(const T* __restrict__ x, int64_t n, int64_t ns,
+                                                  int w, int wpad, const double* __restrict__ mu,
+                                                  const double* __restrict__ isig,
+                                                  const double* __restrict__ R,
+                                                  const double* __restrict__ U, int Cpad, int NF,
+                                                  int K, double inv_r, uint32_t* __restrict__ H)
+{
+    constexpr int WB = 4 * 16 * NB;   // windows per block
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);
+    const int f = blockIdx.y;
+    const int64_t a_blk = (int64_t)blockIdx.x * WB;
+    const T* xf = x + (int64_t)f * n;
+    for (int q = threadIdx.x; q < WB + wpad; q += 256) {
+        int64_t g = a_blk + q;
+        xs[q] = g < n ? xf[g] : T(0);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, kq = lane >> 4;
+    const int acol = 4 * (col & 3) + (col >> 2);   // hash column carried by A row `col`
+    const int wbase = wave * 16 * NB;
+    double m_[NB], s_[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        int64_t a = a_blk + wbase + nb * 16 + col;
+        m_[nb] = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
+        s_[nb] = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
+    }
+    doublex4 acc[MB16][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB16; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const double* Rf = R + (int64_t)f * wpad * Cpad;
+    for (int t0 = 0; t0 < wpad; t0 += 4) {
+        const int t = t0 + kq;
+        double av[MB16], bv[NB];
+#pragma unroll
+        for (int mb = 0; mb < MB16; ++mb) av[mb] = Rf[(int64_t)t * Cpad + mb * 16 + acol];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            bv[nb] = ((double)xs[wbase + nb * 16 + col + t] - m_[nb]) * s_[nb];
+#pragma unroll
+        for (int mb = 0; mb < MB16; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+    }
+    const int half = K / 2;
+#pragma unroll
+    for (int mb = 0; mb < MB16; ++mb) {
+        const int c0 = mb * 16 + 4 * kq;
+        const int F = c0 / 4;
+        if (F >= NF) continue;
+        const double* Uf = U + (int64_t)f * Cpad + c0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int64_t a = a_blk + wbase + nb * 16 + col;
+            if (a >= ns) continue;
+            uint32_t word = 0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                if (p < half) word |= sym_of(fma(acc[mb][nb][p], inv_r, Uf[p])) << (24 - 8 * p);
+            H[((int64_t)f * NF + F) * ns + a] = word;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 projection: v_mfma_f32_32x32x2f32. A (32 x 2): lane l holds
+// A[l % 32][l / 32]; B (2 x 32): B[l / 32][l % 32]; D (32 x 32): lane l holds
+// D[8 (q / 4) + 4 (l / 32) + q % 4][l % 32], q = 0..15, so each group of four
+// accumulators is the four positions of one hash function.
+// The normal form is computed in FP64 and rounded once to FP32.
+// ---------------------------------------------------------------------------
+template <typename T, int MB, int NB>
+__global__ __launch_bounds__(256) void k_proj_f32(const T* __restrict__ x, int64_t n, int64_t ns,
+                                                  int w, int wpad, const double* __restrict__ mu,
+                                                  const double* __restrict__ isig,
+                                                  const float* __restrict__ R,
+                                                  const float* __restrict__ U, int Cpad, int NF,
+                                                  int K, float inv_r, uint32_t* __restrict__ H)
+{
+    constexpr int WB = 4 * 32 * NB;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);
+    const int f = blockIdx.y;
+    const int64_t a_blk = (int64_t)blockIdx.x * WB;
+    const T* xf = x + (int64_t)f * n;
+    for (int q = threadIdx.x; q < WB + wpad; q += 256) {
+        int64_t g = a_blk + q;
+        xs[q] = g < n ? xf[g] : T(0);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 31, kk = lane >> 5;
+    const int wbase = wave * 32 * NB;
+    double m_[NB], s_[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        int64_t a = a_blk + wbase + nb * 32 + col;
+        m_[nb] = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
+        s_[nb] = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
+    }
+    floatx16 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[mb][nb][q] = 0.0f;
+    const float* Rf = R + (int64_t)f * wpad * Cpad;
+#pragma unroll 2
+    for (int t0 = 0; t0 < wpad; t0 += 2) {
+        const int t = t0 + kk;
+        float av[MB], bv[NB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) av[mb] = Rf[(int64_t)t * Cpad + mb * 32 + col];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            bv[nb] = (float)(((double)xs[wbase + nb * 32 + col + t] - m_[nb]) * s_[nb]);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+    }
+    const int half = K / 2;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int c0 = mb * 32 + 8 * g + 4 * kk;
+            const int F = c0 / 4;
+            if (F >= NF) continue;
+            const float* Uf = U + (int64_t)f * Cpad + c0;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int64_t a = a_blk + wbase + nb * 32 + col;
+                if (a >= ns) continue;
+                uint32_t word = 0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    if (p < half) word |= sym_of(fmaf(acc[mb][nb][4 * g + p], inv_r, Uf[p])) << (24 - 8 * p);
+                H[((int64_t)f * NF + F) * ns + a] = word;
+            }
+        }
+}
+
+template <typename T, int MB16>
+static hipError_t go_f64(const T* x, int64_t n, int64_t ns, int D, int w, int wpad, const double* mu,
+                         const double* isig, const double* R, const double* U, int Cpad, int NF,
+                         int K, double inv_r, uint32_t* H, hipStream_t s)
+{
+    constexpr int NB = 2, WB = 4 * 16 * NB;
+    dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
+    size_t lds = (size_t)(WB + wpad) * sizeof(T);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_proj_f64<T, MB16, NB>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_proj_f64<T, MB16, NB>), grid, dim3(256), lds, s, x, n, ns, w, wpad, mu,
+                       isig, R, U, Cpad, NF, K, inv_r, H);
+    return hipGetLastError();
+}
+
+template <typename T, int MB>
+static hipError_t go_f32(const T* x, int64_t n, int64_t ns, int D, int w, int wpad, const double* mu,
+                         const double* isig, const float* R, const float* U, int Cpad, int NF,
+                         int K, float inv_r, uint32_t* H, hipStream_t s)
+{
+    constexpr int NB = 2, WB = 4 * 32 * NB;
+    dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
+    size_t lds = (size_t)(WB + wpad) * sizeof(T);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_proj_f32<T, MB, NB>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_proj_f32<T, MB, NB>), grid, dim3(256), lds, s, x, n, ns, w, wpad, mu,
+                       isig, R, U, Cpad, NF, K, inv_r, H);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t dispatch(int proj, const T* x, int64_t n, int64_t ns, int D, int w,
+                           const double* mu, const double* isig, const void* R, const void* U,
+                           int Cpad, int wpad, int NF, int K, double inv_r, uint32_t* H,
+                           hipStream_t s)
+{
+    const int MB = Cpad / 32;   // Cpad is a multiple of 32, at most 128
+    if (proj == 0) {
+        const double* Rd = (const double*)R;
+        const double* Ud = (const double*)U;
+        switch (MB) {
+        case 1: return go_f64<T, 2>(x, n, ns, D, w, wpad, mu, isig, Rd, Ud, Cpad, NF, K, inv_r, H, s);
+        case 2: return go_f64<T, 4>(x, n, ns, D, w, wpad, mu, isig, Rd, Ud, Cpad, NF, K, inv_r, H, s);
+        case 3: return go_f64<T, 6>(x, n, ns, D, w, wpad, mu, isig, Rd, Ud, Cpad, NF, K, inv_r, H, s);
+        case 4: return go_f64<T, 8>(x, n, ns, D, w, wpad, mu, isig, Rd, Ud, Cpad, NF, K, inv_r, H, s);
+        }
+    } else if (proj == 1) {
+        const float* Rf = (const float*)R;
+        const float* Uf = (const float*)U;
+        const float ir = (float)inv_r;
+        switch (MB) {
+        case 1: return go_f32<T, 1>(x, n, ns, D, w, wpad, mu, isig, Rf, Uf, Cpad, NF, K, ir, H, s);
+        case 2: return go_f32<T, 2>(x, n, ns, D, w, wpad, mu, isig, Rf, Uf, Cpad, NF, K, ir, H, s);
+        case 3: return go_f32<T, 3>(x, n, ns, D, w, wpad, mu, isig, Rf, Uf, Cpad, NF, K, ir, H, s);
+        case 4: return go_f32<T, 4>(x, n, ns, D, w, wpad, mu, isig, Rf, Uf, Cpad, NF, K, ir, H, s);
+        }
+    }
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_proj(int proj, const void* x, int dtype, int64_t n, int64_t ns, int D, int w,
+                       const double* mu, const double* isig, const void* R, const void* U,
+                       int Cpad, int wpad, int NF, int K, double inv_r, uint32_t* H, hipStream_t s)
+{
+    if (dtype == 0)
+        return dispatch<double>(proj, (const double*)x, n, ns, D, w, mu, isig, R, U, Cpad, wpad,
+                                NF, K, inv_r, H, s);
+    return dispatch<float>(proj, (const float*)x, n, ns, D, w, mu, isig, R, U, Cpad, wpad, NF, K,
+                           inv_r, H, s);
+}
+
+}  // namespace mm

@@ -1,0 +1,846 @@
+// C ABI and host orchestration of the MOMENTI motif search on gfx950.
+//
+// Host responsibilities: argument checks, the memory cap on the number of
+// repetitions, the seeded random projections (Philox4x32-10 + Box-Muller),
+// the r estimate from device-computed sample projections, the round /
+// repetition loop of Algorithm 1 with the stopping rule of Algorithm 2
+// (Lemma 6.1 for the tensored index), and the exact fallback. Every step of
+// the data path itself runs in the kernels of k_hash.hip and k_search.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/momenti.h"
+#include "internal.h"
+
+using namespace mm;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(MOMENTI_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+// ------------------------------------------------------------------ RNG
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
+// multiply-xor round with Weyl key increments.
+static void philox4x32_10(const uint32_t in[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = in[0], x1 = in[1], x2 = in[2], x3 = in[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        if (rnd) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t prod0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t prod1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(prod1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(prod0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)prod1;
+        x3 = (uint32_t)prod0;
+        x0 = y0;
+        x2 = y2;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+// Stream identifiers (the last counter word).
+enum : uint32_t { kStreamProj = 0, kStreamOffset = 1, kStreamRVec = 2, kStreamRWin = 3 };
+
+static inline double unit53(uint32_t hi, uint32_t lo)
+{
+    return (double)((((uint64_t)hi << 32) | lo) >> 11) * 0x1.0p-53;
+}
+
+static void block_at(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t stream, uint32_t o[4])
+{
+    const uint32_t ctr[4] = {c0, c1, c2, stream};
+    const uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    philox4x32_10(ctr, key, o);
+}
+
+static double normal_at(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t stream)
+{
+    uint32_t o[4];
+    block_at(seed, c0, c1, c2, stream, o);
+    const double u1 = 1.0 - unit53(o[0], o[1]);
+    const double u2 = unit53(o[2], o[3]);
+    const double rad = std::sqrt(-2.0 * std::log(u1));
+    const double ang = 6.283185307179586 * u2;
+    return rad * std::cos(ang);
+}
+
+static double uniform_at(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t stream)
+{
+    uint32_t o[4];
+    block_at(seed, c0, c1, c2, stream, o);
+    return unit53(o[0], o[1]);
+}
+
+// ------------------------------------------------------------------ plan
+struct momenti_plan {
+    int64_t n = 0, ns = 0;
+    int D = 0, w = 0, dtype = 1;
+    uint64_t mem_limit = 0;
+    momenti_opts o{};
+    int K = 8, L = 200, m = 15, NL = 14, NR = 15, NF = 29, Cpad = 128, wpad = 0;
+    double r = 0.0;
+    bool hashed = false, have_stats = false;
+    hipStream_t st = nullptr;
+    int dev = 0;
+
+    void* series = nullptr;
+    bool own_series = false;
+    double* mu = nullptr;
+    double* isig = nullptr;
+    void* R = nullptr;
+    void* U = nullptr;
+    uint32_t* H = nullptr;
+    double t_hash_ms = 0.0;
+
+    // traversal buffers
+    SortBufs sb{};
+    int sb_nseg = 0;
+    Cand* cand = nullptr;
+    VRec* vrec = nullptr;
+    uint32_t* keep = nullptr;   // 2 * cap (keep list + per-repetition order)
+    uint32_t cap = 0;
+    VRec* pools = nullptr;
+    int P = 0;
+    VRec* top = nullptr;
+    int top_k = 0;
+    unsigned char* status = nullptr;   // Counters | PoolState | Snap[kMaxBatch]
+    VRec* snap_tops = nullptr;
+    int snap_B = 0, snap_k = 0;
+    unsigned char* host_status = nullptr;
+
+    uint64_t bytes = 0, peak = 0;
+
+    // trace
+    int64_t* tr_cand = nullptr;
+    int64_t tr_cap = 0;
+    int64_t* tr_count = nullptr;
+    int32_t* tr_top_size = nullptr;
+    int64_t* tr_top_pairs = nullptr;
+    int64_t tr_steps_cap = 0;
+    int32_t tr_k = 0;
+};
+
+static int dalloc(momenti_plan* p, void** ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (p->bytes + bytes > p->mem_limit)
+        return fail(MOMENTI_E_NOMEM, "device budget exceeded: %llu + %zu > %llu bytes",
+                    (unsigned long long)p->bytes, bytes, (unsigned long long)p->mem_limit);
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(MOMENTI_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    p->bytes += bytes;
+    p->peak = std::max(p->peak, p->bytes);
+    return MOMENTI_OK;
+}
+
+template <typename T>
+static int dalloc_t(momenti_plan* p, T** ptr, size_t bytes)
+{
+    void* v = nullptr;
+    int rc = dalloc(p, &v, bytes);
+    *ptr = (T*)v;
+    return rc;
+}
+
+static void dfree(momenti_plan* p, void* ptr, size_t bytes)
+{
+    if (!ptr) return;
+    (void)hipFree(ptr);
+    if (bytes == 0) bytes = 16;
+    p->bytes -= std::min<uint64_t>(p->bytes, bytes);
+}
+
+static int64_t ceil_sqrt_i(int64_t v)
+{
+    int64_t m = (int64_t)std::sqrt((double)v);
+    while (m * m < v) ++m;
+    while (m > 1 && (m - 1) * (m - 1) >= v) --m;
+    return m;
+}
+
+static void tensor_shape(int L, int* m, int* nl, int* nr)
+{
+    *m = (int)ceil_sqrt_i(L);
+    *nl = (L + *m - 1) / *m;
+    *nr = std::min(L, *m);
+}
+
+// Memory cap: the largest L' <= L_max whose index fits next to the series,
+// the statistics and the fixed traversal reserve (index size O(K L D n)).
+static int cap_repetitions(int64_t n, int D, int w, int L_max, int elem, uint64_t limit)
+{
+    const int64_t ns = n - w + 1;
+    const int64_t fixed = n * D * elem + 16 * ns * D + 32 * ns * D + ((int64_t)64 << 20);
+    for (int L = L_max; L >= 1; --L) {
+        int m, nl, nr;
+        tensor_shape(L, &m, &nl, &nr);
+        const int64_t idx = 4 * ns * (int64_t)D * (nl + nr);
+        if ((uint64_t)(fixed + idx) <= limit) return L;
+    }
+    return 0;
+}
+
+static size_t series_bytes(const momenti_plan* p) { return (size_t)p->n * p->D * (p->dtype == MOMENTI_F64 ? 8 : 4); }
+static size_t proj_elem(int proj) { return proj == MOMENTI_PROJ_F64 ? 8 : 4; }
+
+static void release_search(momenti_plan* p)
+{
+    for (int q = 0; q < 2; ++q) {
+        dfree(p, p->sb.keys[q], (size_t)p->sb_nseg * p->ns * 8);
+        dfree(p, p->sb.idx[q], (size_t)p->sb_nseg * p->ns * 4);
+        p->sb.keys[q] = nullptr;
+        p->sb.idx[q] = nullptr;
+    }
+    dfree(p, p->sb.hist, (size_t)p->sb_nseg * 256 * p->sb.tiles * 4);
+    p->sb.hist = nullptr;
+    p->sb_nseg = 0;
+    dfree(p, p->cand, (size_t)p->cap * sizeof(Cand));
+    dfree(p, p->vrec, (size_t)p->cap * sizeof(VRec));
+    dfree(p, p->keep, (size_t)p->cap * 8);
+    p->cand = nullptr; p->vrec = nullptr; p->keep = nullptr; p->cap = 0;
+    dfree(p, p->pools, (size_t)2 * p->P * sizeof(VRec));
+    p->pools = nullptr; p->P = 0;
+    dfree(p, p->top, (size_t)p->top_k * sizeof(VRec));
+    p->top = nullptr; p->top_k = 0;
+    dfree(p, p->status, 4096);
+    p->status = nullptr;
+    dfree(p, p->snap_tops, (size_t)p->snap_B * p->snap_k * sizeof(VRec));
+    p->snap_tops = nullptr; p->snap_B = 0; p->snap_k = 0;
+    if (p->host_status) (void)hipHostFree(p->host_status);
+    p->host_status = nullptr;
+}
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+void momenti_default_opts(momenti_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->seed = 0x5EED;
+    o->K = 8;
+    o->L = 200;
+    o->r = 0.0;
+    o->proj = MOMENTI_PROJ_F32;
+    o->stop_rule = MOMENTI_STOP_TENSOR;
+}
+
+const char* momenti_last_error(void) { return g_err.c_str(); }
+
+void momenti_destroy(momenti_plan* p)
+{
+    if (!p) return;
+    release_search(p);
+    if (p->own_series) dfree(p, p->series, series_bytes(p));
+    dfree(p, p->mu, (size_t)p->D * p->ns * 8);
+    dfree(p, p->isig, (size_t)p->D * p->ns * 8);
+    dfree(p, p->R, (size_t)p->D * p->wpad * p->Cpad * proj_elem(p->o.proj));
+    dfree(p, p->U, (size_t)p->D * p->Cpad * proj_elem(p->o.proj));
+    dfree(p, p->H, (size_t)p->D * p->NF * p->ns * 4);
+    delete p;
+}
+
+int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t dtype,
+                    uint64_t mem_limit, const momenti_opts* opts)
+{
+    g_err.clear();
+    if (!out) return fail(MOMENTI_E_ARG, "out is NULL");
+    *out = nullptr;
+    momenti_opts o;
+    if (opts) o = *opts; else momenti_default_opts(&o);
+    if (D < 1 || D > kMaxD) return fail(MOMENTI_E_ARG, "D=%d outside [1, %d]", D, kMaxD);
+    if (w < 4 || w > kMaxW) return fail(MOMENTI_E_ARG, "w=%d outside [4, %d]", w, kMaxW);
+    if (n < (int64_t)w + 1) return fail(MOMENTI_E_ARG, "n=%lld shorter than w+1", (long long)n);
+    if (n - w + 1 > ((int64_t)1 << 31)) return fail(MOMENTI_E_ARG, "too many windows");
+    if (dtype != MOMENTI_F64 && dtype != MOMENTI_F32) return fail(MOMENTI_E_ARG, "bad dtype %d", dtype);
+    if (o.K < 2 || o.K > 8 || (o.K & 1)) return fail(MOMENTI_E_ARG, "K=%d must be even in [2, 8]", o.K);
+    if (o.L < 1 || o.L > 1024) return fail(MOMENTI_E_ARG, "L=%d outside [1, 1024]", o.L);
+    if (o.proj != MOMENTI_PROJ_F64 && o.proj != MOMENTI_PROJ_F32)
+        return fail(MOMENTI_E_ARG, "projection precision %d not available", o.proj);
+    if (o.stop_rule != MOMENTI_STOP_TENSOR && o.stop_rule != MOMENTI_STOP_LEMMA52)
+        return fail(MOMENTI_E_ARG, "bad stop rule %d", o.stop_rule);
+    if (o.pool_size < 0 || o.batch_reps < 0) return fail(MOMENTI_E_ARG, "negative pool/batch size");
+
+    const int elem = dtype == MOMENTI_F64 ? 8 : 4;
+    const int L = cap_repetitions(n, D, w, o.L, elem, mem_limit);
+    if (L < 1) return fail(MOMENTI_E_NOMEM, "mem_limit %llu below the one-repetition index",
+                           (unsigned long long)mem_limit);
+
+    momenti_plan* p = new (std::nothrow) momenti_plan();
+    if (!p) return fail(MOMENTI_E_NOMEM, "host allocation failed");
+    p->n = n; p->ns = n - w + 1; p->D = D; p->w = w; p->dtype = dtype; p->mem_limit = mem_limit;
+    p->o = o; p->K = o.K; p->L = L;
+    tensor_shape(L, &p->m, &p->NL, &p->NR);
+    p->NF = p->NL + p->NR;
+    const int C = 4 * p->NF;
+    p->Cpad = ((C + 31) / 32) * 32;
+    p->wpad = ((w + 63) / 64) * 64;
+    p->st = (hipStream_t)o.stream;
+    if (hipGetDevice(&p->dev) != hipSuccess) {
+        delete p;
+        return fail(MOMENTI_E_DEVICE, "no HIP device");
+    }
+
+    // random projections of Eq. drp: R[f][t][c] ~ N(0,1), U[f][c] ~ U[0,1)
+    const size_t pe = proj_elem(o.proj);
+    std::vector<double> R((size_t)D * p->wpad * p->Cpad, 0.0), U((size_t)D * p->Cpad, 0.0);
+    for (int f = 0; f < D; ++f) {
+        for (int t = 0; t < w; ++t)
+            for (int c = 0; c < C; ++c)
+                R[((size_t)f * p->wpad + t) * p->Cpad + c] =
+                    normal_at(o.seed, (uint32_t)t, (uint32_t)c, (uint32_t)f, kStreamProj);
+        for (int c = 0; c < C; ++c)
+            U[(size_t)f * p->Cpad + c] = uniform_at(o.seed, (uint32_t)c, (uint32_t)f, 0u, kStreamOffset);
+    }
+    int rc;
+    if ((rc = dalloc(p, &p->R, R.size() * pe)) || (rc = dalloc(p, &p->U, U.size() * pe)) ||
+        (rc = dalloc_t(p, &p->mu, (size_t)D * p->ns * 8)) ||
+        (rc = dalloc_t(p, &p->isig, (size_t)D * p->ns * 8)) ||
+        (rc = dalloc_t(p, &p->H, (size_t)D * p->NF * p->ns * 4))) {
+        momenti_destroy(p);
+        return rc;
+    }
+    hipError_t e;
+    if (o.proj == MOMENTI_PROJ_F64) {
+        e = hipMemcpy(p->R, R.data(), R.size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->U, U.data(), U.size() * 8, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> Rf(R.begin(), R.end()), Uf(U.begin(), U.end());
+        e = hipMemcpy(p->R, Rf.data(), Rf.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->U, Uf.data(), Uf.size() * 4, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        momenti_destroy(p);
+        return fail(MOMENTI_E_DEVICE, "upload of projections failed: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return MOMENTI_OK;
+}
+
+int momenti_hash(momenti_plan* p, const void* series)
+{
+    g_err.clear();
+    if (!p) return fail(MOMENTI_E_ARG, "plan is NULL");
+    if (!series) return fail(MOMENTI_E_ARG, "series is NULL");
+    const size_t sbytes = series_bytes(p);
+    if (p->o.series_on_device) {
+        if (p->own_series) {
+            dfree(p, p->series, sbytes);
+            p->own_series = false;
+        }
+        p->series = const_cast<void*>(series);
+    } else {
+        if (!p->own_series) {
+            p->series = nullptr;
+            int rc = dalloc(p, &p->series, sbytes);
+            if (rc) return rc;
+            p->own_series = true;
+        }
+        HIP_OK(hipMemcpyAsync(p->series, series, sbytes, hipMemcpyHostToDevice, p->st));
+    }
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, p->st));
+    HIP_OK(launch_stats(p->series, p->dtype, p->n, p->ns, p->D, p->w, p->mu, p->isig, p->st));
+
+    // r (section 6.1): projections of sampled z-normalised windows on 8
+    // Gaussian vectors, split into 256 equal buckets.
+    double r = p->o.r;
+    if (!(r > 0.0)) {
+        const int nvec = 8;
+        const int S = (int)std::min<int64_t>(p->ns, 4096);
+        std::vector<int64_t> win((size_t)p->D * S);
+        for (int f = 0; f < p->D; ++f)
+            for (int q = 0; q < S; ++q) {
+                const double u = uniform_at(p->o.seed, (uint32_t)q, (uint32_t)f, 0u, kStreamRWin);
+                int64_t a = (int64_t)std::floor(u * (double)p->ns);
+                win[(size_t)f * S + q] = std::min<int64_t>(a, p->ns - 1);
+            }
+        std::vector<double> vec((size_t)nvec * p->w);
+        for (int v = 0; v < nvec; ++v)
+            for (int t = 0; t < p->w; ++t)
+                vec[(size_t)v * p->w + t] = normal_at(p->o.seed, (uint32_t)t, (uint32_t)v, 0u, kStreamRVec);
+        int64_t* d_win = nullptr;
+        double *d_vec = nullptr, *d_dots = nullptr;
+        const size_t nd = (size_t)p->D * S * nvec;
+        int rc;
+        if ((rc = dalloc_t(p, &d_win, win.size() * 8)) || (rc = dalloc_t(p, &d_vec, vec.size() * 8)) ||
+            (rc = dalloc_t(p, &d_dots, nd * 8))) {
+            dfree(p, d_win, win.size() * 8);
+            dfree(p, d_vec, vec.size() * 8);
+            return rc;
+        }
+        std::vector<double> dots(nd);
+        hipError_t e = hipMemcpyAsync(d_win, win.data(), win.size() * 8, hipMemcpyHostToDevice, p->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_vec, vec.data(), vec.size() * 8, hipMemcpyHostToDevice, p->st);
+        if (e == hipSuccess) e = launch_rsample(p->series, p->dtype, p->n, p->D, p->w, d_win, S, d_vec, nvec, d_dots, p->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dots.data(), d_dots, nd * 8, hipMemcpyDeviceToHost, p->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+        dfree(p, d_win, win.size() * 8);
+        dfree(p, d_vec, vec.size() * 8);
+        dfree(p, d_dots, nd * 8);
+        if (e != hipSuccess) return fail(MOMENTI_E_DEVICE, "r estimate failed: %s", hipGetErrorString(e));
+        double lo = INFINITY, hi = -INFINITY;
+        for (double v : dots) {
+            lo = std::min(lo, v);
+            hi = std::max(hi, v);
+        }
+        r = (hi - lo) / 256.0;
+        if (!(r > 0.0) || !std::isfinite(r)) r = 1.0;
+    }
+    p->r = r;
+    HIP_OK(launch_proj(p->o.proj, p->series, p->dtype, p->n, p->ns, p->D, p->w, p->mu, p->isig,
+                       p->R, p->U, p->Cpad, p->wpad, p->NF, p->K, 1.0 / r, p->H, p->st));
+    HIP_OK(hipEventRecord(e1, p->st));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->t_hash_ms = ms;
+    p->hashed = true;
+    p->have_stats = true;
+    return MOMENTI_OK;
+}
+
+int momenti_get_params(const momenti_plan* p, double* r, int32_t* L_used, int32_t* n_left, int32_t* n_right)
+{
+    if (!p) return fail(MOMENTI_E_ARG, "plan is NULL");
+    if (r) *r = p->r;
+    if (L_used) *L_used = p->L;
+    if (n_left) *n_left = p->NL;
+    if (n_right) *n_right = p->NR;
+    return MOMENTI_OK;
+}
+
+int momenti_get_stats(momenti_plan* p, double* mu, double* inv_sigma, size_t count)
+{
+    if (!p) return fail(MOMENTI_E_ARG, "plan is NULL");
+    if (!p->have_stats) return fail(MOMENTI_E_STATE, "no statistics yet");
+    if (count != (size_t)p->D * p->ns) return fail(MOMENTI_E_ARG, "count must be D * n_s");
+    HIP_OK(hipStreamSynchronize(p->st));
+    if (mu) HIP_OK(hipMemcpy(mu, p->mu, count * 8, hipMemcpyDeviceToHost));
+    if (inv_sigma) HIP_OK(hipMemcpy(inv_sigma, p->isig, count * 8, hipMemcpyDeviceToHost));
+    return MOMENTI_OK;
+}
+
+int momenti_get_hashes(momenti_plan* p, uint32_t* dst, size_t count)
+{
+    if (!p || !dst) return fail(MOMENTI_E_ARG, "NULL argument");
+    if (!p->hashed) return fail(MOMENTI_E_STATE, "no index yet");
+    if (count != (size_t)p->D * p->NF * p->ns) return fail(MOMENTI_E_ARG, "count must be D * NF * n_s");
+    HIP_OK(hipStreamSynchronize(p->st));
+    HIP_OK(hipMemcpy(dst, p->H, count * 4, hipMemcpyDeviceToHost));
+    return MOMENTI_OK;
+}
+
+int momenti_set_hashes(momenti_plan* p, const uint32_t* src, size_t count)
+{
+    if (!p || !src) return fail(MOMENTI_E_ARG, "NULL argument");
+    if (!p->have_stats) return fail(MOMENTI_E_STATE, "momenti_hash must run once first");
+    if (count != (size_t)p->D * p->NF * p->ns) return fail(MOMENTI_E_ARG, "count must be D * NF * n_s");
+    HIP_OK(hipStreamSynchronize(p->st));
+    HIP_OK(hipMemcpy(p->H, src, count * 4, hipMemcpyHostToDevice));
+    p->hashed = true;
+    return MOMENTI_OK;
+}
+
+int momenti_set_trace(momenti_plan* p, int64_t* cand, int64_t cand_cap, int64_t* cand_count,
+                      int32_t* top_size, int64_t* top_pairs, int64_t steps_cap, int32_t k_cap)
+{
+    if (!p) return fail(MOMENTI_E_ARG, "plan is NULL");
+    p->tr_cand = cand;
+    p->tr_cap = cand_cap;
+    p->tr_count = cand_count;
+    p->tr_top_size = top_size;
+    p->tr_top_pairs = top_pairs;
+    p->tr_steps_cap = steps_cap;
+    p->tr_k = k_cap;
+    return MOMENTI_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ stopping rule
+// Eq. eucl-collision-probability, P(R) = erf(t / sqrt 2) - 2 / (sqrt(2 pi) t) (1 - e^{-t^2/2}),
+// t = r / R (1 - 2 Phi(-t) = erf(t / sqrt 2)), with P(0) = 1.
+static double collision_probability(double R, double r)
+{
+    if (!(R > 0.0)) return 1.0;
+    const double t = r / R;
+    return std::erf(t / std::sqrt(2.0)) + 2.0 / (std::sqrt(2.0 * M_PI) * t) * std::expm1(-0.5 * t * t);
+}
+
+// log of (1 - p^c)^e, with x^0 = 1 (also for x = 0).
+static double log_term(double logp, int c, int64_t e)
+{
+    if (e == 0) return 0.0;
+    const double pc = std::exp((double)c * logp);   // p^c (p^0 = 1)
+    if (pc >= 1.0) return -INFINITY;
+    return (double)e * std::log1p(-pc);
+}
+
+// Algorithm 2: stop when the bound on never having seen a pair at the k-th
+// motif's dist_max is at most delta. TENSOR: Lemma 6.1; LEMMA52: Lemma 5.2.
+static bool stop_holds(double dist_max, double r, int d, int i, int J, int K, int L, int m, int rule,
+                       double delta)
+{
+    const double P = collision_probability(dist_max, r);
+    if (!(P > 0.0)) return false;
+    const double logp = (double)d * std::log(P);   // p = P^d
+    double lf;
+    if (rule == MOMENTI_STOP_LEMMA52) {
+        lf = log_term(logp, i, J);
+        if (i < K) lf += log_term(logp, i + 1, L - J);
+    } else {
+        lf = log_term(logp, (i + 1) / 2, J / m) + log_term(logp, i / 2, J % m);
+        if (i < K) {
+            const int J2 = L - J;
+            lf += log_term(logp, (i + 2) / 2, J2 / m) + log_term(logp, (i + 1) / 2, J2 % m);
+        }
+    }
+    return lf <= std::log(delta);
+}
+
+// ------------------------------------------------------------------ search
+static Counters* st_counters(momenti_plan* p) { return (Counters*)p->status; }
+static PoolState* st_pool(momenti_plan* p) { return (PoolState*)(p->status + 64); }
+static Snap* st_snaps(momenti_plan* p) { return (Snap*)(p->status + 128); }
+static constexpr size_t kStatusBytes = 128 + 64 * sizeof(Snap);
+
+static size_t sort_bytes(int64_t nseg, int64_t ns, int64_t tiles)
+{
+    return (size_t)nseg * ns * (8 + 8 + 4 + 4) + (size_t)nseg * 256 * tiles * 4;
+}
+static size_t cand_bytes(uint32_t cap) { return (size_t)cap * (sizeof(Cand) + sizeof(VRec) + 8); }
+
+static int alloc_sort(momenti_plan* p, int nseg)
+{
+    const int64_t tiles = (p->ns + kSortTile - 1) / kSortTile;
+    int rc;
+    p->sb.tiles = tiles;
+    for (int q = 0; q < 2; ++q) {
+        if ((rc = dalloc(p, &p->sb.keys[q], (size_t)nseg * p->ns * 8))) return rc;
+        if ((rc = dalloc_t(p, &p->sb.idx[q], (size_t)nseg * p->ns * 4))) return rc;
+    }
+    if ((rc = dalloc_t(p, &p->sb.hist, (size_t)nseg * 256 * tiles * 4))) return rc;
+    p->sb_nseg = nseg;
+    return MOMENTI_OK;
+}
+
+static int alloc_cand(momenti_plan* p, uint32_t cap)
+{
+    dfree(p, p->cand, (size_t)p->cap * sizeof(Cand));
+    dfree(p, p->vrec, (size_t)p->cap * sizeof(VRec));
+    dfree(p, p->keep, (size_t)p->cap * 8);
+    p->cand = nullptr; p->vrec = nullptr; p->keep = nullptr; p->cap = 0;
+    int rc;
+    if ((rc = dalloc_t(p, &p->cand, (size_t)cap * sizeof(Cand)))) return rc;
+    if ((rc = dalloc_t(p, &p->vrec, (size_t)cap * sizeof(VRec)))) return rc;
+    if ((rc = dalloc_t(p, &p->keep, (size_t)cap * 8))) return rc;
+    p->cap = cap;
+    return MOMENTI_OK;
+}
+
+static int alloc_pool(momenti_plan* p, int P, int k, int B)
+{
+    dfree(p, p->pools, (size_t)2 * p->P * sizeof(VRec));
+    dfree(p, p->top, (size_t)p->top_k * sizeof(VRec));
+    dfree(p, p->snap_tops, (size_t)p->snap_B * p->snap_k * sizeof(VRec));
+    p->pools = nullptr; p->top = nullptr; p->snap_tops = nullptr;
+    int rc;
+    if ((rc = dalloc_t(p, &p->pools, (size_t)2 * P * sizeof(VRec)))) return rc;
+    p->P = P;
+    if ((rc = dalloc_t(p, &p->top, (size_t)k * sizeof(VRec)))) return rc;
+    p->top_k = k;
+    if ((rc = dalloc_t(p, &p->snap_tops, (size_t)B * k * sizeof(VRec)))) return rc;
+    p->snap_B = B;
+    p->snap_k = k;
+    return MOMENTI_OK;
+}
+
+struct BatchOut {
+    Counters cnt;
+    PoolState ps;
+    Snap snaps[64];
+};
+
+// Run the pool stages (filter + pool) on the candidates already in p->cand.
+static int pool_stage(momenti_plan* p, int k, int j0, int B)
+{
+    Counters* cnt = st_counters(p);
+    HIP_OK(launch_filter(p->vrec, p->cap, cnt, st_pool(p), p->pools, p->P, p->keep, cnt, p->st));
+    HIP_OK(launch_pool(p->vrec, p->keep, p->cap, cnt, st_pool(p), p->pools, p->P, p->top, k, p->w,
+                       j0, B, st_snaps(p), p->snap_tops, p->st));
+    return MOMENTI_OK;
+}
+
+static int read_status(momenti_plan* p, BatchOut* out, int B)
+{
+    HIP_OK(hipMemcpyAsync(p->host_status, p->status, 128 + (size_t)B * sizeof(Snap),
+                          hipMemcpyDeviceToHost, p->st));
+    HIP_OK(hipStreamSynchronize(p->st));
+    std::memcpy(&out->cnt, p->host_status, sizeof(Counters));
+    std::memcpy(&out->ps, p->host_status + 64, sizeof(PoolState));
+    std::memcpy(out->snaps, p->host_status + 128, (size_t)B * sizeof(Snap));
+    return MOMENTI_OK;
+}
+
+static void to_motifs(const std::vector<VRec>& v, int count, momenti_motif* out)
+{
+    for (int s = 0; s < count; ++s) {
+        out[s].a = v[s].a;
+        out[s].b = v[s].b;
+        out[s].dist_d = v[s].dist_d;
+        out[s].dist_max = v[s].dist_max;
+        out[s].dims[0] = v[s].dims[0];
+        out[s].dims[1] = v[s].dims[1];
+    }
+}
+
+static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out,
+                          momenti_report* rep);
+
+extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
+                              int32_t* n_out, momenti_report* rep)
+{
+    g_err.clear();
+    if (!p || !out || !n_out) return fail(MOMENTI_E_ARG, "NULL argument");
+    if (!p->hashed) return fail(MOMENTI_E_STATE, "momenti_hash has not been called");
+    if (d < 1 || d > p->D) return fail(MOMENTI_E_ARG, "d=%d outside [1, D=%d]", d, p->D);
+    if (k < 1 || k > 4096) return fail(MOMENTI_E_ARG, "k=%d outside [1, 4096]", k);
+    if (!(delta > 0.0 && delta < 1.0)) return fail(MOMENTI_E_ARG, "delta=%g outside (0, 1)", delta);
+    *n_out = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    momenti_report R{};
+    R.K = p->K;
+    R.L_used = p->L;
+    R.r = p->r;
+    R.t_hash_ms = p->t_hash_ms;
+
+    release_search(p);
+    int P = p->o.pool_size ? p->o.pool_size : std::max(4096, 128 * k);
+    P = std::max(P, k);
+    int rc;
+    // buffers: status, pool, candidates, then as many repetitions per launch as fit
+    if ((rc = dalloc_t(p, &p->status, 4096))) return rc;
+    if (hipHostMalloc((void**)&p->host_status, 4096, 0) != hipSuccess)
+        return fail(MOMENTI_E_NOMEM, "pinned host allocation failed");
+    int Bmax = p->o.batch_reps ? p->o.batch_reps : 16;
+    Bmax = std::max(1, std::min({Bmax, p->L, 64}));
+    if ((rc = alloc_pool(p, P, k, Bmax))) return rc;
+    const uint64_t left0 = p->mem_limit - p->bytes;
+    const int64_t tiles = (p->ns + kSortTile - 1) / kSortTile;
+    uint32_t cap = 1u << 20;
+    while (cap > (1u << 14) && cand_bytes(cap) + sort_bytes(p->D, p->ns, tiles) > left0) cap >>= 1;
+    if ((rc = alloc_cand(p, cap))) return rc;
+    int B = Bmax;
+    while (B > 1 && sort_bytes((int64_t)B * p->D, p->ns, tiles) > p->mem_limit - p->bytes) B >>= 1;
+    if ((rc = alloc_sort(p, B * p->D))) return rc;
+    R.batch_reps = B;
+
+    const bool tracing = p->tr_cand || p->tr_top_size;
+    if (p->tr_count) *p->tr_count = 0;
+    if (p->tr_top_size)
+        for (int64_t s = 0; s < p->tr_steps_cap; ++s) p->tr_top_size[s] = -1;
+    std::vector<Cand> hcand;
+    std::vector<VRec> hsnap;
+
+restart:
+    HIP_OK(launch_pool_reset(st_pool(p), p->st));
+    for (int i = p->K; i >= 1; --i) {
+        for (int j0 = 0; j0 < p->L;) {
+            const int Bc = std::min(B, p->L - j0);
+            StepGeom g;
+            g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
+            g.j0 = j0; g.nseg = Bc * p->D; g.i = i; g.K = p->K;
+            HIP_OK(launch_zero(p->status, 64, p->st));
+            int buf = 0;
+            HIP_OK(sort_prefixes(g, p->H, p->sb, &buf, p->st));
+            HIP_OK(launch_enum(g, p->H, p->sb, buf, d, p->w, p->cand, p->cap, st_counters(p), p->st));
+            HIP_OK(launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
+                                 p->D, p->w, d, p->mu, p->isig, p->vrec, p->st));
+            if ((rc = pool_stage(p, k, j0, Bc))) return rc;
+            BatchOut bo;
+            if ((rc = read_status(p, &bo, Bc))) return rc;
+            if (bo.cnt.n_cand > p->cap) {
+                // more candidates than room: fewer repetitions per launch, then a larger buffer
+                if (Bc > 1) {
+                    B = std::max(1, Bc / 2);
+                    continue;
+                }
+                uint32_t need = p->cap;
+                while (need < bo.cnt.n_cand && need < (1u << 30)) need <<= 1;
+                if (cand_bytes(need) > p->mem_limit - p->bytes + cand_bytes(p->cap))
+                    return fail(MOMENTI_E_NOMEM, "%u candidates in one step exceed mem_limit", bo.cnt.n_cand);
+                if ((rc = alloc_cand(p, need))) return rc;
+                continue;
+            }
+            R.n_collisions += (int64_t)bo.cnt.n_coll;
+            R.n_cand += bo.cnt.n_cand;
+            R.n_verified += bo.cnt.n_cand;
+            if (tracing) {
+                if (p->tr_cand && bo.cnt.n_cand) {
+                    hcand.resize(bo.cnt.n_cand);
+                    HIP_OK(hipMemcpy(hcand.data(), p->cand, bo.cnt.n_cand * sizeof(Cand), hipMemcpyDeviceToHost));
+                    for (const Cand& c : hcand) {
+                        const int64_t s = (int64_t)(p->K - i) * p->L + c.j;
+                        if (*p->tr_count < p->tr_cap) {
+                            p->tr_cand[3 * *p->tr_count + 0] = s;
+                            p->tr_cand[3 * *p->tr_count + 1] = c.a;
+                            p->tr_cand[3 * *p->tr_count + 2] = c.b;
+                        }
+                        ++*p->tr_count;
+                    }
+                }
+                if (p->tr_top_size) {
+                    hsnap.resize((size_t)Bc * k);
+                    HIP_OK(hipMemcpy(hsnap.data(), p->snap_tops, hsnap.size() * sizeof(VRec), hipMemcpyDeviceToHost));
+                    for (int jb = 0; jb < Bc; ++jb) {
+                        const int64_t s = (int64_t)(p->K - i) * p->L + j0 + jb;
+                        if (s >= p->tr_steps_cap) continue;
+                        p->tr_top_size[s] = bo.snaps[jb].top_n;
+                        for (int q = 0; q < bo.snaps[jb].top_n && q < p->tr_k; ++q) {
+                            p->tr_top_pairs[(s * p->tr_k + q) * 2 + 0] = hsnap[(size_t)jb * k + q].a;
+                            p->tr_top_pairs[(s * p->tr_k + q) * 2 + 1] = hsnap[(size_t)jb * k + q].b;
+                        }
+                    }
+                }
+            }
+            for (int jb = 0; jb < Bc; ++jb) {
+                const Snap& sn = bo.snaps[jb];
+                const int J = j0 + jb + 1;
+                ++R.n_steps;
+                if (sn.top_n < k && sn.truncated) {
+                    // the pool dropped pairs that TOP may still need: redo with a larger pool
+                    ++R.pool_overflow;
+                    P *= 2;
+                    if ((rc = alloc_pool(p, P, k, Bmax))) return rc;
+                    R.n_steps = 0;
+                    if (tracing && p->tr_count) *p->tr_count = 0;
+                    goto restart;
+                }
+                if (sn.top_n == k &&
+                    stop_holds(sn.dist_max, p->r, d, i, J, p->K, p->L, p->m, p->o.stop_rule, delta)) {
+                    std::vector<VRec> tv(k);
+                    HIP_OK(hipMemcpy(tv.data(), p->snap_tops + (size_t)jb * k, (size_t)k * sizeof(VRec),
+                                     hipMemcpyDeviceToHost));
+                    to_motifs(tv, k, out);
+                    *n_out = k;
+                    R.i_stop = i;
+                    R.j_stop = J;
+                    R.peak_bytes = p->peak;
+                    R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                    if (rep) *rep = R;
+                    return MOMENTI_OK;
+                }
+            }
+            j0 += Bc;
+        }
+    }
+    rc = exact_fallback(p, d, k, out, n_out, &R);
+    R.fallback = 1;
+    R.peak_bytes = p->peak;
+    R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = R;
+    return rc == MOMENTI_OK ? MOMENTI_OK_FALLBACK : rc;
+}
+
+// Algorithm 1, last line: no step stopped, so answer with the exact top-k
+// over every non-trivial pair (same verifier and pool, all pairs streamed).
+static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out,
+                          momenti_report* rep)
+{
+    if (p->ns > 65536)
+        return fail(MOMENTI_E_UNSUPPORTED, "exact fallback limited to 65536 windows (n_s=%lld)",
+                    (long long)p->ns);
+    const int64_t h = p->w / 2;
+    const int64_t M = p->ns - h - 1;
+    auto off = [M](int64_t a) { int64_t aa = std::min(a, std::max<int64_t>(M, 0)); return aa * M - aa * (aa - 1) / 2; };
+    int rc;
+    if (M > (int64_t)p->cap) {
+        uint32_t need = p->cap;
+        while ((int64_t)need < M) need <<= 1;
+        if ((rc = alloc_cand(p, need))) return rc;
+    }
+    for (;;) {
+        HIP_OK(launch_pool_reset(st_pool(p), p->st));
+        int64_t row = 0;
+        BatchOut bo{};
+        while (row < std::max<int64_t>(M, 0)) {
+            int64_t hi = row + 1;
+            while (hi < M && off(hi + 1) - off(row) <= (int64_t)p->cap) ++hi;
+            HIP_OK(launch_zero(p->status, 64, p->st));
+            HIP_OK(launch_allpairs(p->ns, p->w, row, hi, off(row), p->cand, st_counters(p), p->st));
+            HIP_OK(launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
+                                 p->D, p->w, d, p->mu, p->isig, p->vrec, p->st));
+            if ((rc = pool_stage(p, k, 0, 1))) return rc;
+            if ((rc = read_status(p, &bo, 1))) return rc;
+            rep->n_verified += bo.cnt.n_cand;
+            row = hi;
+        }
+        const Snap& sn = bo.snaps[0];
+        if (M <= 0 || !(sn.top_n < k && sn.truncated)) {
+            const int got = M <= 0 ? 0 : sn.top_n;
+            std::vector<VRec> tv(std::max(got, 1));
+            if (got)
+                HIP_OK(hipMemcpy(tv.data(), p->snap_tops, (size_t)got * sizeof(VRec), hipMemcpyDeviceToHost));
+            to_motifs(tv, got, out);
+            *n_out = got;
+            return MOMENTI_OK;
+        }
+        ++rep->pool_overflow;
+        if ((rc = alloc_pool(p, p->P * 2, k, p->snap_B))) return rc;
+    }
+}
+
+extern "C" int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_t w,
+                            int32_t d, int32_t k, double delta, uint64_t mem_limit,
+                            const momenti_opts* opts, momenti_motif* out, int32_t* n_out,
+                            momenti_report* rep)
+{
+    momenti_plan* p = nullptr;
+    int rc = momenti_prepare(&p, n, D, w, dtype, mem_limit, opts);
+    if (rc) return rc;
+    rc = momenti_hash(p, series);
+    if (rc == MOMENTI_OK) rc = momenti_search(p, d, k, delta, out, n_out, rep);
+    momenti_destroy(p);
+    return rc;
+}

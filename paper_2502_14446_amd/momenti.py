@@ -1,0 +1,251 @@
+"""Python binding of libmomenti (include/momenti.h): argument marshalling only.
+
+Every step of the search runs in the HIP library; this module converts
+arguments (numpy host arrays or torch device tensors), calls the C ABI and
+turns results into Python objects. It never computes anything itself and has
+no fallback: without a built ``libmomenti.so`` every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmomenti.so")
+
+OK, OK_FALLBACK = 0, 1
+E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+PROJ = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
+STOP = {"tensor": 0, "lemma52": 1}
+
+EXPORTS = [
+    "momenti_default_opts", "momenti_prepare", "momenti_hash", "momenti_search", "momenti_topk",
+    "momenti_destroy", "momenti_last_error", "momenti_get_params", "momenti_get_stats",
+    "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace",
+]
+
+
+class Opts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("K", C.c_int32), ("L", C.c_int32), ("r", C.c_double),
+                ("proj", C.c_int32), ("stop_rule", C.c_int32), ("series_on_device", C.c_int32),
+                ("pool_size", C.c_int32), ("batch_reps", C.c_int32), ("reserved", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class Motif(C.Structure):
+    _fields_ = [("a", C.c_int64), ("b", C.c_int64), ("dist_d", C.c_double),
+                ("dist_max", C.c_double), ("dims", C.c_uint64 * 2)]
+
+
+class Report(C.Structure):
+    _fields_ = [("t_hash_ms", C.c_double), ("t_search_ms", C.c_double),
+                ("i_stop", C.c_int32), ("j_stop", C.c_int32), ("L_used", C.c_int32),
+                ("K", C.c_int32), ("r", C.c_double), ("n_steps", C.c_int64),
+                ("n_collisions", C.c_int64), ("n_cand", C.c_int64), ("n_verified", C.c_int64),
+                ("peak_bytes", C.c_uint64), ("fallback", C.c_int32), ("pool_overflow", C.c_int32),
+                ("batch_reps", C.c_int32), ("reserved", C.c_int32)]
+
+
+class MomentiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"momenti error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmomenti.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, P = C.c_void_p, C.POINTER
+        i32, i64, u64, d = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        sig = {
+            "momenti_default_opts": (None, [P(Opts)]),
+            "momenti_prepare": (i32, [P(vp), i64, i32, i32, i32, u64, P(Opts)]),
+            "momenti_hash": (i32, [vp, vp]),
+            "momenti_search": (i32, [vp, i32, i32, d, P(Motif), P(i32), P(Report)]),
+            "momenti_topk": (i32, [vp, i32, i64, i32, i32, i32, i32, d, u64, P(Opts), P(Motif),
+                                   P(i32), P(Report)]),
+            "momenti_destroy": (None, [vp]),
+            "momenti_last_error": (C.c_char_p, []),
+            "momenti_get_params": (i32, [vp, P(d), P(i32), P(i32), P(i32)]),
+            "momenti_get_stats": (i32, [vp, vp, vp, C.c_size_t]),
+            "momenti_get_hashes": (i32, [vp, vp, C.c_size_t]),
+            "momenti_set_hashes": (i32, [vp, vp, C.c_size_t]),
+            "momenti_set_trace": (i32, [vp, vp, i64, vp, vp, vp, i64, i32]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise MomentiError(rc, lib().momenti_last_error().decode())
+    return rc
+
+
+def make_opts(seed: int = 0x5EED, K: int = 8, L: int = 200, r: float = 0.0, proj: str = "f32",
+              stop: str = "tensor", series_on_device: bool = False, pool_size: int = 0,
+              batch_reps: int = 0, stream: Optional[int] = None) -> Opts:
+    o = Opts()
+    lib().momenti_default_opts(C.byref(o))
+    o.seed, o.K, o.L, o.r = seed, K, L, r
+    o.proj, o.stop_rule = PROJ[proj], STOP[stop]
+    o.series_on_device = 1 if series_on_device else 0
+    o.pool_size, o.batch_reps = pool_size, batch_reps
+    o.stream = stream
+    return o
+
+
+def _motifs(arr, count: int) -> List[Dict]:
+    out = []
+    for m in arr[:count]:
+        dims = tuple(f for f in range(128) if (int(m.dims[f >> 6]) >> (f & 63)) & 1)
+        out.append(dict(a=int(m.a), b=int(m.b), dist_d=float(m.dist_d),
+                        dist_max=float(m.dist_max), dims=dims))
+    return out
+
+
+def _report(r: Report) -> Dict:
+    return {name: getattr(r, name) for name, _ in Report._fields_ if name != "reserved"}
+
+
+def _torch_stream_handle() -> Optional[int]:
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A prepared search (momenti_prepare); owns the device index."""
+
+    def __init__(self, n: int, D: int, w: int, dtype: str = "f32", mem_limit: int = 8 << 30,
+                 device_series: bool = False, **opts):
+        if device_series and "stream" not in opts:
+            opts["stream"] = _torch_stream_handle()
+        self.opts = make_opts(series_on_device=device_series, **opts)
+        self.n, self.D, self.w = n, D, w
+        self.dtype = dtype
+        self.device_series = device_series
+        self._series_ref = None
+        h = C.c_void_p()
+        _check(lib().momenti_prepare(C.byref(h), n, D, w, F64 if dtype == "f64" else F32,
+                                     mem_limit, C.byref(self.opts)))
+        self.h = h
+        self._trace_bufs = None
+
+    # -- lifecycle
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            lib().momenti_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls
+    def hash(self, series) -> None:
+        """series: numpy [D][n] (host plan) or a contiguous torch CUDA tensor (device plan)."""
+        if self.device_series:
+            assert series.is_cuda and series.is_contiguous()
+            want = "torch.float64" if self.dtype == "f64" else "torch.float32"
+            assert str(series.dtype) == want, f"series dtype {series.dtype} != {want}"
+            assert tuple(series.shape) == (self.D, self.n)
+            self._series_ref = series
+            ptr = C.c_void_p(series.data_ptr())
+        else:
+            arr = np.ascontiguousarray(series, dtype=np.float64 if self.dtype == "f64" else np.float32)
+            assert arr.shape == (self.D, self.n)
+            self._series_ref = arr
+            ptr = arr.ctypes.data_as(C.c_void_p)
+        _check(lib().momenti_hash(self.h, ptr))
+
+    def search(self, d: int, k: int, delta: float) -> Tuple[List[Dict], Dict, int]:
+        arr = (Motif * max(k, 1))()
+        got = C.c_int32()
+        rep = Report()
+        rc = _check(lib().momenti_search(self.h, d, k, delta, arr, C.byref(got), C.byref(rep)))
+        return _motifs(arr, got.value), _report(rep), rc
+
+    def params(self) -> Dict:
+        r, L, nl, nr = C.c_double(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().momenti_get_params(self.h, C.byref(r), C.byref(L), C.byref(nl), C.byref(nr)))
+        return dict(r=r.value, L=L.value, n_left=nl.value, n_right=nr.value,
+                    NF=nl.value + nr.value)
+
+    def stats(self) -> Tuple[np.ndarray, np.ndarray]:
+        ns = self.n - self.w + 1
+        mu = np.zeros((self.D, ns)); isg = np.zeros((self.D, ns))
+        _check(lib().momenti_get_stats(self.h, mu.ctypes.data_as(C.c_void_p),
+                                       isg.ctypes.data_as(C.c_void_p), mu.size))
+        return mu, isg
+
+    def hashes(self) -> np.ndarray:
+        ns = self.n - self.w + 1
+        NF = self.params()["NF"]
+        out = np.zeros((self.D, NF, ns), dtype=np.uint32)
+        _check(lib().momenti_get_hashes(self.h, out.ctypes.data_as(C.c_void_p), out.size))
+        return out
+
+    def set_hashes(self, words: np.ndarray) -> None:
+        words = np.ascontiguousarray(words, dtype=np.uint32)
+        _check(lib().momenti_set_hashes(self.h, words.ctypes.data_as(C.c_void_p), words.size))
+
+    def set_trace(self, cand_cap: int, k: int) -> None:
+        K, L = self.opts.K, self.params()["L"]
+        steps = K * L
+        cand = np.zeros((cand_cap, 3), dtype=np.int64)
+        cnt = np.zeros(1, dtype=np.int64)
+        tsz = np.zeros(steps, dtype=np.int32)
+        tpairs = np.zeros((steps, k, 2), dtype=np.int64)
+        self._trace_bufs = (cand, cnt, tsz, tpairs)
+        _check(lib().momenti_set_trace(self.h, cand.ctypes.data_as(C.c_void_p), cand_cap,
+                                       cnt.ctypes.data_as(C.c_void_p), tsz.ctypes.data_as(C.c_void_p),
+                                       tpairs.ctypes.data_as(C.c_void_p), steps, k))
+
+    def trace(self) -> Dict:
+        cand, cnt, tsz, tpairs = self._trace_bufs
+        c = int(cnt[0])
+        if c > cand.shape[0]:
+            raise RuntimeError(f"trace truncated ({c} > {cand.shape[0]})")
+        return dict(cand=cand[:c].copy(), top_size=tsz.copy(), top_pairs=tpairs.copy())
+
+
+def topk(series, w: int, d: int, k: int, delta: float, mem_limit: int = 8 << 30,
+         dtype: str = "f32", **opts) -> Tuple[List[Dict], Dict, int]:
+    """One call: prepare + hash + search + destroy (momenti_topk)."""
+    if hasattr(series, "is_cuda") and series.is_cuda:
+        with Plan(series.shape[1], series.shape[0], w, dtype, mem_limit, device_series=True,
+                  **opts) as p:
+            p.hash(series)
+            return p.search(d, k, delta)
+    arr = np.ascontiguousarray(series, dtype=np.float64 if dtype == "f64" else np.float32)
+    o = make_opts(**opts)
+    out = (Motif * max(k, 1))()
+    got = C.c_int32()
+    rep = Report()
+    rc = _check(lib().momenti_topk(arr.ctypes.data_as(C.c_void_p), F64 if dtype == "f64" else F32,
+                                   arr.shape[1], arr.shape[0], w, d, k, delta, mem_limit,
+                                   C.byref(o), out, C.byref(got), C.byref(rep)))
+    return _motifs(out, got.value), _report(rep), rc

@@ -1,0 +1,62 @@
+"""The C ABI library loads and exports every entry point its header declares
+(no GPU needed: only dlopen and symbol lookup), and the binding fails loudly
+without it."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "momenti.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(momenti_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("momenti_prepare", "momenti_hash", "momenti_search", "momenti_topk",
+                 "momenti_destroy", "momenti_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2502_14446_amd import momenti as mm
+    if not os.path.exists(mm.LIB_PATH):
+        from paper_2502_14446_amd import build
+        build.build()
+    lib = ctypes.CDLL(mm.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(mm.EXPORTS) == _declared()
+
+
+def test_argument_errors_are_reported_without_touching_a_gpu():
+    from paper_2502_14446_amd import momenti as mm
+    lib = mm.lib()
+    h = ctypes.c_void_p()
+    o = mm.make_opts()
+    # n shorter than w + 1
+    assert lib.momenti_prepare(ctypes.byref(h), 10, 2, 50, 1, 1 << 30, ctypes.byref(o)) == mm.E_ARG
+    assert b"shorter" in lib.momenti_last_error()
+    # odd K
+    o.K = 5
+    assert lib.momenti_prepare(ctypes.byref(h), 1000, 2, 50, 1, 1 << 30, ctypes.byref(o)) == mm.E_ARG
+    o.K = 8
+    # mem_limit below the one-repetition index
+    assert lib.momenti_prepare(ctypes.byref(h), 1000, 2, 50, 1, 1 << 20, ctypes.byref(o)) == mm.E_NOMEM
+    # search on a NULL plan
+    out = (mm.Motif * 1)()
+    n = ctypes.c_int32()
+    assert lib.momenti_search(None, 1, 1, 0.1, out, ctypes.byref(n), None) == mm.E_ARG
+
+
+def test_binding_refuses_to_run_without_the_library(monkeypatch):
+    from paper_2502_14446_amd import momenti as mm
+    monkeypatch.setattr(mm, "LIB_PATH", "/nonexistent/libmomenti.so")
+    monkeypatch.setattr(mm, "_lib", None)
+    with pytest.raises(RuntimeError):
+        mm.lib()

@@ -1,0 +1,297 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances:
+* window statistics: |mu_gpu - mu| <= 1e-12 (|mu| + sigma), 1/sigma within 1e-12 relative;
+  the flat-window decision identical;
+* r: identical (both sides compute it sequentially in FP64 from the same draws);
+* hash symbols: identical wherever the oracle's exact pre-floor value is farther
+  from an integer than the rounding bound of the GPU's arithmetic (guard band g);
+  inside the band either neighbouring symbol is a correct evaluation;
+* traversal with the oracle's index injected: emitted candidates, TOP after every
+  step and the stopping step identical;
+* distances: 1e-9 relative (verification is FP64 on both sides);
+* motif indices: identical.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2502_14446_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2502_14446_amd import momenti as mm  # noqa: E402
+
+
+def _unpack(words, K):
+    """[D][NF][ns] words -> [D][ns][4 NF] symbols (positions >= K/2 left 0)."""
+    D, NF, ns = words.shape
+    out = np.zeros((D, ns, 4 * NF), dtype=np.uint8)
+    for p in range(K // 2):
+        out[:, :, p::4] = ((words >> np.uint32(24 - 8 * p)) & np.uint32(255)).transpose(0, 2, 1)
+    return out
+
+
+def _oracle_symbols(orc, x, w, R, U, r):
+    D = x.shape[0]
+    by, pre, sab = [], [], []
+    for f in range(D):
+        b, p_, s_ = orc.hash_dim(x[f], w, R[f], U[f], r)
+        by.append(b); pre.append(p_); sab.append(s_)
+    return np.array(by), np.array(pre), np.array(sab)
+
+
+def _band(proj, w, pre, sab, r):
+    if proj == "f64":
+        return 1e-10 * (sab / r + np.abs(pre) + 1.0)
+    u = 2.0 ** -24
+    return 2.0 * u * ((w + 4) * sab / r + 3.0 * (np.abs(pre) + 1.0))
+
+
+def _check_symbols(gpu_sym, ref_sym, pre, band, K):
+    C = ref_sym.shape[-1]
+    used = np.zeros(C, dtype=bool)
+    for p in range(K // 2):
+        used[p::4] = True
+    g = gpu_sym[..., used].astype(np.int64)
+    o = ref_sym[..., used].astype(np.int64)
+    u = pre[..., used]
+    bd = band[..., used]
+    frac = u - np.floor(u)
+    near = np.minimum(frac, 1.0 - frac) <= bd
+    lo = (np.floor(u - bd).astype(np.int64) + 128) % 256
+    hi = (np.floor(u + bd).astype(np.int64) + 128) % 256
+    bad_out = (~near) & (g != o)
+    bad_in = near & (g != lo) & (g != hi)
+    return int(bad_out.sum()), int(bad_in.sum()), int(near.sum()), int((g != o).sum())
+
+
+def _plan(s, p, proj, seed, **kw):
+    dtype = "f64" if s.dtype == "f64" else "f32"
+    x = torch.from_numpy(s.as_dtype()).to("cuda")
+    plan = mm.Plan(s.n, s.D, p["w"], dtype, p.get("mem_limit", 1 << 30), device_series=True,
+                   seed=seed, proj=proj, **kw)
+    plan.hash(x)
+    return plan, x
+
+
+# --------------------------------------------------------------------------- statistics, r
+def test_stats_and_r_match_oracle(orc):
+    s, p = synth.workload("tiny")
+    x = s.x.copy()
+    x[1, 300:420] = 3.25          # flat stretch: windows fully inside are flat
+    x[2, 900:1000] = 0.0
+    s.x[:] = x
+    plan, _ = _plan(s, p, "f64", 7)
+    mu, isg = plan.stats()
+    mu_o, sg_o, flat_o = orc.stats(x, p["w"])
+    flat_g = isg == 0.0
+    assert np.array_equal(flat_g, flat_o)
+    ok = ~flat_o
+    assert np.all(np.abs(mu - mu_o) <= 1e-12 * (np.abs(mu_o) + sg_o))
+    assert np.allclose(isg[ok], 1.0 / sg_o[ok], rtol=1e-12, atol=0)
+    assert plan.params()["r"] == orc.estimate_r(x, p["w"], 7)
+    plan.close()
+
+
+@pytest.mark.parametrize("w,n", [(4, 300), (63, 5000), (300, 12001), (1000, 9000)])
+def test_stats_match_oracle_across_window_lengths(orc, w, n):
+    s = synth.make_series(11 + w, 3, n, w, 0, 0, dtype="f32")
+    p = dict(w=w, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, "f32", 3)
+    mu, isg = plan.stats()
+    mu_o, sg_o, flat_o = orc.stats(s.x, w)
+    assert np.array_equal(isg == 0.0, flat_o)
+    assert np.all(np.abs(mu - mu_o) <= 1e-12 * (np.abs(mu_o) + sg_o))
+    assert np.allclose(isg, 1.0 / sg_o, rtol=1e-12, atol=0)
+    assert plan.params()["r"] == orc.estimate_r(s.x, w, 3)
+    plan.close()
+
+
+# --------------------------------------------------------------------------- hashes
+@pytest.mark.parametrize("proj", ["f64", "f32"])
+def test_hash_index_matches_oracle(orc, proj):
+    s, p = synth.workload("tiny")
+    if proj == "f32":
+        s = synth.make_series(synth.DATA_SEED["tiny"], 4, 2000, 50, 1, 2, dtype="f32", min_gap=500)
+    seed = synth.LSH_SEED["tiny"]
+    plan, _ = _plan(s, p, proj, seed)
+    prm = plan.params()
+    assert prm["L"] == orc.L_used(s.n, s.D, p["w"], 200, 8 if s.dtype == "f64" else 4, p["mem_limit"])
+    R, U = orc.draw_projections(seed, s.D, p["w"], 4 * prm["NF"])
+    r = orc.estimate_r(s.x, p["w"], seed)
+    assert prm["r"] == r
+    ref, pre, sab = _oracle_symbols(orc, s.x, p["w"], R, U, r)
+    gsym = _unpack(plan.hashes(), 8)
+    bad_out, bad_in, near, diff = _check_symbols(gsym, ref, pre, _band(proj, p["w"], pre, sab, r), 8)
+    print(f"{proj}: symbols={ref.size} band={near} differing={diff}")
+    assert bad_out == 0 and bad_in == 0
+    if proj == "f64":
+        assert diff == 0
+    plan.close()
+
+
+def test_hash_index_ragged_and_small_L(orc):
+    # n_s not a multiple of any tile, L = 7 (m = 3: 3 left + 3 right), K = 6
+    s = synth.make_series(5, 3, 1337, 37, 1, 2, dtype="f64")
+    p = dict(w=37, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, "f64", 99, K=6, L=7)
+    prm = plan.params()
+    assert (prm["L"], prm["n_left"], prm["n_right"]) == (7, 3, 3)
+    R, U = orc.draw_projections(99, s.D, 37, 4 * prm["NF"])
+    r = orc.estimate_r(s.x, 37, 99)
+    ref, pre, sab = _oracle_symbols(orc, s.x, 37, R, U, r)
+    ref_words = orc.pack(ref, prm["NF"], 6)
+    gw = plan.hashes()
+    assert np.array_equal(gw, ref_words)
+    plan.close()
+
+
+# --------------------------------------------------------------------------- traversal
+def _oracle_sets(cand):
+    sets = {}
+    for s_, a, b in cand:
+        sets.setdefault(int(s_), set()).add((int(a), int(b)))
+    return sets
+
+
+def _check_traversal(orc, s, p, seed, K, L, k, d, delta, rule):
+    plan, _ = _plan(s, p, "f64", seed, K=K, L=L, stop=rule, batch_reps=4)
+    prm = plan.params()
+    Lu = prm["L"]
+    R, U = orc.draw_projections(seed, s.D, p["w"], 4 * prm["NF"])
+    r = prm["r"]
+    assert r == orc.estimate_r(s.x, p["w"], seed)
+    ref_sym, _, _ = _oracle_symbols(orc, s.x, p["w"], R, U, r)
+    words = orc.pack(ref_sym, prm["NF"], K)
+    plan.set_hashes(words)                       # traverse the oracle's own index
+    plan.set_trace(4_000_000, k)
+    got, rep, rc = plan.search(d, k, delta)
+    tr = plan.trace()
+    ref = orc.lsh_search(s.x, p["w"], d, k, delta, words, K, Lu, r,
+                         rule=orc.STOP_TENSOR if rule == "tensor" else orc.STOP_LEMMA52, trace=True)
+    # stopping step
+    assert (rep["i_stop"], rep["j_stop"]) == (ref["i_stop"], ref["J_stop"])
+    last = (K - ref["i_stop"]) * Lu + ref["J_stop"] - 1 if ref["i_stop"] else K * Lu - 1
+    osets = _oracle_sets(ref["cand"])
+    gsets = _oracle_sets(tr["cand"])
+    for step in range(last + 1):
+        want = osets.get(step, set())
+        if step >= Lu:                           # round i < K: skip pairs seen at prefix i+1
+            want = want - osets.get(step - Lu, set())
+        assert gsets.get(step, set()) == want, f"step {step}"
+        assert tr["top_size"][step] == ref["top_size"][step], f"step {step}"
+        n = ref["top_size"][step]
+        assert np.array_equal(tr["top_pairs"][step, :n], ref["top_pairs"][step, :n]), f"step {step}"
+    assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ref["motifs"]]
+    for g, o in zip(got, ref["motifs"]):
+        assert g["dist_d"] == pytest.approx(o["dist_d"], rel=1e-9)
+        assert g["dist_max"] == pytest.approx(o["dist_max"], rel=1e-9)
+        assert g["dims"] == o["dims"]
+    plan.close()
+    return rep, ref
+
+
+def test_traversal_matches_oracle_tiny(orc):
+    s, p = synth.workload("tiny")
+    rep, ref = _check_traversal(orc, s, p, synth.LSH_SEED["tiny"], 8, 200, p["k"], p["d"], p["delta"], "tensor")
+    assert rep["n_steps"] >= 1
+
+
+def test_traversal_matches_oracle_multi_motif(orc):
+    s = synth.make_series(21, 5, 2500, 40, 3, 2, dtype="f64")
+    p = dict(w=40, mem_limit=1 << 30)
+    _check_traversal(orc, s, p, 5, 8, 30, 3, 2, 0.05, "lemma52")
+
+
+def test_traversal_matches_oracle_deep_rounds(orc):
+    # K = 4, few repetitions and a tiny delta: the search descends several rounds
+    s = synth.make_series(31, 3, 1500, 30, 2, 2, dtype="f64")
+    p = dict(w=30, mem_limit=1 << 30)
+    _check_traversal(orc, s, p, 8, 4, 9, 2, 2, 1e-3, "lemma52")
+
+
+# --------------------------------------------------------------------------- end to end
+def test_end_to_end_tiny_matches_oracle_and_exact(orc):
+    s, p = synth.workload("tiny")
+    seed = synth.LSH_SEED["tiny"]
+    plan, _ = _plan(s, p, "f64", seed)
+    got, rep, rc = plan.search(p["d"], p["k"], p["delta"])
+    ref = orc.lsh_pipeline(s.x, p["w"], p["d"], p["k"], p["delta"], seed, mem_limit=p["mem_limit"])
+    ex = orc.topk_exact(s.x, p["w"], p["d"], p["k"])
+    assert rc == mm.OK
+    assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ref["motifs"]] == \
+        [(m["a"], m["b"]) for m in ex]
+    assert (rep["i_stop"], rep["j_stop"]) == (ref["i_stop"], ref["J_stop"])
+    assert got[0]["dist_d"] == pytest.approx(ex[0]["dist_d"], rel=1e-9)
+    plan.close()
+
+
+def test_fallback_returns_exact_top_k(orc):
+    # LEMMA52 with a vanishing delta never stops: the exact answer is returned
+    s = synth.make_series(41, 3, 700, 24, 2, 2, dtype="f64")
+    p = dict(w=24, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, "f64", 12, K=4, L=4, stop="lemma52")
+    got, rep, rc = plan.search(2, 3, 1e-300)
+    assert rc == mm.OK_FALLBACK and rep["fallback"] == 1
+    ex = orc.topk_exact(s.x, 24, 2, 3)
+    assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ex]
+    for g, o in zip(got, ex):
+        assert g["dist_d"] == pytest.approx(o["dist_d"], rel=1e-9)
+    plan.close()
+
+
+def test_fewer_pairs_than_k(orc):
+    s = synth.make_series(42, 2, 90, 20, 0, 0, dtype="f64")
+    p = dict(w=20, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, "f64", 1, K=4, L=4)
+    got, rep, rc = plan.search(1, 10, 0.1)
+    ex = orc.topk_exact(s.x, 20, 1, 10)
+    assert len(ex) < 10
+    assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ex]
+    plan.close()
+
+
+def test_constant_series_collision_storm(orc):
+    # every window is flat: all pairs collide everywhere, every distance is 0
+    x = np.full((2, 160), 2.5)
+    s = synth.Series(x, 16, [], "f64")
+    p = dict(w=16, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, "f64", 3, K=4, L=4)
+    got, rep, rc = plan.search(2, 3, 0.1)
+    ex = orc.topk_exact(x, 16, 2, 3)
+    assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ex]
+    assert all(m["dist_d"] == 0.0 for m in got)
+    plan.close()
+
+
+def test_argument_errors_on_device():
+    s, p = synth.workload("tiny")
+    plan, _ = _plan(s, p, "f64", 1)
+    with pytest.raises(mm.MomentiError) as e:
+        plan.search(5, 1, 0.1)                 # d > D
+    assert e.value.code == mm.E_ARG
+    with pytest.raises(mm.MomentiError):
+        plan.search(2, 1, 1.5)                 # delta outside (0, 1)
+    with pytest.raises(mm.MomentiError):
+        plan.search(2, 0, 0.1)                 # k < 1
+    plan.close()
+
+
+def test_memory_cap_reduces_repetitions(orc):
+    s, p = synth.workload("tiny")
+    n, D, w = s.n, s.D, p["w"]
+    ns = n - w + 1
+    fixed = n * D * 8 + 48 * ns * D + (64 << 20)
+    lim = fixed + 4 * ns * D * 20           # room for 20 half-functions
+    want = orc.L_used(n, D, w, 200, 8, lim)
+    assert 1 < want < 200
+    pp = dict(p, mem_limit=lim + (64 << 20))   # the search buffers also come out of the limit
+    plan, _ = _plan(s, pp, "f64", 2)
+    assert plan.params()["L"] == orc.L_used(n, D, w, 200, 8, lim + (64 << 20))
+    plan.close()
