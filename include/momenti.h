@@ -79,9 +79,20 @@ typedef struct {
     int32_t series_on_device; /* 1: the series pointer passed to momenti_hash is device memory */
     int32_t pool_size;        /* verified pairs kept on the device; 0 = max(4096, 64 k) */
     int32_t batch_reps;       /* repetitions traversed per launch; 0 = chosen from mem_limit */
-    int32_t reserved;
+    int32_t profile;          /* 1: time every kernel launch with HIP events (momenti_get_profile) */
     void* stream;             /* hipStream_t, NULL = default stream */
 } momenti_opts;
+
+/* Per-kernel totals collected when opts.profile is set: launches, summed
+ * device time, and the algorithmic bytes moved / flops done by those launches
+ * (what the method must read and write, not cache traffic). */
+typedef struct {
+    char name[24];
+    int64_t launches;
+    double ms;
+    double bytes;
+    double flops;
+} momenti_kprof;
 
 typedef struct {
     int64_t a, b;             /* window starts, a < b, 2 (b - a) > w */
@@ -183,6 +194,11 @@ int momenti_set_hashes(momenti_plan* p, const uint32_t* src, size_t count);
  * the number of candidates (may exceed cand_cap: the trace is then cut). */
 int momenti_set_trace(momenti_plan* p, int64_t* cand, int64_t cand_cap, int64_t* cand_count,
                       int32_t* top_size, int64_t* top_pairs, int64_t steps_cap, int32_t k_cap);
+
+/* Copy up to cap per-kernel profile records (see momenti_kprof) accumulated
+ * since the plan was prepared or the profile was last cleared; *n gets the
+ * number of kernels. clear != 0 resets the totals afterwards. */
+int momenti_get_profile(momenti_plan* p, momenti_kprof* out, int32_t cap, int32_t* n, int32_t clear);
 
 #ifdef __cplusplus
 }

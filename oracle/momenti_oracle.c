@@ -392,6 +392,90 @@ int32_t orc_hash_value(const double* z, int32_t w, const double* R_col, int64_t 
     return (int32_t)byte;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Low-precision forms of the projection (no counterpart in the paper: the  */
+/* inputs of a . x are rounded to a narrow format, the sum is exact).       */
+/* ------------------------------------------------------------------------ */
+
+enum { ORC_FMT_BF16 = 2, ORC_FMT_E4M3 = 3 };
+
+/* Round to nearest, ties to even, to bfloat16 (8 significant bits) or to the
+ * OCP FP8 E4M3 format (4 significant bits, exponent bias 7, subnormal quantum
+ * 2^-9, largest finite value 448, saturating). */
+double orc_round_fmt(double v, int32_t fmt)
+{
+    if (v == 0.0) return v;
+    double a = fabs(v);
+    int ex;
+    frexp(a, &ex);                  /* a in [2^(ex-1), 2^ex) */
+    int lead = ex - 1;
+    int bits = fmt == ORC_FMT_BF16 ? 8 : 4;
+    if (fmt == ORC_FMT_E4M3 && lead < -6) lead = -6;
+    double q = ldexp(1.0, lead - (bits - 1));
+    double r = nearbyint(a / q) * q;
+    if (fmt == ORC_FMT_E4M3 && r > 448.0) r = 448.0;
+    return v < 0 ? -r : r;
+}
+
+/* Spacing of the format's values around v. */
+static double fmt_gap(double v, int32_t fmt)
+{
+    double a = fabs(v);
+    int ex;
+    if (a == 0.0) return fmt == ORC_FMT_BF16 ? ldexp(1.0, -133) : ldexp(1.0, -9);
+    frexp(a, &ex);
+    int lead = ex - 1;
+    int bits = fmt == ORC_FMT_BF16 ? 8 : 4;
+    if (fmt == ORC_FMT_E4M3 && lead < -6) lead = -6;
+    return ldexp(1.0, lead - (bits - 1));
+}
+
+/* Eq. drp with both a and the normal form rounded to the format (the normal
+ * form first to float32): h = floor((Q(a) . Q(x) + b) / r). abs_sum gets
+ * sum |Q(a_t) Q(x_t)|; amb gets sum |Q(a_t)| * gap over the samples whose
+ * float32 value lies within 1e-5 (1 + |x_t|) of a rounding midpoint, where a
+ * differently rounded input is an equally valid evaluation. */
+int32_t orc_hash_value_lowp(const double* z, int32_t w, const double* R_col, int64_t R_stride,
+                            double U, double r, int32_t fmt, double* pre_floor, double* abs_sum,
+                            double* amb)
+{
+    double dot = 0.0, sabs = 0.0, ambs = 0.0;
+    for (int32_t t = 0; t < w; ++t) {
+        double rq = orc_round_fmt(R_col[(int64_t)t * R_stride], fmt);
+        double zf = (double)(float)z[t];
+        double zq = orc_round_fmt(zf, fmt);
+        double term = rq * zq;
+        dot = dot + term;
+        sabs = sabs + fabs(term);
+        double g = fmt_gap(zf, fmt);
+        double to_mid = fabs(g / 2.0 - fabs(zf - zq));
+        if (to_mid <= 1e-5 * (1.0 + fabs(zf))) ambs = ambs + fabs(rq) * g;
+    }
+    double b = r * U;
+    double u = (dot + b) / r;
+    int64_t hv = (int64_t)floor(u);
+    if (pre_floor) *pre_floor = u;
+    if (abs_sum) *abs_sum = sabs;
+    if (amb) *amb = ambs;
+    return (int32_t)(((hv + 128) % 256 + 256) % 256);
+}
+
+void orc_hash_dim_lowp(const double* xf, int64_t n, int32_t w, const double* Rf, const double* Uf,
+                       int32_t C, double r, int32_t fmt, uint8_t* bytes, double* pre, double* sabs,
+                       double* amb)
+{
+    int64_t ns = n - w + 1;
+    double* z = (double*)malloc(sizeof(double) * (size_t)w);
+    for (int64_t a = 0; a < ns; ++a) {
+        znorm(xf + a, w, z);
+        for (int32_t c = 0; c < C; ++c)
+            bytes[a * C + c] = (uint8_t)orc_hash_value_lowp(z, w, Rf + c, C, Uf[c], r, fmt,
+                                                            &pre[a * C + c], &sabs[a * C + c],
+                                                            &amb[a * C + c]);
+    }
+    free(z);
+}
+
 /* Hash every window of one dimension f at the given columns. Outputs are
  * [n_s][C] (bytes, and optionally the pre-floor values and |.| sums). */
 void orc_hash_dim(const double* xf, int64_t n, int32_t w, const double* Rf /* [w][C] */,

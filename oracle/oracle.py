@@ -17,7 +17,7 @@ __all__ = [
     "build", "lib", "philox", "gauss", "uniform", "window_stats", "stats", "dist", "distd",
     "topk_exact", "tensor_shape", "L_used", "draw_projections", "estimate_r", "hash_dim",
     "hash_one", "pack", "prefix", "collision_prob", "fail_bound", "stop", "lsh_search",
-    "lsh_pipeline", "STOP_TENSOR", "STOP_LEMMA52", "FLAT_REL",
+    "lsh_pipeline", "STOP_TENSOR", "STOP_LEMMA52", "FLAT_REL", "round_fmt", "hash_dim_lowp", "FMT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -83,6 +83,9 @@ def lib():
             "orc_hash_dim": (None, [vp, i64, i32, vp, vp, i32, d, vp, vp, vp]),
             "orc_hash_one": (None, [vp, i32, i64, vp, vp, i32, d, vp, vp, vp]),
             "orc_pack": (None, [vp, i64, i32, i32, i32, vp]),
+            "orc_round_fmt": (d, [d, i32]),
+            "orc_hash_value_lowp": (i32, [vp, i32, vp, i64, d, d, i32, P(d), P(d), P(d)]),
+            "orc_hash_dim_lowp": (None, [vp, i64, i32, vp, vp, i32, d, i32, vp, vp, vp, vp]),
             "orc_prefix": (u64, [vp, i64, i32, i32, i32, i32, i32, i64, i32]),
             "orc_collision_prob": (d, [d, d]),
             "orc_fail_bound": (d, [d, i32, i32, i32, i32, i32]),
@@ -219,6 +222,24 @@ def hash_one(xf, w: int, a: int, Rf, Uf, r: float):
     by = np.zeros(Cc, dtype=np.uint8); pre = np.zeros(Cc); sab = np.zeros(Cc)
     lib().orc_hash_one(_p(xf), w, a, _p(Rf), _p(Uf), Cc, r, _p(by), _p(pre), _p(sab))
     return by, pre, sab
+
+
+FMT = {"bf16": 2, "fp8": 3}
+
+
+def round_fmt(v: float, fmt: str) -> float:
+    return lib().orc_round_fmt(v, FMT[fmt])
+
+
+def hash_dim_lowp(xf, w: int, Rf, Uf, r: float, fmt: str):
+    """Symbols, pre-floor values, sum |.| and ambiguity bound of the rounded-input projection."""
+    xf, Rf, Uf = _f64(xf), _f64(Rf), _f64(Uf)
+    n = len(xf); ns = n - w + 1; Cc = Rf.shape[1]
+    by = np.zeros((ns, Cc), dtype=np.uint8)
+    pre = np.zeros((ns, Cc)); sab = np.zeros((ns, Cc)); amb = np.zeros((ns, Cc))
+    lib().orc_hash_dim_lowp(_p(xf), n, w, _p(Rf), _p(Uf), Cc, r, FMT[fmt], _p(by), _p(pre),
+                            _p(sab), _p(amb))
+    return by, pre, sab, amb
 
 
 def pack(bytes_: np.ndarray, NF: int, K: int) -> np.ndarray:

@@ -75,10 +75,14 @@ struct StepGeom {
 };
 constexpr int kSortTile = 4096;
 
-// Sort every segment of the batch by its length-i hash prefix; returns which
-// buffer (0/1) holds the result.
-hipError_t sort_prefixes(const StepGeom& g, const uint32_t* H, SortBufs& b, int* out_buf,
-                         hipStream_t s);
+// Stable LSD sort of every segment of the batch by its length-i hash prefix,
+// one byte per pass (pass 0 reads the keys straight from the index); each
+// pass is histogram + scan + scatter from buffer `cur` to buffer `cur ^ 1`.
+hipError_t launch_hist(const StepGeom& g, const uint32_t* H, const SortBufs& b, int pass, int cur,
+                       hipStream_t s);
+hipError_t launch_scan(const StepGeom& g, const SortBufs& b, hipStream_t s);
+hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& b, int pass, int cur,
+                          hipStream_t s);
 hipError_t launch_enum(const StepGeom& g, const uint32_t* H, const SortBufs& b, int buf, int d,
                        int w, Cand* cand, uint32_t cap, Counters* cnt, hipStream_t s);
 hipError_t launch_verify(const Cand* cand, uint32_t cap, const Counters* cnt, const void* x,

@@ -338,6 +338,203 @@ __global__ __launch_bounds__(256) void k_proj_f32(const T* __restrict__ x, int64
         }
 }
 
+// ---------------------------------------------------------------------------
+// Low-precision projections (BF16, FP8 e4m3) with FP32 accumulation. The
+// normal form x_hat = (x - mu) / sigma is itself the per-window scaling: it is
+// formed in FP32 from a tile-local offset (x - ref, mu - ref, so no large
+// offset cancels) and rounded once to the MFMA input type. R is stored
+// column-major ([c][t], t contiguous) in the same type.
+//   bf16: v_mfma_f32_32x32x16_bf16, lane l holds k = 8 (l / 32) + q, q < 8;
+//   fp8:  v_mfma_scale_f32_32x32x64_f8f6f4 (unit scales), lane l holds
+//         k = 32 (l / 32) + q, q < 32;
+// for row l % 32 of A and column l % 32 of B; D as in the FP32 kernel.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+template <typename T, int WB>
+__device__ inline double load_tile_offset(const T* __restrict__ xf, int64_t n, int64_t a_blk, int wpad,
+                                          float* xs)
+{
+    const double ref = (double)xf[a_blk < n ? a_blk : n - 1];
+    for (int q = threadIdx.x; q < WB + wpad; q += 256) {
+        int64_t g = a_blk + q;
+        xs[q] = g < n ? (float)((double)xf[g] - ref) : 0.0f;
+    }
+    return ref;
+}
+
+template <int MB, int NB>
+__device__ inline void quantize_store(const floatx16 (&acc)[MB][NB], const float* __restrict__ Uf0,
+                                      int64_t a0, int col, int kk, int64_t ns, int NF, int K,
+                                      float inv_r, uint32_t* __restrict__ Hf)
+{
+    const int half = K / 2;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int c0 = mb * 32 + 8 * g + 4 * kk;
+            const int F = c0 / 4;
+            if (F >= NF) continue;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int64_t a = a0 + nb * 32 + col;
+                if (a >= ns) continue;
+                uint32_t word = 0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    if (p < half) word |= sym_of(fmaf(acc[mb][nb][4 * g + p], inv_r, Uf0[c0 + p])) << (24 - 8 * p);
+                Hf[(int64_t)F * ns + a] = word;
+            }
+        }
+}
+
+template <typename T, int MB, int NB>
+__global__ __launch_bounds__(256) void k_proj_bf16(const T* __restrict__ x, int64_t n, int64_t ns,
+                                                   int w, int wpad, const double* __restrict__ mu,
+                                                   const double* __restrict__ isig,
+                                                   const __bf16* __restrict__ R,
+                                                   const float* __restrict__ U, int Cpad, int NF,
+                                                   int K, float inv_r, uint32_t* __restrict__ H)
+{
+    constexpr int WB = 4 * 32 * NB;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* xs = reinterpret_cast<float*>(smem_raw);
+    const int f = blockIdx.y;
+    const int64_t a_blk = (int64_t)blockIdx.x * WB;
+    const double ref = load_tile_offset<T, WB>(x + (int64_t)f * n, n, a_blk, wpad, xs);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 31, kk = lane >> 5;
+    const int wbase = wave * 32 * NB;
+    float sc[NB], off[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int64_t a = a_blk + wbase + nb * 32 + col;
+        const double m = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
+        const double sg = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
+        sc[nb] = (float)sg;
+        off[nb] = (float)(-(m - ref) * sg);
+    }
+    floatx16 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[mb][nb][q] = 0.0f;
+    const __bf16* Rf = R + (int64_t)f * Cpad * wpad;
+    for (int t0 = 0; t0 < wpad; t0 += 16) {
+        const int tb = t0 + 8 * kk;
+        bf16x8 av[MB], bv[NB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+            av[mb] = *reinterpret_cast<const bf16x8*>(Rf + (int64_t)(mb * 32 + col) * wpad + tb);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const float* xp = xs + wbase + nb * 32 + col + tb;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) bv[nb][q] = (__bf16)fmaf(xp[q], sc[nb], off[nb]);
+        }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+    }
+    quantize_store<MB, NB>(acc, U + (int64_t)f * Cpad, a_blk + wbase, col, kk, ns, NF, K, inv_r,
+                           H + (int64_t)f * NF * ns);
+}
+
+template <typename T, int MB, int NB>
+__global__ __launch_bounds__(256) void k_proj_fp8(const T* __restrict__ x, int64_t n, int64_t ns,
+                                                  int w, int wpad, const double* __restrict__ mu,
+                                                  const double* __restrict__ isig,
+                                                  const uint8_t* __restrict__ R,
+                                                  const float* __restrict__ U, int Cpad, int NF,
+                                                  int K, float inv_r, uint32_t* __restrict__ H)
+{
+    constexpr int WB = 4 * 32 * NB;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* xs = reinterpret_cast<float*>(smem_raw);
+    const int f = blockIdx.y;
+    const int64_t a_blk = (int64_t)blockIdx.x * WB;
+    const double ref = load_tile_offset<T, WB>(x + (int64_t)f * n, n, a_blk, wpad, xs);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 31, kk = lane >> 5;
+    const int wbase = wave * 32 * NB;
+    float sc[NB], off[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int64_t a = a_blk + wbase + nb * 32 + col;
+        const double m = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
+        const double sg = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
+        sc[nb] = (float)sg;
+        off[nb] = (float)(-(m - ref) * sg);
+    }
+    floatx16 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[mb][nb][q] = 0.0f;
+    const uint8_t* Rf = R + (int64_t)f * Cpad * wpad;
+    for (int t0 = 0; t0 < wpad; t0 += 64) {
+        const int tb = t0 + 32 * kk;
+        intx8 av[MB], bv[NB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+            av[mb] = *reinterpret_cast<const intx8*>(Rf + (int64_t)(mb * 32 + col) * wpad + tb);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const float* xp = xs + wbase + nb * 32 + col + tb;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                int v = __builtin_amdgcn_cvt_pk_fp8_f32(fmaf(xp[4 * q + 0], sc[nb], off[nb]),
+                                                        fmaf(xp[4 * q + 1], sc[nb], off[nb]), 0, false);
+                v = __builtin_amdgcn_cvt_pk_fp8_f32(fmaf(xp[4 * q + 2], sc[nb], off[nb]),
+                                                    fmaf(xp[4 * q + 3], sc[nb], off[nb]), v, true);
+                bv[nb][q] = v;
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[mb], bv[nb], acc[mb][nb],
+                                                                             0, 0, 0, 127, 0, 127);
+    }
+    quantize_store<MB, NB>(acc, U + (int64_t)f * Cpad, a_blk + wbase, col, kk, ns, NF, K, inv_r,
+                           H + (int64_t)f * NF * ns);
+}
+
+template <typename T, int MB>
+static hipError_t go_lowp(int proj, const T* x, int64_t n, int64_t ns, int D, int w, int wpad,
+                          const double* mu, const double* isig, const void* R, const float* U,
+                          int Cpad, int NF, int K, float inv_r, uint32_t* H, hipStream_t s)
+{
+    constexpr int NB = 2, WB = 4 * 32 * NB;
+    dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
+    size_t lds = (size_t)(WB + wpad) * sizeof(float);
+    if (proj == 2) {
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void*)k_proj_bf16<T, MB, NB>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_proj_bf16<T, MB, NB>), grid, dim3(256), lds, s, x, n, ns, w, wpad, mu,
+                           isig, (const __bf16*)R, U, Cpad, NF, K, inv_r, H);
+    } else {
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void*)k_proj_fp8<T, MB, NB>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_proj_fp8<T, MB, NB>), grid, dim3(256), lds, s, x, n, ns, w, wpad, mu,
+                           isig, (const uint8_t*)R, U, Cpad, NF, K, inv_r, H);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int MB16>
 static hipError_t go_f64(const T* x, int64_t n, int64_t ns, int D, int w, int wpad, const double* mu,
                          const double* isig, const double* R, const double* U, int Cpad, int NF,
@@ -395,6 +592,15 @@ static hipError_t dispatch(int proj, const T* x, int64_t n, int64_t ns, int D, i
         case 2: return go_f32<T, 2>(x, n, ns, D, w, wpad, mu, isig, Rf, Uf, Cpad, NF, K, ir, H, s);
         case 3: return go_f32<T, 3>(x, n, ns, D, w, wpad, mu, isig, Rf, Uf, Cpad, NF, K, ir, H, s);
         case 4: return go_f32<T, 4>(x, n, ns, D, w, wpad, mu, isig, Rf, Uf, Cpad, NF, K, ir, H, s);
+        }
+    } else if (proj == 2 || proj == 3) {
+        const float* Uf = (const float*)U;
+        const float ir = (float)inv_r;
+        switch (MB) {
+        case 1: return go_lowp<T, 1>(proj, x, n, ns, D, w, wpad, mu, isig, R, Uf, Cpad, NF, K, ir, H, s);
+        case 2: return go_lowp<T, 2>(proj, x, n, ns, D, w, wpad, mu, isig, R, Uf, Cpad, NF, K, ir, H, s);
+        case 3: return go_lowp<T, 3>(proj, x, n, ns, D, w, wpad, mu, isig, R, Uf, Cpad, NF, K, ir, H, s);
+        case 4: return go_lowp<T, 4>(proj, x, n, ns, D, w, wpad, mu, isig, R, Uf, Cpad, NF, K, ir, H, s);
         }
     }
     return hipErrorNotSupported;

@@ -259,37 +259,58 @@ __global__ __launch_bounds__(256) void k_scatter(const KT* __restrict__ kin, con
     }
 }
 
-template <typename KT>
-static hipError_t sort_typed(const StepGeom& g, const uint32_t* H, SortBufs& b, int* out_buf,
-                             hipStream_t s)
+// One LSD pass of the segmented sort, as three launches (histogram, scan,
+// scatter); `cur` names the buffer holding the input keys of this pass.
+hipError_t launch_hist(const StepGeom& g, const uint32_t* H, const SortBufs& b, int pass, int cur,
+                       hipStream_t s)
 {
     dim3 grid((unsigned)b.tiles, (unsigned)g.nseg);
-    int cur = 0;
-    for (int pass = 0; pass < g.i; ++pass) {
-        KT* kin = (KT*)b.keys[cur];
-        KT* kout = (KT*)b.keys[cur ^ 1];
-        if (pass == 0) {
-            hipLaunchKernelGGL((k_hist<KT, true>), grid, dim3(256), 0, s, kin, H, g, pass, b.tiles, b.hist);
-            hipLaunchKernelGGL(k_scan, dim3((unsigned)g.nseg), dim3(1024), 0, s, b.hist, b.tiles);
-            hipLaunchKernelGGL((k_scatter<KT, true>), grid, dim3(256), 0, s, kin, b.idx[cur], H, g,
-                               pass, b.tiles, b.hist, kout, b.idx[cur ^ 1]);
-        } else {
-            hipLaunchKernelGGL((k_hist<KT, false>), grid, dim3(256), 0, s, kin, H, g, pass, b.tiles, b.hist);
-            hipLaunchKernelGGL(k_scan, dim3((unsigned)g.nseg), dim3(1024), 0, s, b.hist, b.tiles);
-            hipLaunchKernelGGL((k_scatter<KT, false>), grid, dim3(256), 0, s, kin, b.idx[cur], H, g,
-                               pass, b.tiles, b.hist, kout, b.idx[cur ^ 1]);
-        }
-        cur ^= 1;
+    if (g.i <= 4) {
+        const uint32_t* kin = (const uint32_t*)b.keys[cur];
+        if (pass == 0)
+            hipLaunchKernelGGL((k_hist<uint32_t, true>), grid, dim3(256), 0, s, kin, H, g, pass, b.tiles, b.hist);
+        else
+            hipLaunchKernelGGL((k_hist<uint32_t, false>), grid, dim3(256), 0, s, kin, H, g, pass, b.tiles, b.hist);
+    } else {
+        const uint64_t* kin = (const uint64_t*)b.keys[cur];
+        if (pass == 0)
+            hipLaunchKernelGGL((k_hist<uint64_t, true>), grid, dim3(256), 0, s, kin, H, g, pass, b.tiles, b.hist);
+        else
+            hipLaunchKernelGGL((k_hist<uint64_t, false>), grid, dim3(256), 0, s, kin, H, g, pass, b.tiles, b.hist);
     }
-    *out_buf = cur;
     return hipGetLastError();
 }
 
-hipError_t sort_prefixes(const StepGeom& g, const uint32_t* H, SortBufs& b, int* out_buf,
-                         hipStream_t s)
+hipError_t launch_scan(const StepGeom& g, const SortBufs& b, hipStream_t s)
 {
-    if (g.i <= 4) return sort_typed<uint32_t>(g, H, b, out_buf, s);
-    return sort_typed<uint64_t>(g, H, b, out_buf, s);
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)g.nseg), dim3(1024), 0, s, b.hist, b.tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& b, int pass, int cur,
+                          hipStream_t s)
+{
+    dim3 grid((unsigned)b.tiles, (unsigned)g.nseg);
+    if (g.i <= 4) {
+        const uint32_t* kin = (const uint32_t*)b.keys[cur];
+        uint32_t* kout = (uint32_t*)b.keys[cur ^ 1];
+        if (pass == 0)
+            hipLaunchKernelGGL((k_scatter<uint32_t, true>), grid, dim3(256), 0, s, kin, b.idx[cur], H, g,
+                               pass, b.tiles, b.hist, kout, b.idx[cur ^ 1]);
+        else
+            hipLaunchKernelGGL((k_scatter<uint32_t, false>), grid, dim3(256), 0, s, kin, b.idx[cur], H, g,
+                               pass, b.tiles, b.hist, kout, b.idx[cur ^ 1]);
+    } else {
+        const uint64_t* kin = (const uint64_t*)b.keys[cur];
+        uint64_t* kout = (uint64_t*)b.keys[cur ^ 1];
+        if (pass == 0)
+            hipLaunchKernelGGL((k_scatter<uint64_t, true>), grid, dim3(256), 0, s, kin, b.idx[cur], H, g,
+                               pass, b.tiles, b.hist, kout, b.idx[cur ^ 1]);
+        else
+            hipLaunchKernelGGL((k_scatter<uint64_t, false>), grid, dim3(256), 0, s, kin, b.idx[cur], H, g,
+                               pass, b.tiles, b.hist, kout, b.idx[cur ^ 1]);
+    }
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ enumeration

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -102,6 +103,74 @@ static double uniform_at(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, u
     return unit53(o[0], o[1]);
 }
 
+// ------------------------------------------------------------------ number formats
+// Round-to-nearest-even from FP64, in one step, to the MFMA input types:
+// bfloat16 (8 significant bits, FP32 exponent range) and OCP FP8 E4M3
+// (4 significant bits, bias 7, subnormal quantum 2^-9, largest finite 448).
+static uint16_t to_bf16_bits(double v)
+{
+    if (v == 0.0) return std::signbit(v) ? 0x8000u : 0u;
+    int e;
+    std::frexp(v, &e);                              // |v| in [2^(e-1), 2^e)
+    const double q = std::ldexp(1.0, e - 8);        // quantum for 8 significant bits
+    const double r = std::nearbyint(v / q) * q;     // default rounding mode: nearest-even
+    const float f = (float)r;                       // exact: r has <= 8 significant bits
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint16_t)(u >> 16);
+}
+
+static uint8_t to_e4m3_bits(double v)
+{
+    const uint8_t sgn = std::signbit(v) ? 0x80 : 0x00;
+    double a = std::fabs(v);
+    if (a == 0.0) return sgn;
+    int e;
+    std::frexp(a, &e);
+    int ue = e - 1;                                 // a in [2^ue, 2^(ue+1))
+    if (ue < -6) ue = -6;                           // subnormal range shares the 2^-9 quantum
+    const double q = std::ldexp(1.0, ue - 3);
+    double r = std::nearbyint(a / q) * q;
+    if (r > 448.0) r = 448.0;                       // saturate
+    if (r == 0.0) return sgn;
+    std::frexp(r, &e);
+    int be = e - 1 + 7;                             // biased exponent
+    uint8_t bits;
+    if (be <= 0) {                                  // subnormal: r = m * 2^-9
+        bits = (uint8_t)std::lround(r / std::ldexp(1.0, -9));
+    } else {
+        const double mant = r / std::ldexp(1.0, e - 1) - 1.0;   // in [0, 1)
+        bits = (uint8_t)((be << 3) | (int)std::lround(mant * 8.0));
+    }
+    return sgn | bits;
+}
+
+// ------------------------------------------------------------------ profiling
+// Optional per-kernel timing with HIP events recorded on the plan's stream
+// around each launch; folded into totals whenever the host synchronises.
+enum KernelId { KI_STATS, KI_RSAMPLE, KI_PROJ, KI_HIST, KI_SCAN, KI_SCATTER, KI_ENUM, KI_VERIFY,
+                KI_FILTER, KI_POOL, KI_ALLPAIRS, KI_COUNT };
+static const char* const kKernelNames[KI_COUNT] = {
+    "stats", "rsample", "proj", "sort_hist", "sort_scan", "sort_scatter", "enum", "verify",
+    "pool_filter", "pool", "allpairs"};
+
+struct KTotal {
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0, flops = 0.0;
+};
+
+struct Profiler {
+    bool on = false;
+    struct Pending {
+        int id;
+        hipEvent_t a, b;
+        double bytes, flops;
+    };
+    std::vector<hipEvent_t> spare;
+    std::vector<Pending> pending;
+    KTotal tot[KI_COUNT];
+};
+
 // ------------------------------------------------------------------ plan
 struct momenti_plan {
     int64_t n = 0, ns = 0;
@@ -140,6 +209,7 @@ struct momenti_plan {
     unsigned char* host_status = nullptr;
 
     uint64_t bytes = 0, peak = 0;
+    Profiler prof;
 
     // trace
     int64_t* tr_cand = nullptr;
@@ -186,6 +256,60 @@ static void dfree(momenti_plan* p, void* ptr, size_t bytes)
     p->bytes -= std::min<uint64_t>(p->bytes, bytes);
 }
 
+static hipEvent_t prof_event(momenti_plan* p)
+{
+    if (!p->prof.spare.empty()) {
+        hipEvent_t e = p->prof.spare.back();
+        p->prof.spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Launch through `fn`, bracketed by events when profiling. Returns the index
+// of the pending record (or -1), so that work sizes known only later can be
+// filled in with prof_set.
+template <class F>
+static hipError_t timed(momenti_plan* p, int id, double bytes, double flops, F&& fn, int* slot = nullptr)
+{
+    if (slot) *slot = -1;
+    if (!p->prof.on) return fn();
+    hipEvent_t a = prof_event(p), b = prof_event(p);
+    (void)hipEventRecord(a, p->st);
+    hipError_t e = fn();
+    (void)hipEventRecord(b, p->st);
+    if (slot) *slot = (int)p->prof.pending.size();
+    p->prof.pending.push_back({id, a, b, bytes, flops});
+    return e;
+}
+
+static void prof_set(momenti_plan* p, int slot, double bytes, double flops)
+{
+    if (slot < 0 || slot >= (int)p->prof.pending.size()) return;
+    p->prof.pending[slot].bytes = bytes;
+    p->prof.pending[slot].flops = flops;
+}
+
+// Fold completed launches into the totals (call after a stream synchronisation).
+static void prof_flush(momenti_plan* p)
+{
+    for (auto& q : p->prof.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+            KTotal& t = p->prof.tot[q.id];
+            t.launches += 1;
+            t.ms += ms;
+            t.bytes += q.bytes;
+            t.flops += q.flops;
+        }
+        p->prof.spare.push_back(q.a);
+        p->prof.spare.push_back(q.b);
+    }
+    p->prof.pending.clear();
+}
+
 static int64_t ceil_sqrt_i(int64_t v)
 {
     int64_t m = (int64_t)std::sqrt((double)v);
@@ -217,7 +341,11 @@ static int cap_repetitions(int64_t n, int D, int w, int L_max, int elem, uint64_
 }
 
 static size_t series_bytes(const momenti_plan* p) { return (size_t)p->n * p->D * (p->dtype == MOMENTI_F64 ? 8 : 4); }
-static size_t proj_elem(int proj) { return proj == MOMENTI_PROJ_F64 ? 8 : 4; }
+static size_t proj_elem(int proj)
+{
+    return proj == MOMENTI_PROJ_F64 ? 8 : proj == MOMENTI_PROJ_F32 ? 4 : proj == MOMENTI_PROJ_BF16 ? 2 : 1;
+}
+static size_t offs_elem(int proj) { return proj == MOMENTI_PROJ_F64 ? 8 : 4; }
 
 static void release_search(momenti_plan* p)
 {
@@ -266,12 +394,16 @@ const char* momenti_last_error(void) { return g_err.c_str(); }
 void momenti_destroy(momenti_plan* p)
 {
     if (!p) return;
+    if (p->st) (void)hipStreamSynchronize(p->st); else (void)hipDeviceSynchronize();
+    prof_flush(p);
+    for (hipEvent_t e : p->prof.spare) (void)hipEventDestroy(e);
+    p->prof.spare.clear();
     release_search(p);
     if (p->own_series) dfree(p, p->series, series_bytes(p));
     dfree(p, p->mu, (size_t)p->D * p->ns * 8);
     dfree(p, p->isig, (size_t)p->D * p->ns * 8);
     dfree(p, p->R, (size_t)p->D * p->wpad * p->Cpad * proj_elem(p->o.proj));
-    dfree(p, p->U, (size_t)p->D * p->Cpad * proj_elem(p->o.proj));
+    dfree(p, p->U, (size_t)p->D * p->Cpad * offs_elem(p->o.proj));
     dfree(p, p->H, (size_t)p->D * p->NF * p->ns * 4);
     delete p;
 }
@@ -291,7 +423,7 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
     if (dtype != MOMENTI_F64 && dtype != MOMENTI_F32) return fail(MOMENTI_E_ARG, "bad dtype %d", dtype);
     if (o.K < 2 || o.K > 8 || (o.K & 1)) return fail(MOMENTI_E_ARG, "K=%d must be even in [2, 8]", o.K);
     if (o.L < 1 || o.L > 1024) return fail(MOMENTI_E_ARG, "L=%d outside [1, 1024]", o.L);
-    if (o.proj != MOMENTI_PROJ_F64 && o.proj != MOMENTI_PROJ_F32)
+    if (o.proj < MOMENTI_PROJ_F64 || o.proj > MOMENTI_PROJ_FP8)
         return fail(MOMENTI_E_ARG, "projection precision %d not available", o.proj);
     if (o.stop_rule != MOMENTI_STOP_TENSOR && o.stop_rule != MOMENTI_STOP_LEMMA52)
         return fail(MOMENTI_E_ARG, "bad stop rule %d", o.stop_rule);
@@ -312,6 +444,7 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
     p->Cpad = ((C + 31) / 32) * 32;
     p->wpad = ((w + 63) / 64) * 64;
     p->st = (hipStream_t)o.stream;
+    p->prof.on = o.profile != 0;
     if (hipGetDevice(&p->dev) != hipSuccess) {
         delete p;
         return fail(MOMENTI_E_DEVICE, "no HIP device");
@@ -329,7 +462,7 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
             U[(size_t)f * p->Cpad + c] = uniform_at(o.seed, (uint32_t)c, (uint32_t)f, 0u, kStreamOffset);
     }
     int rc;
-    if ((rc = dalloc(p, &p->R, R.size() * pe)) || (rc = dalloc(p, &p->U, U.size() * pe)) ||
+    if ((rc = dalloc(p, &p->R, R.size() * pe)) || (rc = dalloc(p, &p->U, U.size() * offs_elem(o.proj))) ||
         (rc = dalloc_t(p, &p->mu, (size_t)D * p->ns * 8)) ||
         (rc = dalloc_t(p, &p->isig, (size_t)D * p->ns * 8)) ||
         (rc = dalloc_t(p, &p->H, (size_t)D * p->NF * p->ns * 4))) {
@@ -340,9 +473,31 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
     if (o.proj == MOMENTI_PROJ_F64) {
         e = hipMemcpy(p->R, R.data(), R.size() * 8, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(p->U, U.data(), U.size() * 8, hipMemcpyHostToDevice);
-    } else {
+    } else if (o.proj == MOMENTI_PROJ_F32) {
         std::vector<float> Rf(R.begin(), R.end()), Uf(U.begin(), U.end());
         e = hipMemcpy(p->R, Rf.data(), Rf.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->U, Uf.data(), Uf.size() * 4, hipMemcpyHostToDevice);
+    } else {
+        // low precision: column-major [f][c][t] so that a lane loads consecutive t
+        std::vector<float> Uf(U.begin(), U.end());
+        const size_t cnt = (size_t)D * p->Cpad * p->wpad;
+        if (o.proj == MOMENTI_PROJ_BF16) {
+            std::vector<uint16_t> Rq(cnt, 0);
+            for (int f = 0; f < D; ++f)
+                for (int t = 0; t < p->wpad; ++t)
+                    for (int c = 0; c < p->Cpad; ++c)
+                        Rq[((size_t)f * p->Cpad + c) * p->wpad + t] =
+                            to_bf16_bits(R[((size_t)f * p->wpad + t) * p->Cpad + c]);
+            e = hipMemcpy(p->R, Rq.data(), cnt * 2, hipMemcpyHostToDevice);
+        } else {
+            std::vector<uint8_t> Rq(cnt, 0);
+            for (int f = 0; f < D; ++f)
+                for (int t = 0; t < p->wpad; ++t)
+                    for (int c = 0; c < p->Cpad; ++c)
+                        Rq[((size_t)f * p->Cpad + c) * p->wpad + t] =
+                            to_e4m3_bits(R[((size_t)f * p->wpad + t) * p->Cpad + c]);
+            e = hipMemcpy(p->R, Rq.data(), cnt, hipMemcpyHostToDevice);
+        }
         if (e == hipSuccess) e = hipMemcpy(p->U, Uf.data(), Uf.size() * 4, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
@@ -378,7 +533,10 @@ int momenti_hash(momenti_plan* p, const void* series)
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
     HIP_OK(hipEventRecord(e0, p->st));
-    HIP_OK(launch_stats(p->series, p->dtype, p->n, p->ns, p->D, p->w, p->mu, p->isig, p->st));
+    const double elem = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
+    HIP_OK(timed(p, KI_STATS, (double)p->n * p->D * elem + 16.0 * p->ns * p->D, 0.0, [&] {
+        return launch_stats(p->series, p->dtype, p->n, p->ns, p->D, p->w, p->mu, p->isig, p->st);
+    }));
 
     // r (section 6.1): projections of sampled z-normalised windows on 8
     // Gaussian vectors, split into 256 equal buckets.
@@ -410,7 +568,10 @@ int momenti_hash(momenti_plan* p, const void* series)
         std::vector<double> dots(nd);
         hipError_t e = hipMemcpyAsync(d_win, win.data(), win.size() * 8, hipMemcpyHostToDevice, p->st);
         if (e == hipSuccess) e = hipMemcpyAsync(d_vec, vec.data(), vec.size() * 8, hipMemcpyHostToDevice, p->st);
-        if (e == hipSuccess) e = launch_rsample(p->series, p->dtype, p->n, p->D, p->w, d_win, S, d_vec, nvec, d_dots, p->st);
+        if (e == hipSuccess)
+            e = timed(p, KI_RSAMPLE, (double)p->D * S * p->w * elem, 2.0 * p->D * S * p->w * (nvec + 2), [&] {
+                return launch_rsample(p->series, p->dtype, p->n, p->D, p->w, d_win, S, d_vec, nvec, d_dots, p->st);
+            });
         if (e == hipSuccess) e = hipMemcpyAsync(dots.data(), d_dots, nd * 8, hipMemcpyDeviceToHost, p->st);
         if (e == hipSuccess) e = hipStreamSynchronize(p->st);
         dfree(p, d_win, win.size() * 8);
@@ -426,14 +587,23 @@ int momenti_hash(momenti_plan* p, const void* series)
         if (!(r > 0.0) || !std::isfinite(r)) r = 1.0;
     }
     p->r = r;
-    HIP_OK(launch_proj(p->o.proj, p->series, p->dtype, p->n, p->ns, p->D, p->w, p->mu, p->isig,
-                       p->R, p->U, p->Cpad, p->wpad, p->NF, p->K, 1.0 / r, p->H, p->st));
+    {
+        // useful work: K/2 positions of every half-function, 2 w flops each
+        const double cols = (double)(p->K / 2) * p->NF;
+        const double flops = 2.0 * p->w * cols * (double)p->ns * p->D;
+        const double bytes = (double)p->n * p->D * elem + 16.0 * p->ns * p->D + 4.0 * p->NF * p->ns * p->D;
+        HIP_OK(timed(p, KI_PROJ, bytes, flops, [&] {
+            return launch_proj(p->o.proj, p->series, p->dtype, p->n, p->ns, p->D, p->w, p->mu, p->isig,
+                               p->R, p->U, p->Cpad, p->wpad, p->NF, p->K, 1.0 / r, p->H, p->st);
+        }));
+    }
     HIP_OK(hipEventRecord(e1, p->st));
     HIP_OK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    prof_flush(p);
     p->t_hash_ms = ms;
     p->hashed = true;
     p->have_stats = true;
@@ -479,6 +649,25 @@ int momenti_set_hashes(momenti_plan* p, const uint32_t* src, size_t count)
     HIP_OK(hipStreamSynchronize(p->st));
     HIP_OK(hipMemcpy(p->H, src, count * 4, hipMemcpyHostToDevice));
     p->hashed = true;
+    return MOMENTI_OK;
+}
+
+int momenti_get_profile(momenti_plan* p, momenti_kprof* out, int32_t cap, int32_t* n, int32_t clear)
+{
+    if (!p || !n) return fail(MOMENTI_E_ARG, "NULL argument");
+    HIP_OK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());
+    prof_flush(p);
+    *n = KI_COUNT;
+    for (int q = 0; q < KI_COUNT && q < cap && out; ++q) {
+        std::memset(&out[q], 0, sizeof out[q]);
+        std::snprintf(out[q].name, sizeof out[q].name, "%s", kKernelNames[q]);
+        out[q].launches = p->prof.tot[q].launches;
+        out[q].ms = p->prof.tot[q].ms;
+        out[q].bytes = p->prof.tot[q].bytes;
+        out[q].flops = p->prof.tot[q].flops;
+    }
+    if (clear)
+        for (auto& t : p->prof.tot) t = KTotal();
     return MOMENTI_OK;
 }
 
@@ -606,9 +795,13 @@ struct BatchOut {
 static int pool_stage(momenti_plan* p, int k, int j0, int B)
 {
     Counters* cnt = st_counters(p);
-    HIP_OK(launch_filter(p->vrec, p->cap, cnt, st_pool(p), p->pools, p->P, p->keep, cnt, p->st));
-    HIP_OK(launch_pool(p->vrec, p->keep, p->cap, cnt, st_pool(p), p->pools, p->P, p->top, k, p->w,
-                       j0, B, st_snaps(p), p->snap_tops, p->st));
+    HIP_OK(timed(p, KI_FILTER, 0.0, 0.0, [&] {
+        return launch_filter(p->vrec, p->cap, cnt, st_pool(p), p->pools, p->P, p->keep, cnt, p->st);
+    }));
+    HIP_OK(timed(p, KI_POOL, 0.0, 0.0, [&] {
+        return launch_pool(p->vrec, p->keep, p->cap, cnt, st_pool(p), p->pools, p->P, p->top, k, p->w,
+                           j0, B, st_snaps(p), p->snap_tops, p->st);
+    }));
     return MOMENTI_OK;
 }
 
@@ -683,9 +876,17 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     std::vector<Cand> hcand;
     std::vector<VRec> hsnap;
 
+    static const int verbose = [] {
+        const char* v = std::getenv("MOMENTI_VERBOSE");
+        return v ? std::atoi(v) : 0;
+    }();
 restart:
     HIP_OK(launch_pool_reset(st_pool(p), p->st));
     for (int i = p->K; i >= 1; --i) {
+        if (verbose)
+            std::fprintf(stderr, "[momenti] round i=%d: %.1f ms, steps %lld, collisions %lld, candidates %lld\n", i,
+                         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
+                         (long long)R.n_steps, (long long)R.n_collisions, (long long)R.n_cand);
         for (int j0 = 0; j0 < p->L;) {
             const int Bc = std::min(B, p->L - j0);
             StepGeom g;
@@ -693,13 +894,38 @@ restart:
             g.j0 = j0; g.nseg = Bc * p->D; g.i = i; g.K = p->K;
             HIP_OK(launch_zero(p->status, 64, p->st));
             int buf = 0;
-            HIP_OK(sort_prefixes(g, p->H, p->sb, &buf, p->st));
-            HIP_OK(launch_enum(g, p->H, p->sb, buf, d, p->w, p->cand, p->cap, st_counters(p), p->st));
-            HIP_OK(launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
-                                 p->D, p->w, d, p->mu, p->isig, p->vrec, p->st));
+            const double elems = (double)g.nseg * p->ns;
+            const double kb = i <= 4 ? 4.0 : 8.0;
+            for (int pass = 0; pass < i; ++pass) {
+                const double kin = pass == 0 ? 8.0 : kb;   // pass 0 reads two index words
+                HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
+                HIP_OK(timed(p, KI_SCAN, 8.0 * g.nseg * 256.0 * p->sb.tiles, 0.0, [&] { return launch_scan(g, p->sb, p->st); }));
+                HIP_OK(timed(p, KI_SCATTER, elems * (kin + (pass == 0 ? 0.0 : 4.0) + kb + 4.0), 0.0,
+                             [&] { return launch_scatter(g, p->H, p->sb, pass, buf, p->st); }));
+                buf ^= 1;
+            }
+            int enum_slot = -1, verify_slot = -1;
+            HIP_OK(timed(p, KI_ENUM, elems * kb, 0.0, [&] {
+                return launch_enum(g, p->H, p->sb, buf, d, p->w, p->cand, p->cap, st_counters(p), p->st);
+            }, &enum_slot));
+            HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
+                return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
+                                     p->D, p->w, d, p->mu, p->isig, p->vrec, p->st);
+            }, &verify_slot));
             if ((rc = pool_stage(p, k, j0, Bc))) return rc;
             BatchOut bo;
             if ((rc = read_status(p, &bo, Bc))) return rc;
+            {
+                // sizes known only now: the enumeration read the runs' indices and
+                // gathered 2 words per dimension per endpoint of each scanned pair;
+                // verification read 2 D w samples per candidate
+                const double selem = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
+                const uint32_t nc = std::min(bo.cnt.n_cand, p->cap);
+                prof_set(p, enum_slot, elems * kb + 16.0 * p->D * (double)bo.cnt.n_coll, 0.0);
+                prof_set(p, verify_slot, (double)nc * (2.0 * p->D * p->w * selem + 16.0 * 2 * p->D + sizeof(VRec)),
+                         (double)nc * 6.0 * p->D * p->w);
+                prof_flush(p);
+            }
             if (bo.cnt.n_cand > p->cap) {
                 // more candidates than room: fewer repetitions per launch, then a larger buffer
                 if (Bc > 1) {
@@ -808,11 +1034,16 @@ static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int
             int64_t hi = row + 1;
             while (hi < M && off(hi + 1) - off(row) <= (int64_t)p->cap) ++hi;
             HIP_OK(launch_zero(p->status, 64, p->st));
-            HIP_OK(launch_allpairs(p->ns, p->w, row, hi, off(row), p->cand, st_counters(p), p->st));
-            HIP_OK(launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
-                                 p->D, p->w, d, p->mu, p->isig, p->vrec, p->st));
+            HIP_OK(timed(p, KI_ALLPAIRS, 16.0 * (off(hi) - off(row)), 0.0, [&] {
+                return launch_allpairs(p->ns, p->w, row, hi, off(row), p->cand, st_counters(p), p->st);
+            }));
+            HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
+                return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
+                                     p->D, p->w, d, p->mu, p->isig, p->vrec, p->st);
+            }));
             if ((rc = pool_stage(p, k, 0, 1))) return rc;
             if ((rc = read_status(p, &bo, 1))) return rc;
+            prof_flush(p);
             rep->n_verified += bo.cnt.n_cand;
             row = hi;
         }

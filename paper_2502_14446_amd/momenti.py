@@ -25,15 +25,20 @@ STOP = {"tensor": 0, "lemma52": 1}
 EXPORTS = [
     "momenti_default_opts", "momenti_prepare", "momenti_hash", "momenti_search", "momenti_topk",
     "momenti_destroy", "momenti_last_error", "momenti_get_params", "momenti_get_stats",
-    "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace",
+    "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace", "momenti_get_profile",
 ]
 
 
 class Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("K", C.c_int32), ("L", C.c_int32), ("r", C.c_double),
                 ("proj", C.c_int32), ("stop_rule", C.c_int32), ("series_on_device", C.c_int32),
-                ("pool_size", C.c_int32), ("batch_reps", C.c_int32), ("reserved", C.c_int32),
+                ("pool_size", C.c_int32), ("batch_reps", C.c_int32), ("profile", C.c_int32),
                 ("stream", C.c_void_p)]
+
+
+class KProf(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("launches", C.c_int64), ("ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
 
 
 class Motif(C.Structure):
@@ -82,6 +87,7 @@ def lib():
             "momenti_get_hashes": (i32, [vp, vp, C.c_size_t]),
             "momenti_set_hashes": (i32, [vp, vp, C.c_size_t]),
             "momenti_set_trace": (i32, [vp, vp, i64, vp, vp, vp, i64, i32]),
+            "momenti_get_profile": (i32, [vp, P(KProf), i32, P(i32), i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -99,13 +105,14 @@ def _check(rc: int) -> int:
 
 def make_opts(seed: int = 0x5EED, K: int = 8, L: int = 200, r: float = 0.0, proj: str = "f32",
               stop: str = "tensor", series_on_device: bool = False, pool_size: int = 0,
-              batch_reps: int = 0, stream: Optional[int] = None) -> Opts:
+              batch_reps: int = 0, profile: bool = False, stream: Optional[int] = None) -> Opts:
     o = Opts()
     lib().momenti_default_opts(C.byref(o))
     o.seed, o.K, o.L, o.r = seed, K, L, r
     o.proj, o.stop_rule = PROJ[proj], STOP[stop]
     o.series_on_device = 1 if series_on_device else 0
     o.pool_size, o.batch_reps = pool_size, batch_reps
+    o.profile = 1 if profile else 0
     o.stream = stream
     return o
 
@@ -211,6 +218,14 @@ class Plan:
     def set_hashes(self, words: np.ndarray) -> None:
         words = np.ascontiguousarray(words, dtype=np.uint32)
         _check(lib().momenti_set_hashes(self.h, words.ctypes.data_as(C.c_void_p), words.size))
+
+    def profile(self, clear: bool = False) -> Dict[str, Dict]:
+        """Per-kernel totals (launches, ms, algorithmic bytes, flops) when profiling is on."""
+        recs = (KProf * 32)()
+        n = C.c_int32()
+        _check(lib().momenti_get_profile(self.h, recs, 32, C.byref(n), 1 if clear else 0))
+        return {r.name.decode(): dict(launches=r.launches, ms=r.ms, bytes=r.bytes, flops=r.flops)
+                for r in recs[:n.value]}
 
     def set_trace(self, cand_cap: int, k: int) -> None:
         K, L = self.opts.K, self.params()["L"]

@@ -295,3 +295,51 @@ def test_memory_cap_reduces_repetitions(orc):
     plan, _ = _plan(s, pp, "f64", 2)
     assert plan.params()["L"] == orc.L_used(n, D, w, 200, 8, lim + (64 << 20))
     plan.close()
+
+
+# --------------------------------------------------------------------------- low precision
+def _lowp_band(w, pre, sab, amb, r):
+    # FP32 accumulation of exact products, the FP32 epilogue (1/r, U, fma), and
+    # inputs whose float32 value sits at a rounding midpoint of the format
+    u = 2.0 ** -24
+    return 2.0 * u * ((w + 4) * sab / r + 3.0 * (np.abs(pre) + 1.0)) + amb / r
+
+
+@pytest.mark.parametrize("proj", ["bf16", "fp8"])
+def test_lowp_hash_matches_rounded_input_emulation(orc, proj):
+    s = synth.make_series(synth.DATA_SEED["tiny"], 4, 2000, 50, 1, 2, dtype="f32", min_gap=500)
+    p = dict(w=50, mem_limit=1 << 30)
+    seed = 77
+    plan, _ = _plan(s, p, proj, seed)
+    prm = plan.params()
+    R, U = orc.draw_projections(seed, s.D, 50, 4 * prm["NF"])
+    r = prm["r"]
+    assert r == orc.estimate_r(s.x, 50, seed)
+    by, pre, sab, amb = [], [], [], []
+    for f in range(s.D):
+        b_, p_, s_, a_ = orc.hash_dim_lowp(s.x[f], 50, R[f], U[f], r, proj)
+        by.append(b_); pre.append(p_); sab.append(s_); amb.append(a_)
+    by, pre, sab, amb = map(np.array, (by, pre, sab, amb))
+    gsym = _unpack(plan.hashes(), 8)
+    bad_out, bad_in, near, diff = _check_symbols(gsym, by, pre, _lowp_band(50, pre, sab, amb, r), 8)
+    print(f"{proj}: symbols={by.size} band={near} differing={diff}")
+    assert bad_out == 0 and bad_in == 0
+    # against the FP64 hash: the flip rate the narrow format costs
+    ref, pre64, _ = _oracle_symbols(orc, s.x, 50, R, U, r)
+    flips = float(np.mean(gsym[..., :116] != ref[..., :116]))
+    print(f"{proj}: flip rate vs FP64 = {flips:.4f}")
+    assert flips < (0.05 if proj == "bf16" else 0.5)
+    plan.close()
+
+
+@pytest.mark.parametrize("proj", ["bf16", "fp8"])
+def test_lowp_topk_is_exact(orc, proj):
+    s = synth.make_series(51, 5, 2500, 40, 3, 2, dtype="f32")
+    p = dict(w=40, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, proj, 5)
+    got, rep, rc = plan.search(2, 3, 0.05)
+    ex = orc.topk_exact(s.x, 40, 2, 3)
+    assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ex]
+    for g, o in zip(got, ex):
+        assert g["dist_d"] == pytest.approx(o["dist_d"], rel=1e-9)
+    plan.close()
