@@ -61,11 +61,15 @@ extern "C" {
 #define MOMENTI_PROJ_BF16 2
 #define MOMENTI_PROJ_FP8 3
 
-/* Stopping rule. TENSOR: Lemma 6.1 (the bound for the tensored index, as
- * printed: P_t(i', J') = (1 - p^ceil(i'))^(J' div m) (1 - p^floor(i'))^(J' mod m)).
+/* Stopping rule. TENSOR: Lemma 6.1 (the bound for the tensored index,
+ * P_t(i', J') = (1 - p^ceil(i'))^(J' div m) (1 - p^floor(i'))^(J' mod m)),
+ * where a half contributing no symbol to the prefix (floor(i') = 0 in round
+ * 1) gives the factor 1. TENSOR_LITERAL: the same bound with that factor
+ * taken literally, (1 - p^0)^x = 0, which stops round 1 as soon as |TOP| = k.
  * LEMMA52: Eq. probnotcolliding of Lemma 5.2 ((1 - p^i)^J (1 - p^(i+1))^(L-J)). */
 #define MOMENTI_STOP_TENSOR 0
 #define MOMENTI_STOP_LEMMA52 1
+#define MOMENTI_STOP_TENSOR_LITERAL 2
 
 typedef struct momenti_plan momenti_plan;   /* opaque, owned by the library */
 

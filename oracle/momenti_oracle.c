@@ -432,9 +432,11 @@ static double fmt_gap(double v, int32_t fmt)
 
 /* Eq. drp with both a and the normal form rounded to the format (the normal
  * form first to float32): h = floor((Q(a) . Q(x) + b) / r). abs_sum gets
- * sum |Q(a_t) Q(x_t)|; amb gets sum |Q(a_t)| * gap over the samples whose
- * float32 value lies within 1e-5 (1 + |x_t|) of a rounding midpoint, where a
- * differently rounded input is an equally valid evaluation. */
+ * sum |Q(a_t) Q(x_t)|; amb bounds the change from inputs that another valid
+ * evaluation may round differently: sum |Q(a_t)| * gap over samples whose
+ * float32 value lies within 1e-5 (1 + |x_t|) of a rounding midpoint, plus, for
+ * E4M3, |Q(a_t) Q(x_t)| whenever either factor is subnormal (below 2^-6),
+ * which hardware may flush to zero. */
 int32_t orc_hash_value_lowp(const double* z, int32_t w, const double* R_col, int64_t R_stride,
                             double U, double r, int32_t fmt, double* pre_floor, double* abs_sum,
                             double* amb)
@@ -450,6 +452,8 @@ int32_t orc_hash_value_lowp(const double* z, int32_t w, const double* R_col, int
         double g = fmt_gap(zf, fmt);
         double to_mid = fabs(g / 2.0 - fabs(zf - zq));
         if (to_mid <= 1e-5 * (1.0 + fabs(zf))) ambs = ambs + fabs(rq) * g;
+        if (fmt == ORC_FMT_E4M3 && (fabs(rq) < 0.015625 || fabs(zq) < 0.015625))
+            ambs = ambs + fabs(term) + fabs(rq) * g;
     }
     double b = r * U;
     double u = (dot + b) / r;
@@ -559,16 +563,27 @@ double orc_collision_prob(double R, double r)
     return 1.0 - 2.0 * Phi - 2.0 / (sqrt(2.0 * M_PI) * t) * (1.0 - exp(-(t * t) / 2.0));
 }
 
-enum { ORC_STOP_TENSOR = 0, ORC_STOP_LEMMA52 = 1 };
+enum { ORC_STOP_TENSOR = 0, ORC_STOP_LEMMA52 = 1, ORC_STOP_TENSOR_LITERAL = 2 };
 
 /* Failure bound after J repetitions of round i.
  * rule TENSOR: Lemma 6.1 with P_t(i', J') = (1 - p^ceil(i'))^(J' div m) *
- *              (1 - p^floor(i'))^(J' mod m), m = ceil(sqrt(L));
+ *              (1 - p^floor(i'))^(J' mod m), m = ceil(sqrt(L)), where a half
+ *              that contributes no symbol to the prefix (floor(i') = 0, i.e.
+ *              round 1) gives the factor 1: it offers no collision chance of
+ *              its own. Printed literally that factor is (1 - p^0)^x = 0,
+ *              which would stop round 1 unconditionally (rule TENSOR_LITERAL).
  * rule LEMMA52: Eq. probnotcolliding, (1 - p^i)^J [ * (1 - p^(i+1))^(L - J) ].
  * x^0 is 1 (including 0^0). */
 static double powi_(double base, int64_t e)
 {
     return e == 0 ? 1.0 : pow(base, (double)e);
+}
+
+/* (1 - p^c)^e, one factor of P_t; c = 0 is the empty half (see above). */
+static double tfactor(double p, int32_t c, int64_t e, int32_t rule)
+{
+    if (c == 0 && rule == ORC_STOP_TENSOR) return 1.0;
+    return powi_(1.0 - powi_(p, c), e);
 }
 
 double orc_fail_bound(double p, int32_t i, int32_t J, int32_t K, int32_t L, int32_t rule)
@@ -580,11 +595,11 @@ double orc_fail_bound(double p, int32_t i, int32_t J, int32_t K, int32_t L, int3
     }
     int32_t m = (int32_t)ceil_sqrt(L);
     /* P_t(i/2, J): ceil(i/2) = (i+1)/2, floor(i/2) = i/2 */
-    double v = powi_(1.0 - powi_(p, (i + 1) / 2), J / m) * powi_(1.0 - powi_(p, i / 2), J % m);
+    double v = tfactor(p, (i + 1) / 2, J / m, rule) * tfactor(p, i / 2, J % m, rule);
     if (i < K) {
         /* P_t((i+1)/2, L-J): ceil((i+1)/2) = (i+2)/2, floor((i+1)/2) = (i+1)/2 */
         int32_t J2 = L - J;
-        v = v * powi_(1.0 - powi_(p, (i + 2) / 2), J2 / m) * powi_(1.0 - powi_(p, (i + 1) / 2), J2 % m);
+        v = v * tfactor(p, (i + 2) / 2, J2 / m, rule) * tfactor(p, (i + 1) / 2, J2 % m, rule);
     }
     return v;
 }

@@ -8,16 +8,17 @@
 
 namespace mm {
 
-// A repetition-tagged candidate pair (a < b) emitted by the traversal.
+// A candidate pair (a < b) emitted by the traversal, tagged with the
+// repetition j and the round (prefix length) i that produced it.
 struct Cand {
-    uint32_t a, b, j, pad;
+    uint32_t a, b, j, pad;   // pad: round i
 };
 
 // A verified pair: dist_d (definition "d-dimensional distance"), dist_max
 // (Eq. distdmax), the chosen dimensions and the repetition that produced it.
 struct VRec {
     double dist_d, dist_max;
-    uint32_t a, b, j, pad;
+    uint32_t a, b, j, pad;   // pad: round i
     uint64_t dims[2];
 };
 static_assert(sizeof(VRec) == 48, "VRec layout");
@@ -42,8 +43,24 @@ struct Snap {
 // Device counters of one batch of traversal steps.
 struct Counters {
     uint32_t n_cand;             // candidates emitted (may exceed the buffer)
-    uint32_t n_keep;             // verified candidates kept by the pool filter
+    uint32_t n_runs;             // runs of >= 2 equal prefixes (may exceed the buffer)
     unsigned long long n_coll;   // non-trivial one-dimensional collisions scanned
+    unsigned long long n_memb;   // elements in those runs
+};
+
+// A run of equal prefixes inside one sorted segment.
+struct RunRec {
+    uint32_t seg, start, len, pad;
+};
+
+// Control block of one replay of verified records in step order.
+constexpr int kMaxSteps = 8 * 1024;
+struct ReplayCtl {
+    uint32_t n_keep;
+    int32_t K, L, s0, nsteps;
+    int32_t pad[3];
+    uint32_t step_count[kMaxSteps];
+    uint32_t step_off[kMaxSteps + 1];
 };
 
 constexpr int kMaxD = 128;
@@ -71,7 +88,8 @@ struct StepGeom {
     int64_t ns;
     int D, NF, NL, m;
     int j0, nseg;        // first repetition of the batch, segments = reps * D
-    int i, K;
+    int i, K;            // prefix length the segments are sorted by; K
+    int i_lo;            // lowest round enumerated from this sort (i_lo <= i)
 };
 constexpr int kSortTile = 4096;
 
@@ -83,17 +101,26 @@ hipError_t launch_hist(const StepGeom& g, const uint32_t* H, const SortBufs& b, 
 hipError_t launch_scan(const StepGeom& g, const SortBufs& b, hipStream_t s);
 hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& b, int pass, int cur,
                           hipStream_t s);
-hipError_t launch_enum(const StepGeom& g, const uint32_t* H, const SortBufs& b, int buf, int d,
-                       int w, Cand* cand, uint32_t cap, Counters* cnt, hipStream_t s);
+// Key table of the batch: rows[jb][a][f] = length-kt interleaved prefix
+// (uint32 when kt <= 4, else uint64).
+hipError_t launch_keytable(const uint32_t* H, const StepGeom& g, int reps, int kt, void* rows,
+                           hipStream_t s);
+// Runs of >= 2 equal length-i_lo prefixes and the pairs of every run (one
+// launch); `part` holds enum_partials(g) per-work-group collision counts.
+int64_t enum_partials(const StepGeom& g);
+hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const void* rows, int kt,
+                       int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
+                       unsigned long long* part, hipStream_t s);
 hipError_t launch_verify(const Cand* cand, uint32_t cap, const Counters* cnt, const void* x,
                          int dtype, int64_t n, int64_t ns, int D, int w, int d, const double* mu,
                          const double* isig, VRec* out, hipStream_t s);
-hipError_t launch_filter(const VRec* rec, uint32_t cap, const Counters* cnt,
-                         const PoolState* ps, const VRec* pools, int P, uint32_t* keep,
-                         Counters* cnt_out, hipStream_t s);
-hipError_t launch_pool(const VRec* rec, const uint32_t* keep, uint32_t cap, Counters* cnt,
-                       PoolState* ps, VRec* pools, int P, VRec* top, int k, int w, int j0, int B,
-                       Snap* snaps, VRec* snap_tops, hipStream_t s);
+// Replay `count` verified records (tagged with round and repetition) in step
+// order through the pool: filter, bucket by step, then one work-group walks
+// the steps of rc->[s0, s0 + nsteps) and writes a snapshot per step. rc must
+// hold K, L, s0, nsteps and zeroed counts; keep and order hold count entries.
+hipError_t launch_replay(const VRec* rec, uint32_t count, uint32_t* keep, uint32_t* order,
+                         ReplayCtl* rc, PoolState* ps, VRec* pools, int P, VRec* top, int k, int w,
+                         Snap* snaps, VRec* snap_tops, hipStream_t s);
 hipError_t launch_pool_reset(PoolState* ps, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_allpairs(int64_t ns, int w, int64_t row_lo, int64_t row_hi, int64_t base,

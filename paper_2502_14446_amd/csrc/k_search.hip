@@ -86,17 +86,23 @@ __device__ inline void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Prefix of length i of the tensored key: the first ceil(i/2) symbols of the
-// left word and the first floor(i/2) of the right word. The interleaved key
-// of section 6.1 has equal length-i prefixes exactly when both parts are
-// equal, which is all the traversal needs (no order between runs is used).
+// Prefix of length i of the tensored key of section 6.1: the symbols of the
+// left and right half-functions interleaved (l0 r0 l1 r1 ...), first symbol
+// most significant. The prefix of length i' < i is this value shifted right by
+// 8 (i - i') bits, so one sort by the longest prefix orders every shorter one.
+__device__ inline uint64_t spread_bytes(uint32_t v)
+{
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    return x;   // bytes b0 b1 b2 b3 (b0 most significant) -> 0 b0 0 b1 0 b2 0 b3
+}
+
 template <typename KT>
 __device__ inline KT make_key(uint32_t L, uint32_t R, int i)
 {
-    const int lb = (i + 1) >> 1, rb = i >> 1;
-    uint64_t v = (uint64_t)(L >> (32 - 8 * lb));
-    if (rb) v = (v << (8 * rb)) | (uint64_t)(R >> (32 - 8 * rb));
-    return (KT)v;
+    const uint64_t full = (spread_bytes(L) << 8) | spread_bytes(R);
+    return (KT)(full >> (8 * (8 - i)));
 }
 
 __device__ inline uint32_t top_mask(int nbytes)
@@ -314,84 +320,322 @@ hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& 
 }
 
 // ------------------------------------------------------------------ enumeration
-// Does pair (a, b), colliding at prefix i in dimension f, enter the step's
-// candidates? W_i over all dimensions must reach d, f must be the lowest
-// colliding dimension, and (when i < K) W_{i+1} must stay below d.
-__device__ inline bool pair_is_candidate(const uint32_t* __restrict__ H, const StepGeom& g, int f,
-                                         int l, int r, uint32_t a, uint32_t b, int d)
-{
-    const int i = g.i;
-    const uint32_t mL = top_mask((i + 1) >> 1), mR = top_mask(i >> 1);
-    const bool deeper = i < g.K;
-    const uint32_t mL1 = top_mask((i + 2) >> 1), mR1 = top_mask((i + 1) >> 1);
-    int Wi = 0, Wi1 = 0;
-    for (int fp = 0; fp < g.D; ++fp) {
-        const uint32_t* Lw = H + ((int64_t)fp * g.NF + l) * g.ns;
-        const uint32_t* Rw = H + ((int64_t)fp * g.NF + g.NL + r) * g.ns;
-        const uint32_t xl = Lw[a] ^ Lw[b];
-        const uint32_t xr = Rw[a] ^ Rw[b];
-        const bool eq = ((xl & mL) | (xr & mR)) == 0u;
-        if (fp < f && eq) return false;
-        Wi += eq;
-        if (deeper) {
-            const bool eq1 = ((xl & mL1) | (xr & mR1)) == 0u;
-            Wi1 += eq1;
-            if (Wi1 >= d) return false;
-        }
-        if (Wi + (g.D - 1 - fp) < d) return false;
-    }
-    return Wi >= d;
-}
-
-template <typename KT>
-__global__ __launch_bounds__(256) void k_enum(const KT* __restrict__ keys, const uint32_t* __restrict__ idx,
-                                              const uint32_t* __restrict__ H, StepGeom g, int d, int w,
-                                              Cand* __restrict__ cand, uint32_t cap,
-                                              Counters* __restrict__ cnt)
+// Key table of a batch: for every repetition of the batch and every window,
+// the length-kt prefix of every dimension, one contiguous row per window
+// ([jb][a][f]). kt = min(i_hi + 1, K) symbols: enough to tell, for every round
+// i of the group, whether a pair collides at i and at i + 1 in each dimension.
+template <typename RT>
+__global__ __launch_bounds__(256) void k_keytable(const uint32_t* __restrict__ H, StepGeom g, int reps,
+                                                  int kt, RT* __restrict__ rows)
 {
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t total = (int64_t)g.nseg * g.ns;
-    unsigned long long ncoll = 0;
-    if (gid < total) {
-        const int seg = (int)(gid / g.ns);
-        const int64_t t = gid - (int64_t)seg * g.ns;
+    if (gid >= (int64_t)reps * g.ns) return;
+    const int jb = (int)(gid / g.ns);
+    const int64_t a = gid - (int64_t)jb * g.ns;
+    const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
+    RT* row = rows + gid * g.D;
+    for (int f = 0; f < g.D; ++f) {
+        const uint32_t L = H[((int64_t)f * g.NF + l) * g.ns + a];
+        const uint32_t R = H[((int64_t)f * g.NF + g.NL + r) * g.ns + a];
+        row[f] = make_key<RT>(L, R, kt);
+    }
+}
+
+hipError_t launch_keytable(const uint32_t* H, const StepGeom& g, int reps, int kt, void* rows,
+                           hipStream_t s)
+{
+    const int64_t total = (int64_t)reps * g.ns;
+    dim3 grid((unsigned)((total + 255) / 256));
+    if (kt <= 4)
+        hipLaunchKernelGGL(k_keytable<uint32_t>, grid, dim3(256), 0, s, H, g, reps, kt, (uint32_t*)rows);
+    else
+        hipLaunchKernelGGL(k_keytable<uint64_t>, grid, dim3(256), 0, s, H, g, reps, kt, (uint64_t*)rows);
+    return hipGetLastError();
+}
+
+// Number of leading symbols two kt-symbol prefixes share.
+template <typename RT>
+__device__ inline int common_symbols(RT x, RT y, int kt)
+{
+    const uint64_t v = (uint64_t)(x ^ y);
+    if (v == 0) return kt;
+    return (__clzll(v) - (64 - 8 * kt)) >> 3;
+}
+
+// Enumeration, fused with run detection. Segments are sorted by their
+// length-g.i prefix; runs of the group's lowest round g.i_lo hold every deeper
+// round's runs. Each wavefront owns 64 consecutive elements of one segment:
+// ballots mark the heads of runs of length >= 2 that start there; a run's end
+// is the first tail after its head, or, for the one run that leaves the
+// window, found by the wave 64 keys at a time. The wave then enumerates the
+// pairs of each of its runs from a private LDS region: the run is cut into
+// tiles of TS members, and for every pair of tiles (P <= Q) the members'
+// window index, sort key and key-table row are staged. Lane u owns member u
+// of tile P (its row in registers) and walks its partners in tile Q; inside
+// one tile of n members the partners of u are u + 1 + v (mod n), v < n / 2,
+// which covers each unordered pair once (for even n the last v is kept for
+// u < n / 2 only).
+//
+// For a non-trivial pair: cp(f') = shared prefix symbols of the two rows in
+// dimension f', so the pair collides at round i in f' iff cp(f') >= i. It is
+// a candidate of step (i, j), for each round i of the group at which it
+// collides in the segment's dimension f, iff W_i = #{f' : cp >= i} >= d, no
+// f' < f has cp >= i (emitted once, from its lowest colliding dimension) and,
+// below round K, W_{i+1} < d (section 6.2: pairs seen one symbol deeper are
+// skipped). NLEV = rounds of the group + 1.
+constexpr int kRowRegs = 16;   // rows up to this many dimensions stay in registers
+
+template <typename RT, int NLEV>
+__device__ inline void count_levels(RT x, int kt, int i_lo, bool lower, int (&atleast)[NLEV],
+                                    int (&below)[NLEV])
+{
+    // x = xor of the two rows' entries: equal on the first s symbols iff its
+    // top 8 s bits (of kt symbols) are zero
+#pragma unroll
+    for (int lv = 0; lv < NLEV; ++lv) {
+        const int sym = i_lo + lv;
+        const bool eq = sym >= kt ? x == (RT)0 : (x >> (8 * (kt - sym))) == (RT)0;
+        atleast[lv] += eq;
+        below[lv] += eq && lower;
+    }
+}
+
+template <typename KT, typename RT, int NLEV>
+__global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
+                                                   const uint32_t* __restrict__ idx,
+                                                   const RT* __restrict__ rows, StepGeom g, int kt,
+                                                   int d, int w, int TS, Cand* __restrict__ cand,
+                                                   uint32_t cap, Counters* __restrict__ cnt,
+                                                   unsigned long long* __restrict__ coll_part)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ unsigned long long coll_sh[4], memb_sh[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const size_t region = (size_t)2 * TS * (8 + 4 + g.D * sizeof(RT));
+    unsigned char* mine_lds = smem_raw + (size_t)wave * region;
+    uint64_t* keyA = reinterpret_cast<uint64_t*>(mine_lds);
+    uint64_t* keyB = keyA + TS;
+    RT* rowA = reinterpret_cast<RT*>(keyB + TS);
+    RT* rowB = rowA + (size_t)TS * g.D;
+    uint32_t* idA = reinterpret_cast<uint32_t*>(rowB + (size_t)TS * g.D);
+    uint32_t* idB = idA + TS;
+
+    const int sh = 8 * (g.i - g.i_lo);
+    unsigned long long ncoll = 0, nmemb = 0;
+    const int64_t wins_per_seg = (g.ns + 63) / 64;
+    const int64_t total_wins = wins_per_seg * g.nseg;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    // persistent: each wavefront strides over the 64-element windows of all segments
+    for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < total_wins; win += nwaves) {
+        const int seg = (int)(win / wins_per_seg);
+        const int64_t base = (win - (int64_t)seg * wins_per_seg) * 64;
+        const int jb = seg / g.D, f = seg - jb * g.D;
+        const int j = g.j0 + jb;
         const KT* ks = keys + (int64_t)seg * g.ns;
         const uint32_t* is = idx + (int64_t)seg * g.ns;
-        const KT key = ks[t];
-        if (t + 1 < g.ns && ks[t + 1] == key) {
-            const int jb = seg / g.D, f = seg - jb * g.D;
-            const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
-            const uint32_t a = is[t];
-            for (int64_t q = t + 1; q < g.ns && ks[q] == key; ++q) {
-                const uint32_t b = is[q];
-                if (2 * (int64_t)(b - a) <= (int64_t)w) continue;   // trivial match
-                ++ncoll;
-                if (pair_is_candidate(H, g, f, l, r, a, b, d)) {
-                    const uint32_t pos = atomicAdd(&cnt->n_cand, 1u);
-                    if (pos < cap) cand[pos] = Cand{a, b, (uint32_t)j, 0u};
+        const RT* rbase = rows + (int64_t)jb * g.ns * g.D;
+
+        const int64_t t = base + lane;
+        const bool valid = t < g.ns;
+        const KT k = valid ? (KT)(ks[t] >> sh) : (KT)0;
+        const bool same_prev = valid && t > 0 && (KT)(ks[t - 1] >> sh) == k;
+        const bool same_next = valid && t + 1 < g.ns && (KT)(ks[t + 1] >> sh) == k;
+        const bool head = valid && !same_prev && same_next;
+        uint64_t heads = __ballot(head);
+        if (!heads) continue;
+        const uint64_t tails = __ballot(valid && !same_next);
+        const uint64_t after = lane == 63 ? 0ull : (tails & (~0ull << (lane + 1)));
+        int64_t my_end = -1;
+        if (head && after) my_end = base + __ffsll((unsigned long long)after);
+        const uint64_t open = __ballot(head && !after);
+        if (open) {
+            const int hl = __ffsll((unsigned long long)open) - 1;
+            const KT hk = __shfl(k, hl, 64);
+            int64_t pos = base + 64, found = -1;
+            while (found < 0) {
+                const int64_t e = pos + lane;
+                const bool stop = e >= g.ns || (KT)(ks[e < g.ns ? e : g.ns - 1] >> sh) != hk;
+                const uint64_t m = __ballot(stop);
+                if (m) found = pos + __ffsll((unsigned long long)m) - 1;
+                pos += 64;
+            }
+            if (lane == hl) my_end = found;
+        }
+        while (heads) {
+            const int hl = __ffsll((unsigned long long)heads) - 1;
+            heads &= heads - 1;
+            const int64_t start = base + hl;
+            const int len = (int)(__shfl(my_end, hl, 64) - start);
+            if (lane == 0) nmemb += (unsigned long long)len;
+            const int T = (len + TS - 1) / TS;
+            for (int tp = 0; tp < T; ++tp) {
+                for (int tq = tp; tq < T; ++tq) {
+                    const int nA = min(TS, len - tp * TS), nB = min(TS, len - tq * TS);
+                    const bool same = tp == tq;
+                    wave_sync_lds();
+                    for (int q = lane; q < nA; q += 64) {
+                        const uint32_t a = is[start + tp * TS + q];
+                        idA[q] = a;
+                        keyA[q] = (uint64_t)ks[start + tp * TS + q];
+                        for (int fp = 0; fp < g.D; ++fp) rowA[(size_t)q * g.D + fp] = rbase[(int64_t)a * g.D + fp];
+                    }
+                    if (!same)
+                        for (int q = lane; q < nB; q += 64) {
+                            const uint32_t b = is[start + tq * TS + q];
+                            idB[q] = b;
+                            keyB[q] = (uint64_t)ks[start + tq * TS + q];
+                            for (int fp = 0; fp < g.D; ++fp) rowB[(size_t)q * g.D + fp] = rbase[(int64_t)b * g.D + fp];
+                        }
+                    wave_sync_lds();
+                    const uint64_t* kQ = same ? keyA : keyB;
+                    const RT* rQ = same ? rowA : rowB;
+                    const uint32_t* iQ = same ? idA : idB;
+                    const int nq = same ? nA / 2 : nB;
+                    for (int u = lane; u < nA; u += 64) {
+                        const uint32_t xu = idA[u];
+                        const uint64_t ku = keyA[u];
+                        RT own[kRowRegs];
+                        const RT* ra = rowA + (size_t)u * g.D;
+#pragma unroll
+                        for (int fp = 0; fp < kRowRegs; ++fp) own[fp] = fp < g.D ? ra[fp] : (RT)0;
+                        for (int v = 0; v < nq; ++v) {
+                            int qq = v;
+                            if (same) {
+                                if ((nA & 1) == 0 && v == nq - 1 && u >= nA / 2) continue;
+                                qq = u + 1 + v;
+                                if (qq >= nA) qq -= nA;
+                            }
+                            const uint32_t y = iQ[qq];
+                            const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
+                            if (2 * (int64_t)(b - a) <= (int64_t)w) continue;   // trivial match
+                            ++ncoll;
+                            int atleast[NLEV], below[NLEV];
+#pragma unroll
+                            for (int v2 = 0; v2 < NLEV; ++v2) { atleast[v2] = 0; below[v2] = 0; }
+                            const RT* rb = rQ + (size_t)qq * g.D;
+#pragma unroll
+                            for (int fp = 0; fp < kRowRegs; ++fp)
+                                if (fp < g.D) count_levels<RT, NLEV>(own[fp] ^ rb[fp], kt, g.i_lo, fp < f, atleast, below);
+                            for (int fp = kRowRegs; fp < g.D; ++fp)
+                                count_levels<RT, NLEV>(ra[fp] ^ rb[fp], kt, g.i_lo, fp < f, atleast, below);
+                            if (atleast[0] < d) continue;   // not even at the group's lowest round
+                            const int top = common_symbols<uint64_t>(ku, kQ[qq], g.i);
+#pragma unroll
+                            for (int lv = NLEV - 2; lv >= 0; --lv) {
+                                const int i = g.i_lo + lv;
+                                if (i > top) continue;                    // rounds i_lo .. top
+                                if (atleast[lv] < d || below[lv] > 0) continue;
+                                if (i < g.K && atleast[lv + 1] >= d) continue;
+                                const uint32_t pos = atomicAdd(&cnt->n_cand, 1u);
+                                if (pos < cap) cand[pos] = Cand{a, b, (uint32_t)j, (uint32_t)i};
+                            }
+                        }
+                    }
                 }
             }
         }
     }
-    // one atomic per wave for the collision counter
-    unsigned long long tot = ncoll;
+    // collisions and run members: one pair of partial sums per work-group, no atomics
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
-    if (lane_id() == 0 && tot) atomicAdd(&cnt->n_coll, tot);
+    for (int o = 32; o >= 1; o >>= 1) ncoll += __shfl_xor(ncoll, o, 64);
+    if (lane == 0) {
+        coll_sh[wave] = ncoll;
+        memb_sh[wave] = nmemb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t b = blockIdx.x;
+        coll_part[2 * b] = coll_sh[0] + coll_sh[1] + coll_sh[2] + coll_sh[3];
+        coll_part[2 * b + 1] = memb_sh[0] + memb_sh[1] + memb_sh[2] + memb_sh[3];
+    }
 }
 
-hipError_t launch_enum(const StepGeom& g, const uint32_t* H, const SortBufs& b, int buf, int d,
-                       int w, Cand* cand, uint32_t cap, Counters* cnt, hipStream_t s)
+__global__ __launch_bounds__(1024) void k_sum_partials(const unsigned long long* __restrict__ part,
+                                                       int64_t count, Counters* __restrict__ cnt)
 {
-    const int64_t total = (int64_t)g.nseg * g.ns;
-    dim3 grid((unsigned)((total + 255) / 256));
-    if (g.i <= 4)
-        hipLaunchKernelGGL(k_enum<uint32_t>, grid, dim3(256), 0, s, (const uint32_t*)b.keys[buf],
-                           b.idx[buf], H, g, d, w, cand, cap, cnt);
-    else
-        hipLaunchKernelGGL(k_enum<uint64_t>, grid, dim3(256), 0, s, (const uint64_t*)b.keys[buf],
-                           b.idx[buf], H, g, d, w, cand, cap, cnt);
+    __shared__ unsigned long long sh[32];
+    unsigned long long s = 0, m = 0;
+    for (int64_t q = threadIdx.x; q < count; q += 1024) {
+        s += part[2 * q];
+        m += part[2 * q + 1];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        m += __shfl_xor(m, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = s;
+        sh[16 + (threadIdx.x >> 6)] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0, u = 0;
+        for (int q = 0; q < 16; ++q) {
+            t += sh[q];
+            u += sh[16 + q];
+        }
+        cnt->n_coll += t;
+        cnt->n_memb += u;
+    }
+}
+
+// Members per tile: a wave's two tiles take at most ~6 KB of LDS when rows
+// are narrow, so that many work-groups stay resident.
+static int tile_size(int D, int rb)
+{
+    int ts = 12288 / (2 * (12 + D * rb));   // per wave
+    ts = ts > 64 ? 64 : ts;
+    return ts < 16 ? 16 : (ts / 16) * 16;
+}
+
+constexpr int kEnumBlocks = 2048;   // persistent grid: 8 work-groups per CU
+int64_t enum_partials(const StepGeom&) { return kEnumBlocks; }
+
+template <typename KT, typename RT, int NLEV>
+static hipError_t go_enum(const StepGeom& g, const KT* keys, const uint32_t* idx, const RT* rows,
+                          int kt, int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
+                          unsigned long long* part, hipStream_t s)
+{
+    const int TS = tile_size(g.D, (int)sizeof(RT));
+    const size_t lds = (size_t)4 * 2 * TS * (8 + 4 + g.D * sizeof(RT));   // 4 waves
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_enum_runs<KT, RT, NLEV>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_enum_runs<KT, RT, NLEV>), dim3(kEnumBlocks), dim3(256), lds, s, keys, idx, rows,
+                       g, kt, d, w, TS, cand, cap, cnt, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, enum_partials(g), cnt);
     return hipGetLastError();
+}
+
+template <typename KT, typename RT>
+static hipError_t go_enum_lev(const StepGeom& g, const KT* keys, const uint32_t* idx, const RT* rows,
+                              int kt, int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
+                              unsigned long long* part, hipStream_t s)
+{
+    switch (g.i - g.i_lo + 2) {
+    case 2: return go_enum<KT, RT, 2>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
+    case 3: return go_enum<KT, RT, 3>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
+    case 4: return go_enum<KT, RT, 4>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
+    case 5: return go_enum<KT, RT, 5>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
+    default: return go_enum<KT, RT, 9>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
+    }
+}
+
+hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const void* rows, int kt,
+                       int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
+                       unsigned long long* part, hipStream_t s)
+{
+    if (g.i <= 4) {
+        const uint32_t* k = (const uint32_t*)b.keys[buf];
+        if (kt <= 4)
+            return go_enum_lev<uint32_t, uint32_t>(g, k, b.idx[buf], (const uint32_t*)rows, kt, d, w,
+                                                   cand, cap, cnt, part, s);
+        return go_enum_lev<uint32_t, uint64_t>(g, k, b.idx[buf], (const uint64_t*)rows, kt, d, w, cand,
+                                               cap, cnt, part, s);
+    }
+    return go_enum_lev<uint64_t, uint64_t>(g, (const uint64_t*)b.keys[buf], b.idx[buf],
+                                           (const uint64_t*)rows, kt, d, w, cand, cap, cnt, part, s);
 }
 
 // ------------------------------------------------------------------ verification
@@ -449,7 +693,7 @@ __global__ __launch_bounds__(256) void k_verify(const Cand* __restrict__ cand, u
             v.a = cd.a;
             v.b = cd.b;
             v.j = cd.j;
-            v.pad = 0;
+            v.pad = cd.pad;
             v.dims[0] = m0;
             v.dims[1] = m1;
             out[c] = v;
@@ -480,100 +724,110 @@ __device__ inline bool key_less(double da, uint32_t aa, uint32_t ab, double db, 
     return ab < bb;
 }
 
-__global__ __launch_bounds__(256) void k_filter(const VRec* __restrict__ rec, uint32_t cap,
-                                                const Counters* __restrict__ cnt_in,
+// Step of a verified record inside a replay window starting at step s0:
+// step = (K - i) L + j (rounds descending, repetitions ascending).
+__device__ inline int rec_step(const VRec& r, int K, int L, int s0)
+{
+    return (K - (int)r.pad) * L + (int)r.j - s0;
+}
+
+// Keep the records that can still enter the pool: all of them while it is
+// not full, else those strictly better than its current worst entry.
+__global__ __launch_bounds__(256) void k_filter(const VRec* __restrict__ rec, uint32_t count,
                                                 const PoolState* __restrict__ ps,
                                                 const VRec* __restrict__ pools, int P,
-                                                uint32_t* __restrict__ keep, Counters* cnt_out)
+                                                uint32_t* __restrict__ keep, ReplayCtl* __restrict__ rc)
 {
-    const uint32_t nc = cnt_in->n_cand;
-    if (nc > cap) return;
     const bool full = ps->n_pool >= P;
     VRec thr;
     if (full) thr = pools[(int64_t)ps->cur * P + P - 1];
-    for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c < nc; c += gridDim.x * 256) {
+    for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c < count; c += gridDim.x * 256) {
         const VRec& r = rec[c];
+        const int st = rec_step(r, rc->K, rc->L, rc->s0);
+        if (st < 0 || st >= rc->nsteps) continue;   // not a step of this window
         if (!full || key_less(r.dist_d, r.a, r.b, thr.dist_d, thr.a, thr.b)) {
-            const uint32_t pos = atomicAdd(&cnt_out->n_keep, 1u);
+            const uint32_t pos = atomicAdd(&rc->n_keep, 1u);
             keep[pos] = c;
+            atomicAdd(&rc->step_count[st], 1u);
         }
     }
 }
 
-hipError_t launch_filter(const VRec* rec, uint32_t cap, const Counters* cnt, const PoolState* ps,
-                         const VRec* pools, int P, uint32_t* keep, Counters* cnt_out, hipStream_t s)
+// Exclusive scan of the per-step counts (one block): offsets and cursors.
+__global__ __launch_bounds__(1024) void k_step_scan(ReplayCtl* __restrict__ rc)
 {
-    hipLaunchKernelGGL(k_filter, dim3(1024), dim3(256), 0, s, rec, cap, cnt, ps, pools, P, keep, cnt_out);
-    return hipGetLastError();
+    __shared__ uint32_t sh[16];
+    const int nsteps = rc->nsteps;
+    const int per = (nsteps + 1023) / 1024;
+    const int lo = threadIdx.x * per;
+    const int hi = lo + per < nsteps ? lo + per : nsteps;
+    uint32_t s = 0;
+    for (int q = lo; q < hi; ++q) s += rc->step_count[q];
+    uint32_t tot;
+    uint32_t run = block_excl_scan<1024>(s, sh, &tot);
+    for (int q = lo; q < hi; ++q) {
+        const uint32_t v = rc->step_count[q];
+        rc->step_off[q] = run;
+        rc->step_count[q] = run;   // becomes the scatter cursor
+        run += v;
+    }
+    if (threadIdx.x == 0) rc->step_off[nsteps] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_step_scatter(const VRec* __restrict__ rec,
+                                                      const uint32_t* __restrict__ keep,
+                                                      uint32_t* __restrict__ order,
+                                                      ReplayCtl* __restrict__ rc)
+{
+    const uint32_t nk = rc->n_keep;
+    for (uint32_t q = blockIdx.x * 256 + threadIdx.x; q < nk; q += gridDim.x * 256) {
+        const uint32_t c = keep[q];
+        const uint32_t pos = atomicAdd(&rc->step_count[rec_step(rec[c], rc->K, rc->L, rc->s0)], 1u);
+        order[pos] = c;
+    }
 }
 
 constexpr int kPoolThreads = 1024;
 constexpr int kChunk = 1024;
-constexpr int kMaxBatch = 64;
 
-// Single work-group: for each repetition of the batch in order, merge its
-// kept candidates into the pool (sorted by (dist_d, a, b), duplicates
+// Single work-group: for each step of the replay window in order, merge the
+// step's kept records into the pool (sorted by (dist_d, a, b), duplicates
 // dropped, best P kept), recompute TOP greedily when it can change, and
-// record a snapshot.
+// record a snapshot of |TOP|, the k-th dist_max and TOP itself.
 __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ rec,
-                                                       const uint32_t* __restrict__ keep,
-                                                       uint32_t* __restrict__ order, uint32_t cap,
-                                                       Counters* __restrict__ cnt,
+                                                       const uint32_t* __restrict__ order,
+                                                       const ReplayCtl* __restrict__ rc,
                                                        PoolState* __restrict__ ps,
                                                        VRec* __restrict__ pools, int P,
-                                                       VRec* __restrict__ top, int k, int w, int j0,
-                                                       int B, Snap* __restrict__ snaps,
+                                                       VRec* __restrict__ top, int k, int w,
+                                                       Snap* __restrict__ snaps,
                                                        VRec* __restrict__ snap_tops)
 {
-    __shared__ uint32_t jcount[kMaxBatch + 1];
-    __shared__ uint32_t joff[kMaxBatch + 1];
     __shared__ double cd[kChunk];
     __shared__ uint32_t ca[kChunk], cb[kChunk], ci[kChunk];
+    __shared__ uint32_t ka[kChunk], kb2[kChunk], kidx[kChunk];
+    __shared__ double kd[kChunk];
+    __shared__ int klb[kChunk];
     __shared__ uint32_t scan_sh[kPoolThreads / 64];
     __shared__ int acc_list[4096];
-    __shared__ int s_np, s_cur, s_trunc, s_topn, s_improved, s_cn;
+    __shared__ int s_np, s_cur, s_trunc, s_topn, s_improved;
 
     const int tid = threadIdx.x;
-    if (cnt->n_cand > cap) {
-        if (tid == 0) ps->skipped = 1;
-        return;
-    }
-    const uint32_t nkeep = cnt->n_keep;
+    const int nsteps = rc->nsteps;
     if (tid == 0) {
         s_np = ps->n_pool;
         s_cur = ps->cur;
         s_trunc = ps->truncated;
         s_topn = ps->top_n;
-        ps->skipped = 0;
-    }
-    if (tid <= kMaxBatch) jcount[tid] = 0;
-    __syncthreads();
-    // bucket the kept candidates by repetition
-    for (uint32_t q = tid; q < nkeep; q += kPoolThreads) atomicAdd(&jcount[rec[keep[q]].j - j0], 1u);
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t s = 0;
-        for (int b = 0; b < B; ++b) {
-            joff[b] = s;
-            s += jcount[b];
-            jcount[b] = joff[b];
-        }
-        joff[B] = s;
-    }
-    __syncthreads();
-    for (uint32_t q = tid; q < nkeep; q += kPoolThreads) {
-        const uint32_t c = keep[q];
-        const uint32_t pos = atomicAdd(&jcount[rec[c].j - j0], 1u);
-        order[pos] = c;
     }
     __syncthreads();
 
-    for (int jb = 0; jb < B; ++jb) {
+    for (int st = 0; st < nsteps; ++st) {
+        const uint32_t beg = rc->step_off[st], end = rc->step_off[st + 1];
         if (tid == 0) s_improved = 0;
         __syncthreads();
-        for (uint32_t start = joff[jb]; start < joff[jb + 1]; start += kChunk) {
-            const uint32_t cnum = min((uint32_t)kChunk, joff[jb + 1] - start);
-            // load the chunk, pad with +inf
+        for (uint32_t start = beg; start < end; start += kChunk) {
+            const uint32_t cnum = min((uint32_t)kChunk, end - start);
             if ((uint32_t)tid < cnum) {
                 const VRec& r = rec[order[start + tid]];
                 cd[tid] = r.dist_d;
@@ -607,26 +861,23 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ 
             const int np = s_np;
             const VRec* pool = pools + (int64_t)s_cur * P;
             VRec* npool = pools + (int64_t)(s_cur ^ 1) * P;
-            // drop chunk entries already in the pool
+            // drop chunk entries already in the pool (a pair always has the same key)
             uint32_t keepme = 0;
             int lb_pool = 0;
             if ((uint32_t)tid < cnum) {
                 int lo = 0, hi = np;
                 while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
+                    const int mid = (lo + hi) >> 1;
                     const VRec& pm = pool[mid];
                     if (key_less(pm.dist_d, pm.a, pm.b, cd[tid], ca[tid], cb[tid])) lo = mid + 1; else hi = mid;
                 }
                 lb_pool = lo;
                 const bool dup = lo < np && pool[lo].a == ca[tid] && pool[lo].b == cb[tid];
-                keepme = dup ? 0u : 1u;
+                const bool dup_in_chunk = tid > 0 && ca[tid - 1] == ca[tid] && cb[tid - 1] == cb[tid];
+                keepme = (dup || dup_in_chunk) ? 0u : 1u;
             }
             uint32_t ctot;
             const uint32_t cpos = block_excl_scan<kPoolThreads>(keepme, scan_sh, &ctot);
-            // compact kept chunk entries (their pool lower bounds travel along)
-            __shared__ uint32_t ka[kChunk], kb2[kChunk], kidx[kChunk];
-            __shared__ double kd[kChunk];
-            __shared__ int klb[kChunk];
             if (keepme) {
                 kd[cpos] = cd[tid];
                 ka[cpos] = ca[tid];
@@ -640,7 +891,7 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ 
                 const VRec& pe = pool[p];
                 int lo = 0, hi = (int)ctot;
                 while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
+                    const int mid = (lo + hi) >> 1;
                     if (key_less(kd[mid], ka[mid], kb2[mid], pe.dist_d, pe.a, pe.b)) lo = mid + 1; else hi = mid;
                 }
                 const int pos = p + lo;
@@ -648,10 +899,7 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ 
             }
             if ((uint32_t)tid < ctot) {
                 const int pos = tid + klb[tid];
-                if (pos < P) {
-                    VRec v = rec[kidx[tid]];
-                    npool[pos] = v;
-                }
+                if (pos < P) npool[pos] = rec[kidx[tid]];
             }
             __syncthreads();
             if (tid == 0) {
@@ -676,15 +924,14 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ 
             const int np = s_np;
             int got = 0;
             for (int e = 0; e < np && got < k; ++e) {
-                const uint32_t ea = pool[e].a, eb = pool[e].b;
+                const int64_t ea = pool[e].a, eb = pool[e].b;
                 bool clash = false;
-                for (int s = tid; s < got; s += 64) {
-                    const VRec& t = pool[acc_list[s]];
-                    const int64_t h = w;
-                    clash |= 2 * llabs((int64_t)ea - (int64_t)t.a) <= h;
-                    clash |= 2 * llabs((int64_t)ea - (int64_t)t.b) <= h;
-                    clash |= 2 * llabs((int64_t)eb - (int64_t)t.a) <= h;
-                    clash |= 2 * llabs((int64_t)eb - (int64_t)t.b) <= h;
+                for (int q = tid; q < got; q += 64) {
+                    const VRec& t = pool[acc_list[q]];
+                    clash |= 2 * llabs(ea - (int64_t)t.a) <= (int64_t)w;
+                    clash |= 2 * llabs(ea - (int64_t)t.b) <= (int64_t)w;
+                    clash |= 2 * llabs(eb - (int64_t)t.a) <= (int64_t)w;
+                    clash |= 2 * llabs(eb - (int64_t)t.b) <= (int64_t)w;
                 }
                 if (__ballot(clash) == 0) {
                     if (tid == 0) acc_list[got] = e;
@@ -693,19 +940,18 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ 
                 }
             }
             wave_sync_lds();
-            for (int s = tid; s < got; s += 64) top[s] = pool[acc_list[s]];
+            for (int q = tid; q < got; q += 64) top[q] = pool[acc_list[q]];
             if (tid == 0) s_topn = got;
         }
         __syncthreads();
-        __threadfence_block();
         if (tid == 0) {
             Snap sn;
             sn.top_n = s_topn;
             sn.truncated = s_trunc;
             sn.dist_max = s_topn == k ? top[k - 1].dist_max : 0.0;
-            snaps[jb] = sn;
+            snaps[st] = sn;
         }
-        for (int s = tid; s < s_topn; s += kPoolThreads) snap_tops[(int64_t)jb * k + s] = top[s];
+        for (int q = tid; q < s_topn; q += kPoolThreads) snap_tops[(int64_t)st * k + q] = top[q];
         __syncthreads();
     }
     if (tid == 0) {
@@ -716,15 +962,17 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ 
     }
 }
 
-hipError_t launch_pool(const VRec* rec, const uint32_t* keep, uint32_t cap, Counters* cnt,
-                       PoolState* ps, VRec* pools, int P, VRec* top, int k, int w, int j0, int B,
-                       Snap* snaps, VRec* snap_tops, hipStream_t s)
+hipError_t launch_replay(const VRec* rec, uint32_t count, uint32_t* keep, uint32_t* order,
+                         ReplayCtl* rc, PoolState* ps, VRec* pools, int P, VRec* top, int k, int w,
+                         Snap* snaps, VRec* snap_tops, hipStream_t s)
 {
-    if (B > kMaxBatch || k > 4096) return hipErrorInvalidValue;
-    // the order scratch lives right after the keep list (same capacity)
-    uint32_t* order = const_cast<uint32_t*>(keep) + cap;
-    hipLaunchKernelGGL(k_pool, dim3(1), dim3(kPoolThreads), 0, s, rec, keep, order, cap, cnt, ps,
-                       pools, P, top, k, w, j0, B, snaps, snap_tops);
+    if (k > 4096) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)(count == 0 ? 1 : (count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024);
+    hipLaunchKernelGGL(k_filter, dim3(blocks), dim3(256), 0, s, rec, count, ps, pools, P, keep, rc);
+    hipLaunchKernelGGL(k_step_scan, dim3(1), dim3(1024), 0, s, rc);
+    hipLaunchKernelGGL(k_step_scatter, dim3(blocks), dim3(256), 0, s, rec, keep, order, rc);
+    hipLaunchKernelGGL(k_pool, dim3(1), dim3(kPoolThreads), 0, s, rec, order, rc, ps, pools, P, top,
+                       k, w, snaps, snap_tops);
     return hipGetLastError();
 }
 
@@ -777,7 +1025,7 @@ __global__ void k_allpairs(int64_t ns, int w, int64_t row_lo, int64_t row_hi, in
 __global__ void k_set_count(Counters* cnt, uint32_t v)
 {
     cnt->n_cand = v;
-    cnt->n_keep = 0;
+    cnt->n_runs = 0;
 }
 
 hipError_t launch_allpairs(int64_t ns, int w, int64_t row_lo, int64_t row_hi, int64_t base,

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -148,11 +149,11 @@ static uint8_t to_e4m3_bits(double v)
 // ------------------------------------------------------------------ profiling
 // Optional per-kernel timing with HIP events recorded on the plan's stream
 // around each launch; folded into totals whenever the host synchronises.
-enum KernelId { KI_STATS, KI_RSAMPLE, KI_PROJ, KI_HIST, KI_SCAN, KI_SCATTER, KI_ENUM, KI_VERIFY,
-                KI_FILTER, KI_POOL, KI_ALLPAIRS, KI_COUNT };
+enum KernelId { KI_STATS, KI_RSAMPLE, KI_PROJ, KI_HIST, KI_SCAN, KI_SCATTER, KI_KEYTABLE, KI_ENUM,
+                KI_VERIFY, KI_FILTER, KI_POOL, KI_ALLPAIRS, KI_COUNT };
 static const char* const kKernelNames[KI_COUNT] = {
-    "stats", "rsample", "proj", "sort_hist", "sort_scan", "sort_scatter", "enum", "verify",
-    "pool_filter", "pool", "allpairs"};
+    "stats", "rsample", "proj", "sort_hist", "sort_scan", "sort_scatter", "keytable", "enum",
+    "verify", "pool_filter", "pool", "allpairs"};
 
 struct KTotal {
     int64_t launches = 0;
@@ -195,18 +196,26 @@ struct momenti_plan {
     // traversal buffers
     SortBufs sb{};
     int sb_nseg = 0;
-    Cand* cand = nullptr;
-    VRec* vrec = nullptr;
-    uint32_t* keep = nullptr;   // 2 * cap (keep list + per-repetition order)
+    void* rows = nullptr;       // key table of a batch: [rep][window][dim], up to 8 B each
+    unsigned long long* coll_part = nullptr;   // per-work-group collision counts
+    int64_t coll_parts = 0;
+    Cand* cand = nullptr;       // candidates of one launch batch
+    VRec* vrec = nullptr;       // their verified records
     uint32_t cap = 0;
+    VRec* store = nullptr;      // verified records of the current round group
+    uint32_t* keep = nullptr;   // 2 * store_cap: kept indices, then step order
+    uint32_t store_cap = 0;
     VRec* pools = nullptr;
     int P = 0;
     VRec* top = nullptr;
     int top_k = 0;
-    unsigned char* status = nullptr;   // Counters | PoolState | Snap[kMaxBatch]
-    VRec* snap_tops = nullptr;
-    int snap_B = 0, snap_k = 0;
+    unsigned char* status = nullptr;   // Counters | PoolState
+    ReplayCtl* rctl = nullptr;
+    Snap* snaps = nullptr;             // one per step of a round group
+    VRec* snap_tops = nullptr;         // k per step
+    int snap_steps = 0, snap_k = 0;
     unsigned char* host_status = nullptr;
+    Snap* host_snaps = nullptr;
 
     uint64_t bytes = 0, peak = 0;
     Profiler prof;
@@ -357,21 +366,32 @@ static void release_search(momenti_plan* p)
     }
     dfree(p, p->sb.hist, (size_t)p->sb_nseg * 256 * p->sb.tiles * 4);
     p->sb.hist = nullptr;
+    dfree(p, p->rows, (size_t)p->sb_nseg * p->ns * 8);
+    p->rows = nullptr;
     p->sb_nseg = 0;
     dfree(p, p->cand, (size_t)p->cap * sizeof(Cand));
     dfree(p, p->vrec, (size_t)p->cap * sizeof(VRec));
-    dfree(p, p->keep, (size_t)p->cap * 8);
-    p->cand = nullptr; p->vrec = nullptr; p->keep = nullptr; p->cap = 0;
+    p->cand = nullptr; p->vrec = nullptr; p->cap = 0;
+    dfree(p, p->coll_part, (size_t)p->coll_parts * 16);
+    p->coll_part = nullptr; p->coll_parts = 0;
+    dfree(p, p->store, (size_t)p->store_cap * sizeof(VRec));
+    dfree(p, p->keep, (size_t)p->store_cap * 8);
+    p->store = nullptr; p->keep = nullptr; p->store_cap = 0;
     dfree(p, p->pools, (size_t)2 * p->P * sizeof(VRec));
     p->pools = nullptr; p->P = 0;
     dfree(p, p->top, (size_t)p->top_k * sizeof(VRec));
     p->top = nullptr; p->top_k = 0;
     dfree(p, p->status, 4096);
     p->status = nullptr;
-    dfree(p, p->snap_tops, (size_t)p->snap_B * p->snap_k * sizeof(VRec));
-    p->snap_tops = nullptr; p->snap_B = 0; p->snap_k = 0;
+    dfree(p, p->rctl, sizeof(ReplayCtl));
+    p->rctl = nullptr;
+    dfree(p, p->snaps, (size_t)p->snap_steps * sizeof(Snap));
+    dfree(p, p->snap_tops, (size_t)p->snap_steps * p->snap_k * sizeof(VRec));
+    p->snaps = nullptr; p->snap_tops = nullptr; p->snap_steps = 0; p->snap_k = 0;
     if (p->host_status) (void)hipHostFree(p->host_status);
     p->host_status = nullptr;
+    if (p->host_snaps) (void)hipHostFree(p->host_snaps);
+    p->host_snaps = nullptr;
 }
 
 // ------------------------------------------------------------------ ABI
@@ -425,7 +445,8 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
     if (o.L < 1 || o.L > 1024) return fail(MOMENTI_E_ARG, "L=%d outside [1, 1024]", o.L);
     if (o.proj < MOMENTI_PROJ_F64 || o.proj > MOMENTI_PROJ_FP8)
         return fail(MOMENTI_E_ARG, "projection precision %d not available", o.proj);
-    if (o.stop_rule != MOMENTI_STOP_TENSOR && o.stop_rule != MOMENTI_STOP_LEMMA52)
+    if (o.stop_rule != MOMENTI_STOP_TENSOR && o.stop_rule != MOMENTI_STOP_LEMMA52 &&
+        o.stop_rule != MOMENTI_STOP_TENSOR_LITERAL)
         return fail(MOMENTI_E_ARG, "bad stop rule %d", o.stop_rule);
     if (o.pool_size < 0 || o.batch_reps < 0) return fail(MOMENTI_E_ARG, "negative pool/batch size");
 
@@ -697,10 +718,13 @@ static double collision_probability(double R, double r)
     return std::erf(t / std::sqrt(2.0)) + 2.0 / (std::sqrt(2.0 * M_PI) * t) * std::expm1(-0.5 * t * t);
 }
 
-// log of (1 - p^c)^e, with x^0 = 1 (also for x = 0).
-static double log_term(double logp, int c, int64_t e)
+// log of (1 - p^c)^e, with x^0 = 1 (also for x = 0). Under the TENSOR rule a
+// half that contributes no symbol (c = 0, round 1) gives no collision chance
+// of its own and the factor 1; printed literally it is (1 - p^0)^e = 0.
+static double log_term(double logp, int c, int64_t e, bool empty_half_is_one = false)
 {
     if (e == 0) return 0.0;
+    if (c == 0 && empty_half_is_one) return 0.0;
     const double pc = std::exp((double)c * logp);   // p^c (p^0 = 1)
     if (pc >= 1.0) return -INFINITY;
     return (double)e * std::log1p(-pc);
@@ -719,10 +743,11 @@ static bool stop_holds(double dist_max, double r, int d, int i, int J, int K, in
         lf = log_term(logp, i, J);
         if (i < K) lf += log_term(logp, i + 1, L - J);
     } else {
-        lf = log_term(logp, (i + 1) / 2, J / m) + log_term(logp, i / 2, J % m);
+        const bool e1 = rule == MOMENTI_STOP_TENSOR;
+        lf = log_term(logp, (i + 1) / 2, J / m, e1) + log_term(logp, i / 2, J % m, e1);
         if (i < K) {
             const int J2 = L - J;
-            lf += log_term(logp, (i + 2) / 2, J2 / m) + log_term(logp, (i + 1) / 2, J2 % m);
+            lf += log_term(logp, (i + 2) / 2, J2 / m, e1) + log_term(logp, (i + 1) / 2, J2 % m, e1);
         }
     }
     return lf <= std::log(delta);
@@ -731,14 +756,14 @@ static bool stop_holds(double dist_max, double r, int d, int i, int J, int K, in
 // ------------------------------------------------------------------ search
 static Counters* st_counters(momenti_plan* p) { return (Counters*)p->status; }
 static PoolState* st_pool(momenti_plan* p) { return (PoolState*)(p->status + 64); }
-static Snap* st_snaps(momenti_plan* p) { return (Snap*)(p->status + 128); }
-static constexpr size_t kStatusBytes = 128 + 64 * sizeof(Snap);
 
+// double-buffered keys and indices, digit histograms, and the key table
 static size_t sort_bytes(int64_t nseg, int64_t ns, int64_t tiles)
 {
-    return (size_t)nseg * ns * (8 + 8 + 4 + 4) + (size_t)nseg * 256 * tiles * 4;
+    return (size_t)nseg * ns * (8 + 8 + 4 + 4 + 8) + (size_t)nseg * 256 * tiles * 4;
 }
-static size_t cand_bytes(uint32_t cap) { return (size_t)cap * (sizeof(Cand) + sizeof(VRec) + 8); }
+static size_t cand_bytes(uint32_t cap) { return (size_t)cap * (sizeof(Cand) + sizeof(VRec)); }
+static size_t store_bytes(uint32_t cap) { return (size_t)cap * (sizeof(VRec) + 8); }
 
 static int alloc_sort(momenti_plan* p, int nseg)
 {
@@ -750,6 +775,7 @@ static int alloc_sort(momenti_plan* p, int nseg)
         if ((rc = dalloc_t(p, &p->sb.idx[q], (size_t)nseg * p->ns * 4))) return rc;
     }
     if ((rc = dalloc_t(p, &p->sb.hist, (size_t)nseg * 256 * tiles * 4))) return rc;
+    if ((rc = dalloc(p, &p->rows, (size_t)nseg * p->ns * 8))) return rc;
     p->sb_nseg = nseg;
     return MOMENTI_OK;
 }
@@ -758,61 +784,79 @@ static int alloc_cand(momenti_plan* p, uint32_t cap)
 {
     dfree(p, p->cand, (size_t)p->cap * sizeof(Cand));
     dfree(p, p->vrec, (size_t)p->cap * sizeof(VRec));
-    dfree(p, p->keep, (size_t)p->cap * 8);
-    p->cand = nullptr; p->vrec = nullptr; p->keep = nullptr; p->cap = 0;
+    p->cand = nullptr; p->vrec = nullptr; p->cap = 0;
     int rc;
     if ((rc = dalloc_t(p, &p->cand, (size_t)cap * sizeof(Cand)))) return rc;
     if ((rc = dalloc_t(p, &p->vrec, (size_t)cap * sizeof(VRec)))) return rc;
-    if ((rc = dalloc_t(p, &p->keep, (size_t)cap * 8))) return rc;
     p->cap = cap;
     return MOMENTI_OK;
 }
 
-static int alloc_pool(momenti_plan* p, int P, int k, int B)
+// Grow the group store to hold at least `need` records, keeping `used` of them.
+static int grow_store(momenti_plan* p, uint32_t need, uint32_t used)
+{
+    if (need <= p->store_cap) return MOMENTI_OK;
+    uint32_t cap = std::max<uint32_t>(p->store_cap, 1u << 16);
+    while (cap < need) cap = cap >= (1u << 31) ? need : cap * 2;
+    VRec* ns = nullptr;
+    uint32_t* nk = nullptr;
+    int rc;
+    if ((rc = dalloc_t(p, &ns, (size_t)cap * sizeof(VRec)))) return rc;
+    if ((rc = dalloc_t(p, &nk, (size_t)cap * 8))) {
+        dfree(p, ns, (size_t)cap * sizeof(VRec));
+        return rc;
+    }
+    if (used) HIP_OK(hipMemcpyAsync(ns, p->store, (size_t)used * sizeof(VRec), hipMemcpyDeviceToDevice, p->st));
+    HIP_OK(hipStreamSynchronize(p->st));
+    dfree(p, p->store, (size_t)p->store_cap * sizeof(VRec));
+    dfree(p, p->keep, (size_t)p->store_cap * 8);
+    p->store = ns;
+    p->keep = nk;
+    p->store_cap = cap;
+    return MOMENTI_OK;
+}
+
+static int alloc_pool(momenti_plan* p, int P, int k, int steps)
 {
     dfree(p, p->pools, (size_t)2 * p->P * sizeof(VRec));
     dfree(p, p->top, (size_t)p->top_k * sizeof(VRec));
-    dfree(p, p->snap_tops, (size_t)p->snap_B * p->snap_k * sizeof(VRec));
-    p->pools = nullptr; p->top = nullptr; p->snap_tops = nullptr;
+    dfree(p, p->snaps, (size_t)p->snap_steps * sizeof(Snap));
+    dfree(p, p->snap_tops, (size_t)p->snap_steps * p->snap_k * sizeof(VRec));
+    p->pools = nullptr; p->top = nullptr; p->snaps = nullptr; p->snap_tops = nullptr;
+    if (p->host_snaps) (void)hipHostFree(p->host_snaps);
+    p->host_snaps = nullptr;
     int rc;
     if ((rc = dalloc_t(p, &p->pools, (size_t)2 * P * sizeof(VRec)))) return rc;
     p->P = P;
     if ((rc = dalloc_t(p, &p->top, (size_t)k * sizeof(VRec)))) return rc;
     p->top_k = k;
-    if ((rc = dalloc_t(p, &p->snap_tops, (size_t)B * k * sizeof(VRec)))) return rc;
-    p->snap_B = B;
+    if ((rc = dalloc_t(p, &p->snaps, (size_t)steps * sizeof(Snap)))) return rc;
+    if ((rc = dalloc_t(p, &p->snap_tops, (size_t)steps * k * sizeof(VRec)))) return rc;
+    p->snap_steps = steps;
     p->snap_k = k;
+    if (hipHostMalloc((void**)&p->host_snaps, (size_t)steps * sizeof(Snap), 0) != hipSuccess)
+        return fail(MOMENTI_E_NOMEM, "pinned host allocation failed");
     return MOMENTI_OK;
 }
 
-struct BatchOut {
-    Counters cnt;
-    PoolState ps;
-    Snap snaps[64];
-};
-
-// Run the pool stages (filter + pool) on the candidates already in p->cand.
-static int pool_stage(momenti_plan* p, int k, int j0, int B)
+// Replay `count` verified records at `rec` (tagged with round and repetition)
+// through the pool for steps [s0, s0 + nsteps); snapshots land in p->snaps.
+static int replay(momenti_plan* p, const VRec* rec, uint32_t count, uint32_t* keep, int k, int s0,
+                  int nsteps)
 {
-    Counters* cnt = st_counters(p);
-    HIP_OK(timed(p, KI_FILTER, 0.0, 0.0, [&] {
-        return launch_filter(p->vrec, p->cap, cnt, st_pool(p), p->pools, p->P, p->keep, cnt, p->st);
-    }));
+    HIP_OK(launch_zero(p->rctl, offsetof(ReplayCtl, step_count) + (size_t)nsteps * 4, p->st));
+    struct {
+        uint32_t n_keep;
+        int32_t K, L, s0, nsteps;
+    } hdr = {0u, p->K, p->L, s0, nsteps};
+    HIP_OK(hipMemcpyAsync(p->rctl, &hdr, sizeof hdr, hipMemcpyHostToDevice, p->st));
     HIP_OK(timed(p, KI_POOL, 0.0, 0.0, [&] {
-        return launch_pool(p->vrec, p->keep, p->cap, cnt, st_pool(p), p->pools, p->P, p->top, k, p->w,
-                           j0, B, st_snaps(p), p->snap_tops, p->st);
+        return launch_replay(rec, count, keep, keep + std::max<uint32_t>(count, 1u), p->rctl, st_pool(p),
+                             p->pools, p->P, p->top, k, p->w, p->snaps, p->snap_tops, p->st);
     }));
-    return MOMENTI_OK;
-}
-
-static int read_status(momenti_plan* p, BatchOut* out, int B)
-{
-    HIP_OK(hipMemcpyAsync(p->host_status, p->status, 128 + (size_t)B * sizeof(Snap),
-                          hipMemcpyDeviceToHost, p->st));
+    HIP_OK(hipMemcpyAsync(p->host_snaps, p->snaps, (size_t)nsteps * sizeof(Snap), hipMemcpyDeviceToHost, p->st));
     HIP_OK(hipStreamSynchronize(p->st));
-    std::memcpy(&out->cnt, p->host_status, sizeof(Counters));
-    std::memcpy(&out->ps, p->host_status + 64, sizeof(PoolState));
-    std::memcpy(out->snaps, p->host_status + 128, (size_t)B * sizeof(Snap));
+    prof_flush(p);
     return MOMENTI_OK;
 }
 
@@ -830,6 +874,18 @@ static void to_motifs(const std::vector<VRec>& v, int count, momenti_motif* out)
 
 static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out,
                           momenti_report* rep);
+
+// Rounds processed from one sort: the first group shares the sort by the
+// longest prefix (its shorter prefixes are right shifts of the same key);
+// the deeper rounds, where collisions multiply, are sorted one by one.
+static std::vector<std::pair<int, int>> round_groups(int K)
+{
+    std::vector<std::pair<int, int>> g;
+    const int lo = std::max(1, K - 3);
+    g.push_back({K, lo});
+    for (int i = lo - 1; i >= 1; --i) g.push_back({i, i});
+    return g;
+}
 
 extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
                               int32_t* n_out, momenti_report* rep)
@@ -849,24 +905,37 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     R.t_hash_ms = p->t_hash_ms;
 
     release_search(p);
+    const auto groups = round_groups(p->K);
+    int max_group = 0;
+    for (auto& gr : groups) max_group = std::max(max_group, gr.first - gr.second + 1);
+    const int max_steps = max_group * p->L;
     int P = p->o.pool_size ? p->o.pool_size : std::max(4096, 128 * k);
     P = std::max(P, k);
     int rc;
-    // buffers: status, pool, candidates, then as many repetitions per launch as fit
     if ((rc = dalloc_t(p, &p->status, 4096))) return rc;
+    if ((rc = dalloc_t(p, &p->rctl, sizeof(ReplayCtl)))) return rc;
     if (hipHostMalloc((void**)&p->host_status, 4096, 0) != hipSuccess)
         return fail(MOMENTI_E_NOMEM, "pinned host allocation failed");
+    if ((rc = alloc_pool(p, P, k, max_steps))) return rc;
+    const int64_t tiles = (p->ns + kSortTile - 1) / kSortTile;
+    const uint64_t left0 = p->mem_limit - p->bytes;
+    uint32_t cap = 1u << 20;
+    while (cap > (1u << 14) && cand_bytes(cap) + store_bytes(cap) + sort_bytes(p->D, p->ns, tiles) > left0)
+        cap >>= 1;
+    if ((rc = alloc_cand(p, cap))) return rc;
+    if ((rc = grow_store(p, cap, 0))) return rc;
     int Bmax = p->o.batch_reps ? p->o.batch_reps : 16;
     Bmax = std::max(1, std::min({Bmax, p->L, 64}));
-    if ((rc = alloc_pool(p, P, k, Bmax))) return rc;
-    const uint64_t left0 = p->mem_limit - p->bytes;
-    const int64_t tiles = (p->ns + kSortTile - 1) / kSortTile;
-    uint32_t cap = 1u << 20;
-    while (cap > (1u << 14) && cand_bytes(cap) + sort_bytes(p->D, p->ns, tiles) > left0) cap >>= 1;
-    if ((rc = alloc_cand(p, cap))) return rc;
     int B = Bmax;
     while (B > 1 && sort_bytes((int64_t)B * p->D, p->ns, tiles) > p->mem_limit - p->bytes) B >>= 1;
     if ((rc = alloc_sort(p, B * p->D))) return rc;
+    {
+        StepGeom gmax{};
+        gmax.ns = p->ns;
+        gmax.nseg = B * p->D;
+        p->coll_parts = enum_partials(gmax);
+        if ((rc = dalloc_t(p, &p->coll_part, (size_t)p->coll_parts * 16))) return rc;
+    }
     R.batch_reps = B;
 
     const bool tracing = p->tr_cand || p->tr_top_size;
@@ -875,28 +944,40 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         for (int64_t s = 0; s < p->tr_steps_cap; ++s) p->tr_top_size[s] = -1;
     std::vector<Cand> hcand;
     std::vector<VRec> hsnap;
-
     static const int verbose = [] {
         const char* v = std::getenv("MOMENTI_VERBOSE");
         return v ? std::atoi(v) : 0;
     }();
+    const double elem_x = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
+
 restart:
     HIP_OK(launch_pool_reset(st_pool(p), p->st));
-    for (int i = p->K; i >= 1; --i) {
-        if (verbose)
-            std::fprintf(stderr, "[momenti] round i=%d: %.1f ms, steps %lld, collisions %lld, candidates %lld\n", i,
+    R.n_steps = 0;
+    if (tracing && p->tr_count) *p->tr_count = 0;
+    for (const auto& gr : groups) {
+        const int i_hi = gr.first, i_lo = gr.second;
+        const int s0 = (p->K - i_hi) * p->L;
+        const int nsteps = (i_hi - i_lo + 1) * p->L;
+        if (verbose) {
+            std::fprintf(stderr, "[momenti] rounds %d..%d: %.1f ms, steps %lld, collisions %lld, candidates %lld |",
+                         i_hi, i_lo,
                          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
                          (long long)R.n_steps, (long long)R.n_collisions, (long long)R.n_cand);
+            for (int q = 0; q < KI_COUNT; ++q)
+                if (p->prof.tot[q].launches) std::fprintf(stderr, " %s %.1f", kKernelNames[q], p->prof.tot[q].ms);
+            std::fprintf(stderr, "\n");
+        }
+        uint32_t stored = 0;
         for (int j0 = 0; j0 < p->L;) {
             const int Bc = std::min(B, p->L - j0);
             StepGeom g;
             g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
-            g.j0 = j0; g.nseg = Bc * p->D; g.i = i; g.K = p->K;
+            g.j0 = j0; g.nseg = Bc * p->D; g.i = i_hi; g.K = p->K; g.i_lo = i_lo;
             HIP_OK(launch_zero(p->status, 64, p->st));
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
-            const double kb = i <= 4 ? 4.0 : 8.0;
-            for (int pass = 0; pass < i; ++pass) {
+            const double kb = i_hi <= 4 ? 4.0 : 8.0;
+            for (int pass = 0; pass < i_hi; ++pass) {
                 const double kin = pass == 0 ? 8.0 : kb;   // pass 0 reads two index words
                 HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
                 HIP_OK(timed(p, KI_SCAN, 8.0 * g.nseg * 256.0 * p->sb.tiles, 0.0, [&] { return launch_scan(g, p->sb, p->st); }));
@@ -904,101 +985,113 @@ restart:
                              [&] { return launch_scatter(g, p->H, p->sb, pass, buf, p->st); }));
                 buf ^= 1;
             }
+            const int kt = std::min(i_hi + 1, p->K);
+            const double rb = kt <= 4 ? 4.0 : 8.0;
+            HIP_OK(timed(p, KI_KEYTABLE, (double)Bc * p->ns * p->D * (8.0 + rb), 0.0, [&] {
+                return launch_keytable(p->H, g, Bc, kt, p->rows, p->st);
+            }));
             int enum_slot = -1, verify_slot = -1;
-            HIP_OK(timed(p, KI_ENUM, elems * kb, 0.0, [&] {
-                return launch_enum(g, p->H, p->sb, buf, d, p->w, p->cand, p->cap, st_counters(p), p->st);
+            HIP_OK(timed(p, KI_ENUM, 0.0, 0.0, [&] {
+                return launch_enum(g, p->sb, buf, p->rows, kt, d, p->w, p->cand, p->cap, st_counters(p),
+                                   p->coll_part, p->st);
             }, &enum_slot));
             HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
                 return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
                                      p->D, p->w, d, p->mu, p->isig, p->vrec, p->st);
             }, &verify_slot));
-            if ((rc = pool_stage(p, k, j0, Bc))) return rc;
-            BatchOut bo;
-            if ((rc = read_status(p, &bo, Bc))) return rc;
+            Counters cnt;
+            HIP_OK(hipMemcpyAsync(p->host_status, p->status, sizeof(Counters), hipMemcpyDeviceToHost, p->st));
+            HIP_OK(hipStreamSynchronize(p->st));
+            std::memcpy(&cnt, p->host_status, sizeof cnt);
             {
-                // sizes known only now: the enumeration read the runs' indices and
-                // gathered 2 words per dimension per endpoint of each scanned pair;
-                // verification read 2 D w samples per candidate
-                const double selem = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
-                const uint32_t nc = std::min(bo.cnt.n_cand, p->cap);
-                prof_set(p, enum_slot, elems * kb + 16.0 * p->D * (double)bo.cnt.n_coll, 0.0);
-                prof_set(p, verify_slot, (double)nc * (2.0 * p->D * p->w * selem + 16.0 * 2 * p->D + sizeof(VRec)),
+                // sizes known only now: the enumeration staged every run member
+                // (key, index, key-table row) once per tile pair; verification
+                // read 2 D w samples per candidate
+                const uint32_t nc = std::min(cnt.n_cand, p->cap);
+                const double rbytes = (std::min(i_hi + 1, p->K) <= 4 ? 4.0 : 8.0) * p->D;
+                prof_set(p, enum_slot, elems * 2.0 * kb + (double)cnt.n_memb * (kb + 4.0 + rbytes), 0.0);
+                prof_set(p, verify_slot, (double)nc * (2.0 * p->D * p->w * elem_x + 32.0 * p->D + sizeof(VRec)),
                          (double)nc * 6.0 * p->D * p->w);
                 prof_flush(p);
             }
-            if (bo.cnt.n_cand > p->cap) {
+            if (cnt.n_cand > p->cap) {
                 // more candidates than room: fewer repetitions per launch, then a larger buffer
                 if (Bc > 1) {
                     B = std::max(1, Bc / 2);
                     continue;
                 }
                 uint32_t need = p->cap;
-                while (need < bo.cnt.n_cand && need < (1u << 30)) need <<= 1;
+                while (need < cnt.n_cand && need < (1u << 30)) need <<= 1;
                 if (cand_bytes(need) > p->mem_limit - p->bytes + cand_bytes(p->cap))
-                    return fail(MOMENTI_E_NOMEM, "%u candidates in one step exceed mem_limit", bo.cnt.n_cand);
+                    return fail(MOMENTI_E_NOMEM, "%u candidates in one step exceed mem_limit", cnt.n_cand);
                 if ((rc = alloc_cand(p, need))) return rc;
                 continue;
             }
-            R.n_collisions += (int64_t)bo.cnt.n_coll;
-            R.n_cand += bo.cnt.n_cand;
-            R.n_verified += bo.cnt.n_cand;
-            if (tracing) {
-                if (p->tr_cand && bo.cnt.n_cand) {
-                    hcand.resize(bo.cnt.n_cand);
-                    HIP_OK(hipMemcpy(hcand.data(), p->cand, bo.cnt.n_cand * sizeof(Cand), hipMemcpyDeviceToHost));
-                    for (const Cand& c : hcand) {
-                        const int64_t s = (int64_t)(p->K - i) * p->L + c.j;
-                        if (*p->tr_count < p->tr_cap) {
-                            p->tr_cand[3 * *p->tr_count + 0] = s;
-                            p->tr_cand[3 * *p->tr_count + 1] = c.a;
-                            p->tr_cand[3 * *p->tr_count + 2] = c.b;
-                        }
-                        ++*p->tr_count;
-                    }
-                }
-                if (p->tr_top_size) {
-                    hsnap.resize((size_t)Bc * k);
-                    HIP_OK(hipMemcpy(hsnap.data(), p->snap_tops, hsnap.size() * sizeof(VRec), hipMemcpyDeviceToHost));
-                    for (int jb = 0; jb < Bc; ++jb) {
-                        const int64_t s = (int64_t)(p->K - i) * p->L + j0 + jb;
-                        if (s >= p->tr_steps_cap) continue;
-                        p->tr_top_size[s] = bo.snaps[jb].top_n;
-                        for (int q = 0; q < bo.snaps[jb].top_n && q < p->tr_k; ++q) {
-                            p->tr_top_pairs[(s * p->tr_k + q) * 2 + 0] = hsnap[(size_t)jb * k + q].a;
-                            p->tr_top_pairs[(s * p->tr_k + q) * 2 + 1] = hsnap[(size_t)jb * k + q].b;
-                        }
-                    }
-                }
+            if (cnt.n_cand) {
+                if ((rc = grow_store(p, stored + cnt.n_cand, stored))) return rc;
+                HIP_OK(hipMemcpyAsync(p->store + stored, p->vrec, (size_t)cnt.n_cand * sizeof(VRec),
+                                      hipMemcpyDeviceToDevice, p->st));
+                stored += cnt.n_cand;
             }
-            for (int jb = 0; jb < Bc; ++jb) {
-                const Snap& sn = bo.snaps[jb];
-                const int J = j0 + jb + 1;
-                ++R.n_steps;
-                if (sn.top_n < k && sn.truncated) {
-                    // the pool dropped pairs that TOP may still need: redo with a larger pool
-                    ++R.pool_overflow;
-                    P *= 2;
-                    if ((rc = alloc_pool(p, P, k, Bmax))) return rc;
-                    R.n_steps = 0;
-                    if (tracing && p->tr_count) *p->tr_count = 0;
-                    goto restart;
-                }
-                if (sn.top_n == k &&
-                    stop_holds(sn.dist_max, p->r, d, i, J, p->K, p->L, p->m, p->o.stop_rule, delta)) {
-                    std::vector<VRec> tv(k);
-                    HIP_OK(hipMemcpy(tv.data(), p->snap_tops + (size_t)jb * k, (size_t)k * sizeof(VRec),
-                                     hipMemcpyDeviceToHost));
-                    to_motifs(tv, k, out);
-                    *n_out = k;
-                    R.i_stop = i;
-                    R.j_stop = J;
-                    R.peak_bytes = p->peak;
-                    R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                    if (rep) *rep = R;
-                    return MOMENTI_OK;
+            R.n_collisions += (int64_t)cnt.n_coll;
+            R.n_cand += cnt.n_cand;
+            R.n_verified += cnt.n_cand;
+            if (tracing && p->tr_cand && cnt.n_cand) {
+                hcand.resize(cnt.n_cand);
+                HIP_OK(hipMemcpy(hcand.data(), p->cand, cnt.n_cand * sizeof(Cand), hipMemcpyDeviceToHost));
+                for (const Cand& c : hcand) {
+                    const int64_t s = (int64_t)(p->K - (int)c.pad) * p->L + c.j;
+                    if (*p->tr_count < p->tr_cap) {
+                        p->tr_cand[3 * *p->tr_count + 0] = s;
+                        p->tr_cand[3 * *p->tr_count + 1] = c.a;
+                        p->tr_cand[3 * *p->tr_count + 2] = c.b;
+                    }
+                    ++*p->tr_count;
                 }
             }
             j0 += Bc;
+        }
+        // replay the group's verified records in step order through the pool
+        if ((rc = replay(p, p->store, stored, p->keep, k, s0, nsteps))) return rc;
+        if (tracing && p->tr_top_size) {
+            hsnap.resize((size_t)nsteps * k);
+            HIP_OK(hipMemcpy(hsnap.data(), p->snap_tops, hsnap.size() * sizeof(VRec), hipMemcpyDeviceToHost));
+            for (int st = 0; st < nsteps; ++st) {
+                const int64_t s = s0 + st;
+                if (s >= p->tr_steps_cap) continue;
+                p->tr_top_size[s] = p->host_snaps[st].top_n;
+                for (int q = 0; q < p->host_snaps[st].top_n && q < p->tr_k; ++q) {
+                    p->tr_top_pairs[(s * p->tr_k + q) * 2 + 0] = hsnap[(size_t)st * k + q].a;
+                    p->tr_top_pairs[(s * p->tr_k + q) * 2 + 1] = hsnap[(size_t)st * k + q].b;
+                }
+            }
+        }
+        for (int st = 0; st < nsteps; ++st) {
+            const Snap& sn = p->host_snaps[st];
+            const int i = i_hi - st / p->L;
+            const int J = st % p->L + 1;
+            ++R.n_steps;
+            if (sn.top_n < k && sn.truncated) {
+                // the pool dropped pairs that TOP may still need: redo with a larger pool
+                ++R.pool_overflow;
+                P *= 2;
+                if ((rc = alloc_pool(p, P, k, max_steps))) return rc;
+                goto restart;
+            }
+            if (sn.top_n == k &&
+                stop_holds(sn.dist_max, p->r, d, i, J, p->K, p->L, p->m, p->o.stop_rule, delta)) {
+                std::vector<VRec> tv(k);
+                HIP_OK(hipMemcpy(tv.data(), p->snap_tops + (size_t)st * k, (size_t)k * sizeof(VRec),
+                                 hipMemcpyDeviceToHost));
+                to_motifs(tv, k, out);
+                *n_out = k;
+                R.i_stop = i;
+                R.j_stop = J;
+                R.peak_bytes = p->peak;
+                R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                if (rep) *rep = R;
+                return MOMENTI_OK;
+            }
         }
     }
     rc = exact_fallback(p, d, k, out, n_out, &R);
@@ -1010,7 +1103,8 @@ restart:
 }
 
 // Algorithm 1, last line: no step stopped, so answer with the exact top-k
-// over every non-trivial pair (same verifier and pool, all pairs streamed).
+// over every non-trivial pair (same verifier and pool, all pairs streamed as
+// one step).
 static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out,
                           momenti_report* rep)
 {
@@ -1026,30 +1120,31 @@ static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int
         while ((int64_t)need < M) need <<= 1;
         if ((rc = alloc_cand(p, need))) return rc;
     }
+    if ((rc = grow_store(p, p->cap, 0))) return rc;
     for (;;) {
         HIP_OK(launch_pool_reset(st_pool(p), p->st));
         int64_t row = 0;
-        BatchOut bo{};
+        Snap last{};
         while (row < std::max<int64_t>(M, 0)) {
             int64_t hi = row + 1;
             while (hi < M && off(hi + 1) - off(row) <= (int64_t)p->cap) ++hi;
+            const uint32_t cnt = (uint32_t)(off(hi) - off(row));
             HIP_OK(launch_zero(p->status, 64, p->st));
-            HIP_OK(timed(p, KI_ALLPAIRS, 16.0 * (off(hi) - off(row)), 0.0, [&] {
+            HIP_OK(timed(p, KI_ALLPAIRS, 16.0 * cnt, 0.0, [&] {
                 return launch_allpairs(p->ns, p->w, row, hi, off(row), p->cand, st_counters(p), p->st);
             }));
             HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
                 return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
                                      p->D, p->w, d, p->mu, p->isig, p->vrec, p->st);
             }));
-            if ((rc = pool_stage(p, k, 0, 1))) return rc;
-            if ((rc = read_status(p, &bo, 1))) return rc;
-            prof_flush(p);
-            rep->n_verified += bo.cnt.n_cand;
+            // all-pairs records carry round 0, repetition 0: the single step K L
+            if ((rc = replay(p, p->vrec, cnt, p->keep, k, p->K * p->L, 1))) return rc;
+            last = p->host_snaps[0];
+            rep->n_verified += cnt;
             row = hi;
         }
-        const Snap& sn = bo.snaps[0];
-        if (M <= 0 || !(sn.top_n < k && sn.truncated)) {
-            const int got = M <= 0 ? 0 : sn.top_n;
+        if (M <= 0 || !(last.top_n < k && last.truncated)) {
+            const int got = M <= 0 ? 0 : last.top_n;
             std::vector<VRec> tv(std::max(got, 1));
             if (got)
                 HIP_OK(hipMemcpy(tv.data(), p->snap_tops, (size_t)got * sizeof(VRec), hipMemcpyDeviceToHost));
@@ -1058,7 +1153,7 @@ static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int
             return MOMENTI_OK;
         }
         ++rep->pool_overflow;
-        if ((rc = alloc_pool(p, p->P * 2, k, p->snap_B))) return rc;
+        if ((rc = alloc_pool(p, p->P * 2, k, p->snap_steps))) return rc;
     }
 }
 

@@ -20,7 +20,7 @@ OK, OK_FALLBACK = 0, 1
 E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 PROJ = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
-STOP = {"tensor": 0, "lemma52": 1}
+STOP = {"tensor": 0, "lemma52": 1, "tensor_literal": 2}
 
 EXPORTS = [
     "momenti_default_opts", "momenti_prepare", "momenti_hash", "momenti_search", "momenti_topk",

@@ -273,10 +273,17 @@ def test_fail_bound_hand_values(orc):
     assert orc.fail_bound(0.5, 8, 20, 8, 200, T) == pytest.approx(0.9375 ** 6, rel=1e-15)
     # i = 7 < K: P_t(3.5, 20) * P_t(4, 180) = (15/16)^1 (7/8)^5 * (15/16)^(12 + 0)
     assert orc.fail_bound(0.5, 7, 20, 8, 200, T) == pytest.approx(0.9375 * 0.875 ** 5 * 0.9375 ** 12, rel=1e-14)
-    # round 1: the factor (1 - p^0)^(J mod m) vanishes as soon as J mod m > 0
-    assert orc.fail_bound(0.3, 1, 1, 8, 200, T) == 0.0
-    # J = 15: P_t(1/2, 15) = (1 - p)^1 (1 - p^0)^0; P_t(1, 185) = (1 - p)^12 (1 - p)^5
-    assert orc.fail_bound(0.5, 1, 15, 8, 200, T) == pytest.approx(0.5 ** 18, rel=1e-14)
+    # round 1: the right half contributes no symbol; its factor is 1, so
+    # J = 1: P_t(1/2, 1) = (1 - p)^0 = 1; P_t(1, 199) = (1 - p)^13 (1 - p)^4
+    assert orc.fail_bound(0.3, 1, 1, 8, 200, T) == pytest.approx(0.7 ** 17, rel=1e-14)
+    # J = 20: P_t(1/2, 20) = (1 - p)^1; P_t(1, 180) = (1 - p)^12 (1 - p)^0
+    assert orc.fail_bound(0.5, 1, 20, 8, 200, T) == pytest.approx(0.5 ** 13, rel=1e-14)
+    # taken literally, (1 - p^0)^(J mod m) vanishes as soon as J mod m > 0
+    TL = orc.STOP_TENSOR_LITERAL
+    assert orc.fail_bound(0.3, 1, 1, 8, 200, TL) == 0.0
+    assert orc.fail_bound(0.5, 1, 15, 8, 200, TL) == pytest.approx(0.5 ** 18, rel=1e-14)
+    # rounds above 1 are the same under both readings
+    assert orc.fail_bound(0.5, 7, 20, 8, 200, TL) == orc.fail_bound(0.5, 7, 20, 8, 200, T)
     # Lemma 5.2 form: (1 - p^i)^J (1 - p^(i+1))^(L - J)
     assert orc.fail_bound(0.5, 8, 3, 8, 200, L52) == pytest.approx((1 - 2 ** -8) ** 3, rel=1e-15)
     assert orc.fail_bound(0.5, 2, 10, 8, 20, L52) == pytest.approx(0.75 ** 10 * 0.875 ** 10, rel=1e-15)
@@ -328,17 +335,27 @@ def test_step_candidates_match_all_pairs_brute_force(orc):
         [(m["a"], m["b"]) for m in orc.topk_exact(x, w, d, k)]
 
 
-def test_lsh_search_stops_on_the_planted_motif(orc):
+def test_lsh_search_returns_the_exact_answer_on_the_tiny_workload(orc):
     s, p = synth.workload("tiny")
     res = orc.lsh_pipeline(s.x, p["w"], p["d"], p["k"], p["delta"], seed=synth.LSH_SEED["tiny"],
                            mem_limit=p["mem_limit"])
     ex = orc.topk_exact(s.x, p["w"], p["d"], p["k"])
     assert [(m["a"], m["b"]) for m in res["motifs"]] == [(m["a"], m["b"]) for m in ex]
-    assert not res["fallback"]
-    # the stopping rule holds at the reported step
+
+
+def test_lsh_search_stops_on_a_close_planted_motif(orc):
+    # noise 0.02 instead of 0.05: the motif is close enough for the bound to
+    # reach delta before round 1
+    s = synth.make_series(0xD00D01, 4, 2000, 50, 1, 2, noise=0.02, min_gap=500)
+    res = orc.lsh_pipeline(s.x, 50, 2, 1, 0.1, seed=synth.LSH_SEED["tiny"], mem_limit=1 << 30)
+    ex = orc.topk_exact(s.x, 50, 2, 1)
+    assert [(m["a"], m["b"]) for m in res["motifs"]] == [(m["a"], m["b"]) for m in ex]
+    assert (ex[0]["a"], ex[0]["b"]) == (s.motifs[0].p1, s.motifs[0].p2)
+    assert not res["fallback"] and res["i_stop"] > 1
+    # the stopping rule holds at the reported step, and not one step earlier
     m = res["motifs"][-1]
-    assert orc.stop(m["dist_max"], res["r"], p["d"], res["i_stop"], res["J_stop"], 8, res["L"],
-                    orc.STOP_TENSOR, p["delta"])
+    i, J = res["i_stop"], res["J_stop"]
+    assert orc.stop(m["dist_max"], res["r"], 2, i, J, 8, res["L"], orc.STOP_TENSOR, 0.1)
 
 
 def test_lsh_recall_is_at_least_one_minus_delta(orc):
