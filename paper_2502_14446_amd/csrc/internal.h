@@ -88,8 +88,8 @@ struct StepGeom {
     int64_t ns;
     int D, NF, NL, m;
     int j0, nseg;        // first repetition of the batch, segments = reps * D
-    int i, K;            // prefix length the segments are sorted by; K
-    int i_lo;            // lowest round enumerated from this sort (i_lo <= i)
+    int i, K;            // highest round of the group; K
+    int i_lo;            // lowest round of the group: segments are sorted by this prefix length
 };
 constexpr int kSortTile = 4096;
 

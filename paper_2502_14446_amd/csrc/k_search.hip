@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_hist(const KT* __restrict__ kin, const 
     if (FIRST) sp = seg_words(H, g, seg);
     const KT* ks = kin + (int64_t)seg * g.ns;
     for (int64_t e = base + threadIdx.x; e < end; e += 256) {
-        KT key = FIRST ? make_key<KT>(sp.Lw[e], sp.Rw[e], g.i) : ks[e];
+        KT key = FIRST ? make_key<KT>(sp.Lw[e], sp.Rw[e], g.i_lo) : ks[e];
         atomicAdd(&cnt[(uint32_t)(key >> (8 * pass)) & 255u], 1u);
     }
     __syncthreads();
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_scatter(const KT* __restrict__ kin, con
         if (valid) {
             const int64_t ge = base + e;
             if (FIRST) {
-                key = make_key<KT>(sp.Lw[ge], sp.Rw[ge], g.i);
+                key = make_key<KT>(sp.Lw[ge], sp.Rw[ge], g.i_lo);
                 id = (uint32_t)ge;
             } else {
                 key = ks[ge];
@@ -271,7 +271,7 @@ hipError_t launch_hist(const StepGeom& g, const uint32_t* H, const SortBufs& b, 
                        hipStream_t s)
 {
     dim3 grid((unsigned)b.tiles, (unsigned)g.nseg);
-    if (g.i <= 4) {
+    if (g.i_lo <= 4) {
         const uint32_t* kin = (const uint32_t*)b.keys[cur];
         if (pass == 0)
             hipLaunchKernelGGL((k_hist<uint32_t, true>), grid, dim3(256), 0, s, kin, H, g, pass, b.tiles, b.hist);
@@ -297,7 +297,7 @@ hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& 
                           hipStream_t s)
 {
     dim3 grid((unsigned)b.tiles, (unsigned)g.nseg);
-    if (g.i <= 4) {
+    if (g.i_lo <= 4) {
         const uint32_t* kin = (const uint32_t*)b.keys[cur];
         uint32_t* kout = (uint32_t*)b.keys[cur ^ 1];
         if (pass == 0)
@@ -363,8 +363,9 @@ __device__ inline int common_symbols(RT x, RT y, int kt)
 }
 
 // Enumeration, fused with run detection. Segments are sorted by their
-// length-g.i prefix; runs of the group's lowest round g.i_lo hold every deeper
-// round's runs. Each wavefront owns 64 consecutive elements of one segment:
+// length-g.i_lo prefix (the group's lowest round); its runs hold every deeper
+// round's runs, and the round at which a pair stops colliding is read from
+// the key table. Each wavefront owns 64 consecutive elements of one segment:
 // ballots mark the heads of runs of length >= 2 that start there; a run's end
 // is the first tail after its head, or, for the one run that leaves the
 // window, found by the wave 64 keys at a time. The wave then enumerates the
@@ -385,19 +386,21 @@ __device__ inline int common_symbols(RT x, RT y, int kt)
 // skipped). NLEV = rounds of the group + 1.
 constexpr int kRowRegs = 16;   // rows up to this many dimensions stay in registers
 
+// x = xor of two key-table entries of kt symbols; returns the number of
+// leading symbols they share and counts, per round i_lo + lv, the dimensions
+// colliding there (and those below the segment's dimension).
 template <typename RT, int NLEV>
-__device__ inline void count_levels(RT x, int kt, int i_lo, bool lower, int (&atleast)[NLEV],
-                                    int (&below)[NLEV])
+__device__ inline int count_levels(RT x, int kt, int i_lo, bool lower, int (&atleast)[NLEV],
+                                   int (&below)[NLEV])
 {
-    // x = xor of the two rows' entries: equal on the first s symbols iff its
-    // top 8 s bits (of kt symbols) are zero
+    const int cp = common_symbols<RT>(x, (RT)0, kt);
 #pragma unroll
     for (int lv = 0; lv < NLEV; ++lv) {
-        const int sym = i_lo + lv;
-        const bool eq = sym >= kt ? x == (RT)0 : (x >> (8 * (kt - sym))) == (RT)0;
+        const bool eq = cp >= i_lo + lv;
         atleast[lv] += eq;
         below[lv] += eq && lower;
     }
+    return cp;
 }
 
 template <typename KT, typename RT, int NLEV>
@@ -411,16 +414,14 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ unsigned long long coll_sh[4], memb_sh[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const size_t region = (size_t)2 * TS * (8 + 4 + g.D * sizeof(RT));
+    const size_t region = (size_t)2 * TS * (4 + g.D * sizeof(RT));
     unsigned char* mine_lds = smem_raw + (size_t)wave * region;
-    uint64_t* keyA = reinterpret_cast<uint64_t*>(mine_lds);
-    uint64_t* keyB = keyA + TS;
-    RT* rowA = reinterpret_cast<RT*>(keyB + TS);
+    RT* rowA = reinterpret_cast<RT*>(mine_lds);
     RT* rowB = rowA + (size_t)TS * g.D;
     uint32_t* idA = reinterpret_cast<uint32_t*>(rowB + (size_t)TS * g.D);
     uint32_t* idB = idA + TS;
 
-    const int sh = 8 * (g.i - g.i_lo);
+    const int sh = 0;   // keys hold exactly the group's lowest-round prefix
     unsigned long long ncoll = 0, nmemb = 0;
     const int64_t wins_per_seg = (g.ns + 63) / 64;
     const int64_t total_wins = wins_per_seg * g.nseg;
@@ -476,24 +477,20 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                     for (int q = lane; q < nA; q += 64) {
                         const uint32_t a = is[start + tp * TS + q];
                         idA[q] = a;
-                        keyA[q] = (uint64_t)ks[start + tp * TS + q];
                         for (int fp = 0; fp < g.D; ++fp) rowA[(size_t)q * g.D + fp] = rbase[(int64_t)a * g.D + fp];
                     }
                     if (!same)
                         for (int q = lane; q < nB; q += 64) {
                             const uint32_t b = is[start + tq * TS + q];
                             idB[q] = b;
-                            keyB[q] = (uint64_t)ks[start + tq * TS + q];
                             for (int fp = 0; fp < g.D; ++fp) rowB[(size_t)q * g.D + fp] = rbase[(int64_t)b * g.D + fp];
                         }
                     wave_sync_lds();
-                    const uint64_t* kQ = same ? keyA : keyB;
                     const RT* rQ = same ? rowA : rowB;
                     const uint32_t* iQ = same ? idA : idB;
                     const int nq = same ? nA / 2 : nB;
                     for (int u = lane; u < nA; u += 64) {
                         const uint32_t xu = idA[u];
-                        const uint64_t ku = keyA[u];
                         RT own[kRowRegs];
                         const RT* ra = rowA + (size_t)u * g.D;
 #pragma unroll
@@ -513,13 +510,19 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
 #pragma unroll
                             for (int v2 = 0; v2 < NLEV; ++v2) { atleast[v2] = 0; below[v2] = 0; }
                             const RT* rb = rQ + (size_t)qq * g.D;
+                            int cpf = 0;   // shared symbols in the segment's own dimension
 #pragma unroll
                             for (int fp = 0; fp < kRowRegs; ++fp)
-                                if (fp < g.D) count_levels<RT, NLEV>(own[fp] ^ rb[fp], kt, g.i_lo, fp < f, atleast, below);
-                            for (int fp = kRowRegs; fp < g.D; ++fp)
-                                count_levels<RT, NLEV>(ra[fp] ^ rb[fp], kt, g.i_lo, fp < f, atleast, below);
+                                if (fp < g.D) {
+                                    const int cp = count_levels<RT, NLEV>(own[fp] ^ rb[fp], kt, g.i_lo, fp < f, atleast, below);
+                                    if (fp == f) cpf = cp;
+                                }
+                            for (int fp = kRowRegs; fp < g.D; ++fp) {
+                                const int cp = count_levels<RT, NLEV>(ra[fp] ^ rb[fp], kt, g.i_lo, fp < f, atleast, below);
+                                if (fp == f) cpf = cp;
+                            }
                             if (atleast[0] < d) continue;   // not even at the group's lowest round
-                            const int top = common_symbols<uint64_t>(ku, kQ[qq], g.i);
+                            const int top = cpf < g.i ? cpf : g.i;
 #pragma unroll
                             for (int lv = NLEV - 2; lv >= 0; --lv) {
                                 const int i = g.i_lo + lv;
@@ -584,7 +587,7 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const unsigned long long*
 // are narrow, so that many work-groups stay resident.
 static int tile_size(int D, int rb)
 {
-    int ts = 12288 / (2 * (12 + D * rb));   // per wave
+    int ts = 12288 / (2 * (4 + D * rb));   // per wave
     ts = ts > 64 ? 64 : ts;
     return ts < 16 ? 16 : (ts / 16) * 16;
 }
@@ -598,7 +601,7 @@ static hipError_t go_enum(const StepGeom& g, const KT* keys, const uint32_t* idx
                           unsigned long long* part, hipStream_t s)
 {
     const int TS = tile_size(g.D, (int)sizeof(RT));
-    const size_t lds = (size_t)4 * 2 * TS * (8 + 4 + g.D * sizeof(RT));   // 4 waves
+    const size_t lds = (size_t)4 * 2 * TS * (4 + g.D * sizeof(RT));   // 4 waves
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_enum_runs<KT, RT, NLEV>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -618,6 +621,7 @@ static hipError_t go_enum_lev(const StepGeom& g, const KT* keys, const uint32_t*
     case 3: return go_enum<KT, RT, 3>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
     case 4: return go_enum<KT, RT, 4>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
     case 5: return go_enum<KT, RT, 5>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
+    case 6: return go_enum<KT, RT, 6>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
     default: return go_enum<KT, RT, 9>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
     }
 }
@@ -626,7 +630,7 @@ hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const void
                        int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
                        unsigned long long* part, hipStream_t s)
 {
-    if (g.i <= 4) {
+    if (g.i_lo <= 4) {
         const uint32_t* k = (const uint32_t*)b.keys[buf];
         if (kt <= 4)
             return go_enum_lev<uint32_t, uint32_t>(g, k, b.idx[buf], (const uint32_t*)rows, kt, d, w,

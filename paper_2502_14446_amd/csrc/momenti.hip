@@ -875,13 +875,14 @@ static void to_motifs(const std::vector<VRec>& v, int count, momenti_motif* out)
 static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out,
                           momenti_report* rep);
 
-// Rounds processed from one sort: the first group shares the sort by the
-// longest prefix (its shorter prefixes are right shifts of the same key);
-// the deeper rounds, where collisions multiply, are sorted one by one.
+// Rounds processed from one sort: a group is sorted by its lowest round's
+// prefix, whose runs contain every deeper round's runs. The first rounds,
+// where collisions are rare, share one sort; the deeper rounds, where
+// collisions multiply, are sorted one by one.
 static std::vector<std::pair<int, int>> round_groups(int K)
 {
     std::vector<std::pair<int, int>> g;
-    const int lo = std::max(1, K - 3);
+    const int lo = std::max(1, K - 4);
     g.push_back({K, lo});
     for (int i = lo - 1; i >= 1; --i) g.push_back({i, i});
     return g;
@@ -976,8 +977,8 @@ restart:
             HIP_OK(launch_zero(p->status, 64, p->st));
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
-            const double kb = i_hi <= 4 ? 4.0 : 8.0;
-            for (int pass = 0; pass < i_hi; ++pass) {
+            const double kb = i_lo <= 4 ? 4.0 : 8.0;
+            for (int pass = 0; pass < i_lo; ++pass) {
                 const double kin = pass == 0 ? 8.0 : kb;   // pass 0 reads two index words
                 HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
                 HIP_OK(timed(p, KI_SCAN, 8.0 * g.nseg * 256.0 * p->sb.tiles, 0.0, [&] { return launch_scan(g, p->sb, p->st); }));
