@@ -366,16 +366,17 @@ __device__ inline int common_symbols(RT x, RT y, int kt)
 // length-g.i_lo prefix (the group's lowest round); its runs hold every deeper
 // round's runs, and the round at which a pair stops colliding is read from
 // the key table. Each wavefront owns 64 consecutive elements of one segment:
-// ballots mark the heads of runs of length >= 2 that start there; a run's end
-// is the first tail after its head, or, for the one run that leaves the
-// window, found by the wave 64 keys at a time. The wave then enumerates the
-// pairs of each of its runs from a private LDS region: the run is cut into
-// tiles of TS members, and for every pair of tiles (P <= Q) the members'
-// window index, sort key and key-table row are staged. Lane u owns member u
-// of tile P (its row in registers) and walks its partners in tile Q; inside
-// one tile of n members the partners of u are u + 1 + v (mod n), v < n / 2,
-// which covers each unordered pair once (for even n the last v is kept for
-// u < n / 2 only).
+// ballots mark the heads of runs of length >= 2 that start there and the
+// tails where runs end. Runs that close inside the window are enumerated all
+// at once, lane by lane: the member at position q of a run of n pairs with
+// the members at q + s (mod n), 1 <= s <= (n - 1) / 2, plus, for even n and
+// q < n / 2, the one at q + n / 2, which covers each unordered pair once;
+// rows reach the partner by cross-lane permutes. The one run that leaves the
+// window has its end found 64 keys at a time and is enumerated from a
+// private LDS region: it is cut into tiles of TS members, and for every pair
+// of tiles (P <= Q) the members' window index and key-table row are staged.
+// Lane u owns member u of tile P (its row in registers) and walks its
+// partners in tile Q, with the same circulant map inside one tile.
 //
 // For a non-trivial pair: cp(f') = shared prefix symbols of the two rows in
 // dimension f', so the pair collides at round i in f' iff cp(f') >= i. It is
@@ -403,6 +404,49 @@ __device__ inline int count_levels(RT x, int kt, int i_lo, bool lower, int (&atl
     return cp;
 }
 
+// Per dimension fp, xor_of(fp) is the xor of the two key-table entries; the
+// counts per round of the group are accumulated and the number of symbols
+// shared in the segment's own dimension f is returned.
+template <typename RT, int NLEV, typename XorOf>
+__device__ inline int count_row(const XorOf& xor_of, int D, int f, int kt, int i_lo,
+                                int (&atleast)[NLEV], int (&below)[NLEV])
+{
+#pragma unroll
+    for (int lv = 0; lv < NLEV; ++lv) { atleast[lv] = 0; below[lv] = 0; }
+    int cpf = 0;
+#pragma unroll
+    for (int fp = 0; fp < kRowRegs; ++fp)
+        if (fp < D) {
+            const int cp = count_levels<RT, NLEV>(xor_of(fp), kt, i_lo, fp < f, atleast, below);
+            if (fp == f) cpf = cp;
+        }
+    for (int fp = kRowRegs; fp < D; ++fp) {
+        const int cp = count_levels<RT, NLEV>(xor_of(fp), kt, i_lo, fp < f, atleast, below);
+        if (fp == f) cpf = cp;
+    }
+    return cpf;
+}
+
+// Records the non-trivial pair (a < b) as a candidate of every round of the
+// group at which the rule above accepts it.
+template <int NLEV>
+__device__ inline void emit_pair(uint32_t a, uint32_t b, const int (&atleast)[NLEV],
+                                 const int (&below)[NLEV], int cpf, const StepGeom& g, int j, int d,
+                                 Cand* __restrict__ cand, uint32_t cap, Counters* __restrict__ cnt)
+{
+    if (atleast[0] < d) return;   // not even at the group's lowest round
+    const int top = cpf < g.i ? cpf : g.i;
+#pragma unroll
+    for (int lv = NLEV - 2; lv >= 0; --lv) {
+        const int i = g.i_lo + lv;
+        if (i > top) continue;                    // rounds i_lo .. top
+        if (atleast[lv] < d || below[lv] > 0) continue;
+        if (i < g.K && atleast[lv + 1] >= d) continue;
+        const uint32_t pos = atomicAdd(&cnt->n_cand, 1u);
+        if (pos < cap) cand[pos] = Cand{a, b, (uint32_t)j, (uint32_t)i};
+    }
+}
+
 template <typename KT, typename RT, int NLEV>
 __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
@@ -421,11 +465,13 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
     uint32_t* idA = reinterpret_cast<uint32_t*>(rowB + (size_t)TS * g.D);
     uint32_t* idB = idA + TS;
 
-    const int sh = 0;   // keys hold exactly the group's lowest-round prefix
     unsigned long long ncoll = 0, nmemb = 0;
     const int64_t wins_per_seg = (g.ns + 63) / 64;
     const int64_t total_wins = wins_per_seg * g.nseg;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const uint64_t lane_bit = 1ull << lane;
+    const uint64_t le_mask = lane_bit | (lane_bit - 1);   // lanes <= this one
+    const uint64_t ge_mask = ~(lane_bit - 1);             // lanes >= this one
     // persistent: each wavefront strides over the 64-element windows of all segments
     for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < total_wins; win += nwaves) {
         const int seg = (int)(win / wins_per_seg);
@@ -438,101 +484,128 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
 
         const int64_t t = base + lane;
         const bool valid = t < g.ns;
-        const KT k = valid ? (KT)(ks[t] >> sh) : (KT)0;
-        const bool same_prev = valid && t > 0 && (KT)(ks[t - 1] >> sh) == k;
-        const bool same_next = valid && t + 1 < g.ns && (KT)(ks[t + 1] >> sh) == k;
+        const KT k = valid ? ks[t] : (KT)0;
+        const bool same_prev = valid && t > 0 && ks[t - 1] == k;
+        const bool same_next = valid && t + 1 < g.ns && ks[t + 1] == k;
         const bool head = valid && !same_prev && same_next;
-        uint64_t heads = __ballot(head);
+        const uint64_t heads = __ballot(head);
         if (!heads) continue;
         const uint64_t tails = __ballot(valid && !same_next);
-        const uint64_t after = lane == 63 ? 0ull : (tails & (~0ull << (lane + 1)));
-        int64_t my_end = -1;
-        if (head && after) my_end = base + __ffsll((unsigned long long)after);
-        const uint64_t open = __ballot(head && !after);
-        if (open) {
-            const int hl = __ffsll((unsigned long long)open) - 1;
-            const KT hk = __shfl(k, hl, 64);
-            int64_t pos = base + 64, found = -1;
-            while (found < 0) {
-                const int64_t e = pos + lane;
-                const bool stop = e >= g.ns || (KT)(ks[e < g.ns ? e : g.ns - 1] >> sh) != hk;
-                const uint64_t m = __ballot(stop);
-                if (m) found = pos + __ffsll((unsigned long long)m) - 1;
-                pos += 64;
-            }
-            if (lane == hl) my_end = found;
-        }
-        while (heads) {
-            const int hl = __ffsll((unsigned long long)heads) - 1;
-            heads &= heads - 1;
-            const int64_t start = base + hl;
-            const int len = (int)(__shfl(my_end, hl, 64) - start);
-            if (lane == 0) nmemb += (unsigned long long)len;
-            const int T = (len + TS - 1) / TS;
-            for (int tp = 0; tp < T; ++tp) {
-                for (int tq = tp; tq < T; ++tq) {
-                    const int nA = min(TS, len - tp * TS), nB = min(TS, len - tq * TS);
-                    const bool same = tp == tq;
-                    wave_sync_lds();
-                    for (int q = lane; q < nA; q += 64) {
-                        const uint32_t a = is[start + tp * TS + q];
-                        idA[q] = a;
-                        for (int fp = 0; fp < g.D; ++fp) rowA[(size_t)q * g.D + fp] = rbase[(int64_t)a * g.D + fp];
-                    }
-                    if (!same)
-                        for (int q = lane; q < nB; q += 64) {
-                            const uint32_t b = is[start + tq * TS + q];
-                            idB[q] = b;
-                            for (int fp = 0; fp < g.D; ++fp) rowB[(size_t)q * g.D + fp] = rbase[(int64_t)b * g.D + fp];
-                        }
-                    wave_sync_lds();
-                    const RT* rQ = same ? rowA : rowB;
-                    const uint32_t* iQ = same ? idA : idB;
-                    const int nq = same ? nA / 2 : nB;
-                    for (int u = lane; u < nA; u += 64) {
-                        const uint32_t xu = idA[u];
-                        RT own[kRowRegs];
-                        const RT* ra = rowA + (size_t)u * g.D;
+
+        // Runs that close inside the window: a member's partners are lanes of
+        // this wave, so rows travel by cross-lane permutes (or, for wide rows,
+        // are read back through the cache) with no staging.
+        const uint64_t hb = heads & le_mask, tb = tails & ge_mask;
+        const bool inner = valid && (head || same_prev) && hb && tb;
+        const int h = 63 - __clzll((long long)(hb | 1ull));   // the run's head lane
+        const int e = __ffsll((unsigned long long)(tb | (1ull << 63)));   // one past its tail lane
+        const int L = e - h, q = lane - h;
+        const int npart = inner ? (L - 1) / 2 + (((L & 1) == 0 && q < L / 2) ? 1 : 0) : 0;
+        const uint64_t inner_bits = __ballot(inner);
+        if (lane == 0) nmemb += (unsigned long long)__popcll(inner_bits);
+        if (inner_bits) {
+            const uint32_t xu = valid ? is[t] : 0u;
+            RT own[kRowRegs];
 #pragma unroll
-                        for (int fp = 0; fp < kRowRegs; ++fp) own[fp] = fp < g.D ? ra[fp] : (RT)0;
-                        for (int v = 0; v < nq; ++v) {
-                            int qq = v;
-                            if (same) {
-                                if ((nA & 1) == 0 && v == nq - 1 && u >= nA / 2) continue;
-                                qq = u + 1 + v;
-                                if (qq >= nA) qq -= nA;
-                            }
-                            const uint32_t y = iQ[qq];
-                            const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
-                            if (2 * (int64_t)(b - a) <= (int64_t)w) continue;   // trivial match
+            for (int fp = 0; fp < kRowRegs; ++fp)
+                own[fp] = (inner && fp < g.D) ? rbase[(int64_t)xu * g.D + fp] : (RT)0;
+            for (int s = 1;; ++s) {
+                const bool act = s <= npart;
+                if (!__ballot(act)) break;
+                int qs = q + s;
+                if (qs >= L) qs -= L;
+                const int pl = act ? h + qs : lane;
+                const uint32_t y = __shfl(xu, pl, 64);
+                int atleast[NLEV], below[NLEV];
+                if (g.D <= kRowRegs) {
+                    // every lane takes part in the permutes; only active lanes use them
+                    const int cpf = count_row<RT, NLEV>(
+                        [&](int fp) { return own[fp] ^ (RT)__shfl(own[fp], pl, 64); }, g.D, f, kt, g.i_lo,
+                        atleast, below);
+                    if (act) {
+                        const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
+                        if (2 * (int64_t)(b - a) > (int64_t)w) {   // else a trivial match
                             ++ncoll;
-                            int atleast[NLEV], below[NLEV];
-#pragma unroll
-                            for (int v2 = 0; v2 < NLEV; ++v2) { atleast[v2] = 0; below[v2] = 0; }
-                            const RT* rb = rQ + (size_t)qq * g.D;
-                            int cpf = 0;   // shared symbols in the segment's own dimension
-#pragma unroll
-                            for (int fp = 0; fp < kRowRegs; ++fp)
-                                if (fp < g.D) {
-                                    const int cp = count_levels<RT, NLEV>(own[fp] ^ rb[fp], kt, g.i_lo, fp < f, atleast, below);
-                                    if (fp == f) cpf = cp;
-                                }
-                            for (int fp = kRowRegs; fp < g.D; ++fp) {
-                                const int cp = count_levels<RT, NLEV>(ra[fp] ^ rb[fp], kt, g.i_lo, fp < f, atleast, below);
-                                if (fp == f) cpf = cp;
-                            }
-                            if (atleast[0] < d) continue;   // not even at the group's lowest round
-                            const int top = cpf < g.i ? cpf : g.i;
-#pragma unroll
-                            for (int lv = NLEV - 2; lv >= 0; --lv) {
-                                const int i = g.i_lo + lv;
-                                if (i > top) continue;                    // rounds i_lo .. top
-                                if (atleast[lv] < d || below[lv] > 0) continue;
-                                if (i < g.K && atleast[lv + 1] >= d) continue;
-                                const uint32_t pos = atomicAdd(&cnt->n_cand, 1u);
-                                if (pos < cap) cand[pos] = Cand{a, b, (uint32_t)j, (uint32_t)i};
-                            }
+                            emit_pair<NLEV>(a, b, atleast, below, cpf, g, j, d, cand, cap, cnt);
                         }
+                    }
+                } else if (act) {
+                    const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
+                    if (2 * (int64_t)(b - a) > (int64_t)w) {
+                        ++ncoll;
+                        const RT* ra = rbase + (int64_t)xu * g.D;
+                        const RT* rb = rbase + (int64_t)y * g.D;
+                        const int cpf = count_row<RT, NLEV>(
+                            [&](int fp) { return (fp < kRowRegs ? own[fp] : ra[fp]) ^ rb[fp]; }, g.D, f, kt,
+                            g.i_lo, atleast, below);
+                        emit_pair<NLEV>(a, b, atleast, below, cpf, g, j, d, cand, cap, cnt);
+                    }
+                }
+            }
+        }
+
+        // The one run that leaves the window (if its head is here): find its
+        // end 64 keys at a time, then enumerate it tile pair by tile pair
+        // from the wave's LDS region.
+        const uint64_t open = __ballot(head && !tb);
+        if (!open) continue;
+        const int hl = __ffsll((unsigned long long)open) - 1;
+        const KT hk = __shfl(k, hl, 64);
+        int64_t pos = base + 64, end = -1;
+        while (end < 0) {
+            const int64_t ee = pos + lane;
+            const bool stop = ee >= g.ns || ks[ee < g.ns ? ee : g.ns - 1] != hk;
+            const uint64_t m = __ballot(stop);
+            if (m) end = pos + __ffsll((unsigned long long)m) - 1;
+            pos += 64;
+        }
+        const int64_t start = base + hl;
+        const int len = (int)(end - start);
+        if (lane == 0) nmemb += (unsigned long long)len;
+        const int T = (len + TS - 1) / TS;
+        for (int tp = 0; tp < T; ++tp) {
+            for (int tq = tp; tq < T; ++tq) {
+                const int nA = min(TS, len - tp * TS), nB = min(TS, len - tq * TS);
+                const bool same = tp == tq;
+                wave_sync_lds();
+                for (int r = lane; r < nA; r += 64) {
+                    const uint32_t a = is[start + tp * TS + r];
+                    idA[r] = a;
+                    for (int fp = 0; fp < g.D; ++fp) rowA[(size_t)r * g.D + fp] = rbase[(int64_t)a * g.D + fp];
+                }
+                if (!same)
+                    for (int r = lane; r < nB; r += 64) {
+                        const uint32_t b = is[start + tq * TS + r];
+                        idB[r] = b;
+                        for (int fp = 0; fp < g.D; ++fp) rowB[(size_t)r * g.D + fp] = rbase[(int64_t)b * g.D + fp];
+                    }
+                wave_sync_lds();
+                const RT* rQ = same ? rowA : rowB;
+                const uint32_t* iQ = same ? idA : idB;
+                const int nq = same ? nA / 2 : nB;
+                for (int u = lane; u < nA; u += 64) {
+                    const uint32_t xu = idA[u];
+                    RT own[kRowRegs];
+                    const RT* ra = rowA + (size_t)u * g.D;
+#pragma unroll
+                    for (int fp = 0; fp < kRowRegs; ++fp) own[fp] = fp < g.D ? ra[fp] : (RT)0;
+                    for (int v = 0; v < nq; ++v) {
+                        int qq = v;
+                        if (same) {
+                            if ((nA & 1) == 0 && v == nq - 1 && u >= nA / 2) continue;
+                            qq = u + 1 + v;
+                            if (qq >= nA) qq -= nA;
+                        }
+                        const uint32_t y = iQ[qq];
+                        const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
+                        if (2 * (int64_t)(b - a) <= (int64_t)w) continue;   // trivial match
+                        ++ncoll;
+                        int atleast[NLEV], below[NLEV];
+                        const RT* rb = rQ + (size_t)qq * g.D;
+                        const int cpf = count_row<RT, NLEV>(
+                            [&](int fp) { return (fp < kRowRegs ? own[fp] : ra[fp]) ^ rb[fp]; }, g.D, f, kt,
+                            g.i_lo, atleast, below);
+                        emit_pair<NLEV>(a, b, atleast, below, cpf, g, j, d, cand, cap, cnt);
                     }
                 }
             }

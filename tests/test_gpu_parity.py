@@ -218,6 +218,23 @@ def test_traversal_matches_oracle_deep_rounds(orc):
     _check_traversal(orc, s, p, 8, 4, 9, 2, 2, 1e-3, "lemma52")
 
 
+def test_traversal_matches_oracle_wide_rows_stop(orc):
+    # D = 20: key-table rows wider than the registers a lane keeps, so pairs
+    # in short runs read the partner's row back from memory
+    s = synth.make_series(51, 20, 1500, 32, 2, 4, dtype="f64", noise=0.02)
+    p = dict(w=32, mem_limit=1 << 30)
+    rep, ref = _check_traversal(orc, s, p, 9, 8, 30, 1, 2, 0.1, "lemma52")
+    assert ref["i_stop"] == 3
+
+
+def test_traversal_matches_oracle_wide_rows_all_rounds(orc):
+    # D = 24, K = 6: no step stops, so every round down to 1 is compared
+    s = synth.make_series(52, 24, 1200, 30, 2, 3, dtype="f64")
+    p = dict(w=30, mem_limit=1 << 30)
+    rep, ref = _check_traversal(orc, s, p, 9, 6, 8, 3, 3, 1e-4, "lemma52")
+    assert ref["i_stop"] == 0
+
+
 # --------------------------------------------------------------------------- end to end
 def test_end_to_end_tiny_matches_oracle_and_exact(orc):
     s, p = synth.workload("tiny")
