@@ -43,9 +43,10 @@ struct Snap {
 // Device counters of one batch of traversal steps.
 struct Counters {
     uint32_t n_cand;             // candidates emitted (may exceed the buffer)
-    uint32_t n_runs;             // runs of >= 2 equal prefixes (may exceed the buffer)
-    unsigned long long n_coll;   // non-trivial one-dimensional collisions scanned
-    unsigned long long n_memb;   // elements in those runs
+    uint32_t pad;
+    unsigned long long n_coll;   // pairs of equal prefixes in the segments (trivial matches included)
+    unsigned long long n_memb;   // elements in runs of >= 2
+    unsigned long long n_screen; // non-trivial pairs that passed the fingerprint screen
 };
 
 // A run of equal prefixes inside one sorted segment.
@@ -87,10 +88,13 @@ struct SortBufs {
 struct StepGeom {
     int64_t ns;
     int D, NF, NL, m;
-    int j0, nseg;        // first repetition of the batch, segments = reps * D
+    int j0, nseg;        // first repetition of the batch, segments = reps * Ds
+    int Ds;              // dimensions that get segments: seg = rep * Ds + f, f < Ds
     int i, K;            // highest round of the group; K
     int i_lo;            // lowest round of the group: segments are sorted by this prefix length
 };
+// 32-bit words of a window's fingerprint row (one byte per dimension)
+__host__ __device__ inline int fp_words(int D) { return (D + 3) / 4; }
 constexpr int kSortTile = 4096;
 
 // Stable LSD sort of every segment of the batch by its length-i hash prefix,
@@ -101,16 +105,17 @@ hipError_t launch_hist(const StepGeom& g, const uint32_t* H, const SortBufs& b, 
 hipError_t launch_scan(const StepGeom& g, const SortBufs& b, hipStream_t s);
 hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& b, int pass, int cur,
                           hipStream_t s);
-// Key table of the batch: rows[jb][a][f] = length-kt interleaved prefix
-// (uint32 when kt <= 4, else uint64).
-hipError_t launch_keytable(const uint32_t* H, const StepGeom& g, int reps, int kt, void* rows,
-                           hipStream_t s);
+// Fingerprint rows of the batch, fps[jb][a][fp_words(D)]: byte f digests
+// dimension f's length-i_lo prefix (the prefix itself when i_lo = 1), padded
+// with zero bytes to whole words.
+hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, hipStream_t s);
 // Runs of >= 2 equal length-i_lo prefixes and the pairs of every run (one
-// launch); `part` holds enum_partials(g) per-work-group collision counts.
+// launch); `part` holds enum_partials(g) per-work-group triples of counts
+// (pairs in runs, run members, screened pairs). kt = min(i_hi + 1, K).
 int64_t enum_partials(const StepGeom& g);
-hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const void* rows, int kt,
-                       int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
-                       unsigned long long* part, hipStream_t s);
+hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint32_t* H,
+                       const uint32_t* fps, int kt, int d, int w, Cand* cand, uint32_t cap,
+                       Counters* cnt, unsigned long long* part, hipStream_t s);
 hipError_t launch_verify(const Cand* cand, uint32_t cap, const Counters* cnt, const void* x,
                          int dtype, int64_t n, int64_t ns, int D, int w, int d, const double* mu,
                          const double* isig, VRec* out, hipStream_t s);

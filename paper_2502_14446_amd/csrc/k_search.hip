@@ -117,7 +117,7 @@ struct SegPtr {
 
 __device__ inline SegPtr seg_words(const uint32_t* H, const StepGeom& g, int seg)
 {
-    const int jb = seg / g.D, f = seg - jb * g.D;
+    const int jb = seg / g.Ds, f = seg - jb * g.Ds;
     const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
     SegPtr p;
     p.Lw = H + ((int64_t)f * g.NF + l) * g.ns;
@@ -320,121 +320,111 @@ hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& 
 }
 
 // ------------------------------------------------------------------ enumeration
-// Key table of a batch: for every repetition of the batch and every window,
-// the length-kt prefix of every dimension, one contiguous row per window
-// ([jb][a][f]). kt = min(i_hi + 1, K) symbols: enough to tell, for every round
-// i of the group, whether a pair collides at i and at i + 1 in each dimension.
-template <typename RT>
-__global__ __launch_bounds__(256) void k_keytable(const uint32_t* __restrict__ H, StepGeom g, int reps,
-                                                  int kt, RT* __restrict__ rows)
+// Fingerprint rows of a batch: for every repetition of the batch and every
+// window, one byte per dimension digesting that dimension's length-i_lo
+// prefix (equal prefixes give equal bytes), four to a word, padded with zero
+// bytes ([jb][a][fp_words(D)]). The pairs of a run are screened with them for
+// >= d colliding dimensions a word at a time; the few that pass have their
+// per-dimension prefixes rebuilt from the index and counted exactly.
+__device__ inline uint32_t prefix_digest(uint64_t prefix, int i_lo)
+{
+    // one symbol is its own digest; longer prefixes are mixed by a
+    // multiplicative (Fibonacci) hash and the top byte kept
+    return i_lo == 1 ? (uint32_t)(prefix & 0xFFu) : (uint32_t)((prefix * 0x9E3779B97F4A7C15ull) >> 56);
+}
+
+__global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H, StepGeom g, int reps,
+                                                 uint32_t* __restrict__ fps)
 {
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (gid >= (int64_t)reps * g.ns) return;
     const int jb = (int)(gid / g.ns);
     const int64_t a = gid - (int64_t)jb * g.ns;
     const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
-    RT* row = rows + gid * g.D;
+    uint32_t* fw = fps + gid * fp_words(g.D);
+    uint32_t word = 0;
     for (int f = 0; f < g.D; ++f) {
         const uint32_t L = H[((int64_t)f * g.NF + l) * g.ns + a];
         const uint32_t R = H[((int64_t)f * g.NF + g.NL + r) * g.ns + a];
-        row[f] = make_key<RT>(L, R, kt);
+        word |= prefix_digest(make_key<uint64_t>(L, R, g.i_lo), g.i_lo) << (8 * (f & 3));
+        if ((f & 3) == 3 || f == g.D - 1) {
+            fw[f >> 2] = word;
+            word = 0;
+        }
     }
 }
 
-hipError_t launch_keytable(const uint32_t* H, const StepGeom& g, int reps, int kt, void* rows,
-                           hipStream_t s)
+hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, hipStream_t s)
 {
     const int64_t total = (int64_t)reps * g.ns;
-    dim3 grid((unsigned)((total + 255) / 256));
-    if (kt <= 4)
-        hipLaunchKernelGGL(k_keytable<uint32_t>, grid, dim3(256), 0, s, H, g, reps, kt, (uint32_t*)rows);
-    else
-        hipLaunchKernelGGL(k_keytable<uint64_t>, grid, dim3(256), 0, s, H, g, reps, kt, (uint64_t*)rows);
+    hipLaunchKernelGGL(k_fptable, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, H, g, reps, fps);
     return hipGetLastError();
 }
 
-// Number of leading symbols two kt-symbol prefixes share.
-template <typename RT>
-__device__ inline int common_symbols(RT x, RT y, int kt)
+// Bytes of x that are not zero, plus 28 (SWAR: the top bit of a byte of
+// ((x & 0x7F..) + 0x7F..) | x is set iff the byte is non-zero, and no carry
+// crosses a byte; the other 28 bits are forced to one).
+__device__ inline int nonzero_bytes_28(uint32_t x)
 {
-    const uint64_t v = (uint64_t)(x ^ y);
-    if (v == 0) return kt;
-    return (__clzll(v) - (64 - 8 * kt)) >> 3;
+    return __popc(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
 }
 
-// Enumeration, fused with run detection. Segments are sorted by their
-// length-g.i_lo prefix (the group's lowest round); its runs hold every deeper
-// round's runs, and the round at which a pair stops colliding is read from
-// the key table. Each wavefront owns 64 consecutive elements of one segment:
-// ballots mark the heads of runs of length >= 2 that start there and the
-// tails where runs end. Runs that close inside the window are enumerated all
-// at once, lane by lane: the member at position q of a run of n pairs with
-// the members at q + s (mod n), 1 <= s <= (n - 1) / 2, plus, for even n and
-// q < n / 2, the one at q + n / 2, which covers each unordered pair once;
-// rows reach the partner by cross-lane permutes. The one run that leaves the
-// window has its end found 64 keys at a time and is enumerated from a
-// private LDS region: it is cut into tiles of TS members, and for every pair
-// of tiles (P <= Q) the members' window index and key-table row are staged.
-// Lane u owns member u of tile P (its row in registers) and walks its
-// partners in tile Q, with the same circulant map inside one tile.
-//
-// For a non-trivial pair: cp(f') = shared prefix symbols of the two rows in
-// dimension f', so the pair collides at round i in f' iff cp(f') >= i. It is
-// a candidate of step (i, j), for each round i of the group at which it
-// collides in the segment's dimension f, iff W_i = #{f' : cp >= i} >= d, no
-// f' < f has cp >= i (emitted once, from its lowest colliding dimension) and,
-// below round K, W_{i+1} < d (section 6.2: pairs seen one symbol deeper are
-// skipped). NLEV = rounds of the group + 1.
-constexpr int kRowRegs = 16;   // rows up to this many dimensions stay in registers
+constexpr int kFpRegs = 8;   // fingerprint rows up to this many words (32 dimensions) stay in registers
 
-// x = xor of two key-table entries of kt symbols; returns the number of
-// leading symbols they share and counts, per round i_lo + lv, the dimensions
-// colliding there (and those below the segment's dimension).
-template <typename RT, int NLEV>
-__device__ inline int count_levels(RT x, int kt, int i_lo, bool lower, int (&atleast)[NLEV],
-                                   int (&below)[NLEV])
+// Sum over the words of nonzero_bytes_28(own ^ partner): the lane's own row
+// (first words in registers, the rest at own_tail) against the partner's
+// (pw). A pair has at least `need` equal bytes iff the sum is <= 32 nw - need.
+template <typename GetW>
+__device__ inline int screen(const uint32_t (&ofp)[kFpRegs], const uint32_t* own_tail, const GetW& pw,
+                             int nw)
 {
-    const int cp = common_symbols<RT>(x, (RT)0, kt);
+    int z = 0;
 #pragma unroll
-    for (int lv = 0; lv < NLEV; ++lv) {
-        const bool eq = cp >= i_lo + lv;
-        atleast[lv] += eq;
-        below[lv] += eq && lower;
-    }
-    return cp;
+    for (int wd = 0; wd < kFpRegs; ++wd)
+        if (wd < nw) z += nonzero_bytes_28(ofp[wd] ^ pw(wd));
+    for (int wd = kFpRegs; wd < nw; ++wd) z += nonzero_bytes_28(own_tail[wd] ^ pw(wd));
+    return z;
 }
 
-// Per dimension fp, xor_of(fp) is the xor of the two key-table entries; the
-// counts per round of the group are accumulated and the number of symbols
-// shared in the segment's own dimension f is returned.
-template <typename RT, int NLEV, typename XorOf>
-__device__ inline int count_row(const XorOf& xor_of, int D, int f, int kt, int i_lo,
-                                int (&atleast)[NLEV], int (&below)[NLEV])
+// Number of leading symbols two kt-symbol prefixes share.
+__device__ inline int common_symbols(uint64_t x, uint64_t y, int kt)
 {
+    const uint64_t v = x ^ y;
+    if (v == 0) return kt;
+    return (__clzll((long long)v) - (64 - 8 * kt)) >> 3;
+}
+
+// Exact test of a pair (a < b) that passed the screen, in repetition j of a
+// segment of dimension f. cp(f') = symbols shared by the two length-kt
+// prefixes in dimension f' (kt = min(i_hi + 1, K)), so the pair collides at
+// round i in f' iff cp(f') >= i. It is a candidate of step (i, j), for each
+// round i of the group at which it collides in f, iff W_i = #{f' : cp >= i}
+// >= d, no f' < f has cp >= i (it is reported once, from its lowest colliding
+// dimension) and, below round K, W_{i+1} < d (section 6.2: pairs seen one
+// symbol deeper are skipped). NLEV = rounds of the group + 1.
+template <int NLEV>
+__device__ void judge_pair(uint32_t a, uint32_t b, const uint32_t* __restrict__ H, const StepGeom& g,
+                           int f, int j, int kt, int d, Cand* __restrict__ cand, uint32_t cap,
+                           Counters* __restrict__ cnt)
+{
+    const int l = j / g.m, r = j - l * g.m;
+    int atleast[NLEV], below[NLEV];
 #pragma unroll
     for (int lv = 0; lv < NLEV; ++lv) { atleast[lv] = 0; below[lv] = 0; }
     int cpf = 0;
+    for (int fp = 0; fp < g.D; ++fp) {
+        const uint32_t* Hl = H + ((int64_t)fp * g.NF + l) * g.ns;
+        const uint32_t* Hr = H + ((int64_t)fp * g.NF + g.NL + r) * g.ns;
+        const int cp = common_symbols(make_key<uint64_t>(Hl[a], Hr[a], kt), make_key<uint64_t>(Hl[b], Hr[b], kt), kt);
 #pragma unroll
-    for (int fp = 0; fp < kRowRegs; ++fp)
-        if (fp < D) {
-            const int cp = count_levels<RT, NLEV>(xor_of(fp), kt, i_lo, fp < f, atleast, below);
-            if (fp == f) cpf = cp;
+        for (int lv = 0; lv < NLEV; ++lv) {
+            const bool eq = cp >= g.i_lo + lv;
+            atleast[lv] += eq;
+            below[lv] += eq && fp < f;
         }
-    for (int fp = kRowRegs; fp < D; ++fp) {
-        const int cp = count_levels<RT, NLEV>(xor_of(fp), kt, i_lo, fp < f, atleast, below);
         if (fp == f) cpf = cp;
     }
-    return cpf;
-}
-
-// Records the non-trivial pair (a < b) as a candidate of every round of the
-// group at which the rule above accepts it.
-template <int NLEV>
-__device__ inline void emit_pair(uint32_t a, uint32_t b, const int (&atleast)[NLEV],
-                                 const int (&below)[NLEV], int cpf, const StepGeom& g, int j, int d,
-                                 Cand* __restrict__ cand, uint32_t cap, Counters* __restrict__ cnt)
-{
-    if (atleast[0] < d) return;   // not even at the group's lowest round
+    if (atleast[0] < d) return;   // the digests agreed by chance
     const int top = cpf < g.i ? cpf : g.i;
 #pragma unroll
     for (int lv = NLEV - 2; lv >= 0; --lv) {
@@ -447,25 +437,45 @@ __device__ inline void emit_pair(uint32_t a, uint32_t b, const int (&atleast)[NL
     }
 }
 
-template <typename KT, typename RT, int NLEV>
-__global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
+// Enumeration, fused with run detection. Segments are sorted by their
+// length-i_lo prefix (the group's lowest round), so every deeper round's runs
+// lie inside its runs. Each wavefront owns 64 consecutive elements of one
+// segment: ballots mark the heads of runs of length >= 2 that start there and
+// the tails where runs end.
+//  * Runs that close inside the window are enumerated all at once, lane by
+//    lane: the member at position q of a run of n pairs with the members at
+//    q + s (mod n), 1 <= s <= (n - 1) / 2, plus, for even n and q < n / 2, the
+//    one at q + n / 2, which covers each unordered pair once; fingerprint
+//    words reach the partner by cross-lane permutes.
+//  * The one run that leaves the window has its end found 64 keys at a time
+//    and is cut into tiles of TS members, staged (window index, fingerprint
+//    row) in the wave's LDS region; tile P is stored twice in a row so that
+//    the circulant partners u + 1 + v of member u need no wrap. Lane u owns
+//    member u of P and walks its partners in tile Q >= P (all lanes read the
+//    same partner of Q at once: an LDS broadcast).
+// Pairs that pass the screen and are not trivial matches go to judge_pair.
+template <int NLEV>
+__global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
-                                                   const RT* __restrict__ rows, StepGeom g, int kt,
+                                                   const uint32_t* __restrict__ H,
+                                                   const uint32_t* __restrict__ fps, StepGeom g, int kt,
                                                    int d, int w, int TS, Cand* __restrict__ cand,
                                                    uint32_t cap, Counters* __restrict__ cnt,
                                                    unsigned long long* __restrict__ coll_part)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ unsigned long long coll_sh[4], memb_sh[4];
+    __shared__ unsigned long long coll_sh[4], memb_sh[4], scr_sh[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const size_t region = (size_t)2 * TS * (4 + g.D * sizeof(RT));
-    unsigned char* mine_lds = smem_raw + (size_t)wave * region;
-    RT* rowA = reinterpret_cast<RT*>(mine_lds);
-    RT* rowB = rowA + (size_t)TS * g.D;
-    uint32_t* idA = reinterpret_cast<uint32_t*>(rowB + (size_t)TS * g.D);
+    const int nw = fp_words(g.D);
+    // equal bytes >= d + padding bytes (zero on both sides)
+    const int zmax = 32 * nw - (d + 4 * nw - g.D);
+    uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * (3 * nw + 2);
+    uint32_t* fpA = mine;                        // 2 TS rows: tile P twice
+    uint32_t* fpB = fpA + (size_t)2 * TS * nw;   // TS rows: tile Q
+    uint32_t* idA = fpB + (size_t)TS * nw;
     uint32_t* idB = idA + TS;
 
-    unsigned long long ncoll = 0, nmemb = 0;
+    unsigned long long ncoll = 0, nmemb = 0, nscr = 0;
     const int64_t wins_per_seg = (g.ns + 63) / 64;
     const int64_t total_wins = wins_per_seg * g.nseg;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -476,15 +486,15 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
     for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < total_wins; win += nwaves) {
         const int seg = (int)(win / wins_per_seg);
         const int64_t base = (win - (int64_t)seg * wins_per_seg) * 64;
-        const int jb = seg / g.D, f = seg - jb * g.D;
+        const int jb = seg / g.Ds, f = seg - jb * g.Ds;
         const int j = g.j0 + jb;
-        const KT* ks = keys + (int64_t)seg * g.ns;
+        const uint32_t* ks = keys + (int64_t)seg * g.ns;
         const uint32_t* is = idx + (int64_t)seg * g.ns;
-        const RT* rbase = rows + (int64_t)jb * g.ns * g.D;
+        const uint32_t* fbase = fps + (int64_t)jb * g.ns * nw;
 
         const int64_t t = base + lane;
         const bool valid = t < g.ns;
-        const KT k = valid ? ks[t] : (KT)0;
+        const uint32_t k = valid ? ks[t] : 0u;
         const bool same_prev = valid && t > 0 && ks[t - 1] == k;
         const bool same_next = valid && t + 1 < g.ns && ks[t + 1] == k;
         const bool head = valid && !same_prev && same_next;
@@ -492,23 +502,22 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
         if (!heads) continue;
         const uint64_t tails = __ballot(valid && !same_next);
 
-        // Runs that close inside the window: a member's partners are lanes of
-        // this wave, so rows travel by cross-lane permutes (or, for wide rows,
-        // are read back through the cache) with no staging.
+        // runs that close inside the window
         const uint64_t hb = heads & le_mask, tb = tails & ge_mask;
         const bool inner = valid && (head || same_prev) && hb && tb;
-        const int h = 63 - __clzll((long long)(hb | 1ull));   // the run's head lane
+        const int h = 63 - __clzll((long long)(hb | 1ull));               // the run's head lane
         const int e = __ffsll((unsigned long long)(tb | (1ull << 63)));   // one past its tail lane
         const int L = e - h, q = lane - h;
         const int npart = inner ? (L - 1) / 2 + (((L & 1) == 0 && q < L / 2) ? 1 : 0) : 0;
         const uint64_t inner_bits = __ballot(inner);
+        ncoll += (unsigned long long)npart;
         if (lane == 0) nmemb += (unsigned long long)__popcll(inner_bits);
         if (inner_bits) {
             const uint32_t xu = valid ? is[t] : 0u;
-            RT own[kRowRegs];
+            const uint32_t* ofw = fbase + (int64_t)xu * nw;
+            uint32_t ofp[kFpRegs];
 #pragma unroll
-            for (int fp = 0; fp < kRowRegs; ++fp)
-                own[fp] = (inner && fp < g.D) ? rbase[(int64_t)xu * g.D + fp] : (RT)0;
+            for (int wd = 0; wd < kFpRegs; ++wd) ofp[wd] = (inner && wd < nw) ? ofw[wd] : 0u;
             for (int s = 1;; ++s) {
                 const bool act = s <= npart;
                 if (!__ballot(act)) break;
@@ -516,41 +525,29 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                 if (qs >= L) qs -= L;
                 const int pl = act ? h + qs : lane;
                 const uint32_t y = __shfl(xu, pl, 64);
-                int atleast[NLEV], below[NLEV];
-                if (g.D <= kRowRegs) {
+                int z = 0;
+                if (nw <= kFpRegs) {
                     // every lane takes part in the permutes; only active lanes use them
-                    const int cpf = count_row<RT, NLEV>(
-                        [&](int fp) { return own[fp] ^ (RT)__shfl(own[fp], pl, 64); }, g.D, f, kt, g.i_lo,
-                        atleast, below);
-                    if (act) {
-                        const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
-                        if (2 * (int64_t)(b - a) > (int64_t)w) {   // else a trivial match
-                            ++ncoll;
-                            emit_pair<NLEV>(a, b, atleast, below, cpf, g, j, d, cand, cap, cnt);
-                        }
-                    }
+                    z = screen(ofp, ofw, [&](int wd) { return (uint32_t)__shfl(ofp[wd], pl, 64); }, nw);
                 } else if (act) {
+                    const uint32_t* pfw = fbase + (int64_t)y * nw;
+                    z = screen(ofp, ofw, [&](int wd) { return pfw[wd]; }, nw);
+                }
+                if (act && z <= zmax) {
                     const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
-                    if (2 * (int64_t)(b - a) > (int64_t)w) {
-                        ++ncoll;
-                        const RT* ra = rbase + (int64_t)xu * g.D;
-                        const RT* rb = rbase + (int64_t)y * g.D;
-                        const int cpf = count_row<RT, NLEV>(
-                            [&](int fp) { return (fp < kRowRegs ? own[fp] : ra[fp]) ^ rb[fp]; }, g.D, f, kt,
-                            g.i_lo, atleast, below);
-                        emit_pair<NLEV>(a, b, atleast, below, cpf, g, j, d, cand, cap, cnt);
+                    if (2 * (int64_t)(b - a) > (int64_t)w) {   // else a trivial match
+                        ++nscr;
+                        judge_pair<NLEV>(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     }
                 }
             }
         }
 
-        // The one run that leaves the window (if its head is here): find its
-        // end 64 keys at a time, then enumerate it tile pair by tile pair
-        // from the wave's LDS region.
+        // the one run that leaves the window, if its head is here
         const uint64_t open = __ballot(head && !tb);
         if (!open) continue;
         const int hl = __ffsll((unsigned long long)open) - 1;
-        const KT hk = __shfl(k, hl, 64);
+        const uint32_t hk = __shfl(k, hl, 64);
         int64_t pos = base + 64, end = -1;
         while (end < 0) {
             const int64_t ee = pos + lane;
@@ -561,106 +558,109 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
         }
         const int64_t start = base + hl;
         const int len = (int)(end - start);
-        if (lane == 0) nmemb += (unsigned long long)len;
+        if (lane == 0) {
+            nmemb += (unsigned long long)len;
+            ncoll += (unsigned long long)len * (len - 1) / 2;
+        }
         const int T = (len + TS - 1) / TS;
         for (int tp = 0; tp < T; ++tp) {
-            for (int tq = tp; tq < T; ++tq) {
-                const int nA = min(TS, len - tp * TS), nB = min(TS, len - tq * TS);
-                const bool same = tp == tq;
-                wave_sync_lds();
-                for (int r = lane; r < nA; r += 64) {
-                    const uint32_t a = is[start + tp * TS + r];
-                    idA[r] = a;
-                    for (int fp = 0; fp < g.D; ++fp) rowA[(size_t)r * g.D + fp] = rbase[(int64_t)a * g.D + fp];
+            const int nA = min(TS, len - tp * TS);
+            wave_sync_lds();
+            for (int r = lane; r < nA; r += 64) {
+                const uint32_t a = is[start + tp * TS + r];
+                idA[r] = a;
+                for (int wd = 0; wd < nw; ++wd) {
+                    const uint32_t v = fbase[(int64_t)a * nw + wd];
+                    fpA[(size_t)r * nw + wd] = v;
+                    fpA[(size_t)(r + nA) * nw + wd] = v;
                 }
-                if (!same)
+            }
+            for (int tq = tp; tq < T; ++tq) {
+                const bool same = tq == tp;
+                const int nB = min(TS, len - tq * TS);
+                if (!same) {
+                    wave_sync_lds();
                     for (int r = lane; r < nB; r += 64) {
                         const uint32_t b = is[start + tq * TS + r];
                         idB[r] = b;
-                        for (int fp = 0; fp < g.D; ++fp) rowB[(size_t)r * g.D + fp] = rbase[(int64_t)b * g.D + fp];
+                        for (int wd = 0; wd < nw; ++wd) fpB[(size_t)r * nw + wd] = fbase[(int64_t)b * nw + wd];
                     }
+                }
                 wave_sync_lds();
-                const RT* rQ = same ? rowA : rowB;
-                const uint32_t* iQ = same ? idA : idB;
-                const int nq = same ? nA / 2 : nB;
                 for (int u = lane; u < nA; u += 64) {
-                    const uint32_t xu = idA[u];
-                    RT own[kRowRegs];
-                    const RT* ra = rowA + (size_t)u * g.D;
+                    const uint32_t* ofw = fpA + (size_t)u * nw;
+                    uint32_t ofp[kFpRegs];
 #pragma unroll
-                    for (int fp = 0; fp < kRowRegs; ++fp) own[fp] = fp < g.D ? ra[fp] : (RT)0;
-                    for (int v = 0; v < nq; ++v) {
-                        int qq = v;
-                        if (same) {
-                            if ((nA & 1) == 0 && v == nq - 1 && u >= nA / 2) continue;
-                            qq = u + 1 + v;
-                            if (qq >= nA) qq -= nA;
-                        }
-                        const uint32_t y = iQ[qq];
+                    for (int wd = 0; wd < kFpRegs; ++wd) ofp[wd] = wd < nw ? ofw[wd] : 0u;
+                    // partners: u + 1 + v in P (v < nA / 2, the last one only for
+                    // u < nA / 2 when nA is even), or every member v of Q
+                    const uint32_t* P0 = same ? fpA + (size_t)(u + 1) * nw : fpB;
+                    const int nv = same ? ((nA & 1) == 0 && u >= nA / 2 ? nA / 2 - 1 : nA / 2) : nB;
+                    for (int v = 0; v < nv; ++v) {
+                        const uint32_t* pfw = P0 + (size_t)v * nw;
+                        if (screen(ofp, ofw, [&](int wd) { return pfw[wd]; }, nw) > zmax) continue;
+                        int qq = same ? u + 1 + v : v;
+                        if (qq >= nA && same) qq -= nA;
+                        const uint32_t xu = idA[u], y = same ? idA[qq] : idB[qq];
                         const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
                         if (2 * (int64_t)(b - a) <= (int64_t)w) continue;   // trivial match
-                        ++ncoll;
-                        int atleast[NLEV], below[NLEV];
-                        const RT* rb = rQ + (size_t)qq * g.D;
-                        const int cpf = count_row<RT, NLEV>(
-                            [&](int fp) { return (fp < kRowRegs ? own[fp] : ra[fp]) ^ rb[fp]; }, g.D, f, kt,
-                            g.i_lo, atleast, below);
-                        emit_pair<NLEV>(a, b, atleast, below, cpf, g, j, d, cand, cap, cnt);
+                        ++nscr;
+                        judge_pair<NLEV>(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     }
                 }
             }
         }
     }
-    // collisions and run members: one pair of partial sums per work-group, no atomics
+    // pairs, run members and screened pairs: one triple of partial sums per
+    // work-group, no atomics
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) ncoll += __shfl_xor(ncoll, o, 64);
+    for (int o = 32; o >= 1; o >>= 1) {
+        ncoll += __shfl_xor(ncoll, o, 64);
+        nscr += __shfl_xor(nscr, o, 64);
+    }
     if (lane == 0) {
         coll_sh[wave] = ncoll;
         memb_sh[wave] = nmemb;
+        scr_sh[wave] = nscr;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         const int64_t b = blockIdx.x;
-        coll_part[2 * b] = coll_sh[0] + coll_sh[1] + coll_sh[2] + coll_sh[3];
-        coll_part[2 * b + 1] = memb_sh[0] + memb_sh[1] + memb_sh[2] + memb_sh[3];
+        coll_part[3 * b] = coll_sh[0] + coll_sh[1] + coll_sh[2] + coll_sh[3];
+        coll_part[3 * b + 1] = memb_sh[0] + memb_sh[1] + memb_sh[2] + memb_sh[3];
+        coll_part[3 * b + 2] = scr_sh[0] + scr_sh[1] + scr_sh[2] + scr_sh[3];
     }
 }
 
 __global__ __launch_bounds__(1024) void k_sum_partials(const unsigned long long* __restrict__ part,
                                                        int64_t count, Counters* __restrict__ cnt)
 {
-    __shared__ unsigned long long sh[32];
-    unsigned long long s = 0, m = 0;
-    for (int64_t q = threadIdx.x; q < count; q += 1024) {
-        s += part[2 * q];
-        m += part[2 * q + 1];
-    }
+    __shared__ unsigned long long sh[3][16];
+    unsigned long long v[3] = {0, 0, 0};
+    for (int64_t q = threadIdx.x; q < count; q += 1024)
+        for (int c = 0; c < 3; ++c) v[c] += part[3 * q + c];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        s += __shfl_xor(s, o, 64);
-        m += __shfl_xor(m, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        sh[threadIdx.x >> 6] = s;
-        sh[16 + (threadIdx.x >> 6)] = m;
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[c] += __shfl_xor(v[c], o, 64);
+        if ((threadIdx.x & 63) == 0) sh[c][threadIdx.x >> 6] = v[c];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0, u = 0;
-        for (int q = 0; q < 16; ++q) {
-            t += sh[q];
-            u += sh[16 + q];
-        }
-        cnt->n_coll += t;
-        cnt->n_memb += u;
+        unsigned long long t[3] = {0, 0, 0};
+        for (int c = 0; c < 3; ++c)
+            for (int q = 0; q < 16; ++q) t[c] += sh[c][q];
+        cnt->n_coll += t[0];
+        cnt->n_memb += t[1];
+        cnt->n_screen += t[2];
     }
 }
 
-// Members per tile: a wave's two tiles take at most ~6 KB of LDS when rows
-// are narrow, so that many work-groups stay resident.
-static int tile_size(int D, int rb)
+// Members per tile: a wave's region (tile P twice, tile Q, indices) stays
+// within ~12 KB, so that several work-groups stay resident per CU.
+static int tile_size(int D)
 {
-    int ts = 12288 / (2 * (4 + D * rb));   // per wave
+    int ts = 12288 / (4 * (3 * fp_words(D) + 2));
     ts = ts > 64 ? 64 : ts;
     return ts < 16 ? 16 : (ts / 16) * 16;
 }
@@ -668,51 +668,36 @@ static int tile_size(int D, int rb)
 constexpr int kEnumBlocks = 2048;   // persistent grid: 8 work-groups per CU
 int64_t enum_partials(const StepGeom&) { return kEnumBlocks; }
 
-template <typename KT, typename RT, int NLEV>
-static hipError_t go_enum(const StepGeom& g, const KT* keys, const uint32_t* idx, const RT* rows,
-                          int kt, int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
-                          unsigned long long* part, hipStream_t s)
+template <int NLEV>
+static hipError_t go_enum(const StepGeom& g, const uint32_t* keys, const uint32_t* idx, const uint32_t* H,
+                          const uint32_t* fps, int kt, int d, int w, Cand* cand, uint32_t cap,
+                          Counters* cnt, unsigned long long* part, hipStream_t s)
 {
-    const int TS = tile_size(g.D, (int)sizeof(RT));
-    const size_t lds = (size_t)4 * 2 * TS * (4 + g.D * sizeof(RT));   // 4 waves
+    const int TS = tile_size(g.D);
+    const size_t lds = (size_t)4 * TS * (3 * fp_words(g.D) + 2) * 4;   // 4 waves
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_enum_runs<KT, RT, NLEV>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_enum_runs<KT, RT, NLEV>), dim3(kEnumBlocks), dim3(256), lds, s, keys, idx, rows,
-                       g, kt, d, w, TS, cand, cap, cnt, part);
+        (void)hipFuncSetAttribute((const void*)k_enum_runs<NLEV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    hipLaunchKernelGGL((k_enum_runs<NLEV>), dim3(kEnumBlocks), dim3(256), lds, s, keys, idx, H, fps, g, kt, d,
+                       w, TS, cand, cap, cnt, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, enum_partials(g), cnt);
     return hipGetLastError();
 }
 
-template <typename KT, typename RT>
-static hipError_t go_enum_lev(const StepGeom& g, const KT* keys, const uint32_t* idx, const RT* rows,
-                              int kt, int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
-                              unsigned long long* part, hipStream_t s)
+hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint32_t* H,
+                       const uint32_t* fps, int kt, int d, int w, Cand* cand, uint32_t cap,
+                       Counters* cnt, unsigned long long* part, hipStream_t s)
 {
+    if (g.i_lo > 4) return hipErrorInvalidValue;   // keys are 32-bit: prefixes of at most 4 symbols
+    const uint32_t* k = (const uint32_t*)b.keys[buf];
     switch (g.i - g.i_lo + 2) {
-    case 2: return go_enum<KT, RT, 2>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
-    case 3: return go_enum<KT, RT, 3>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
-    case 4: return go_enum<KT, RT, 4>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
-    case 5: return go_enum<KT, RT, 5>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
-    case 6: return go_enum<KT, RT, 6>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
-    default: return go_enum<KT, RT, 9>(g, keys, idx, rows, kt, d, w, cand, cap, cnt, part, s);
+    case 2: return go_enum<2>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
+    case 3: return go_enum<3>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
+    case 4: return go_enum<4>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
+    case 5: return go_enum<5>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
+    case 6: return go_enum<6>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
+    default: return hipErrorInvalidValue;   // groups span at most 5 rounds
     }
-}
-
-hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const void* rows, int kt,
-                       int d, int w, Cand* cand, uint32_t cap, Counters* cnt,
-                       unsigned long long* part, hipStream_t s)
-{
-    if (g.i_lo <= 4) {
-        const uint32_t* k = (const uint32_t*)b.keys[buf];
-        if (kt <= 4)
-            return go_enum_lev<uint32_t, uint32_t>(g, k, b.idx[buf], (const uint32_t*)rows, kt, d, w,
-                                                   cand, cap, cnt, part, s);
-        return go_enum_lev<uint32_t, uint64_t>(g, k, b.idx[buf], (const uint64_t*)rows, kt, d, w, cand,
-                                               cap, cnt, part, s);
-    }
-    return go_enum_lev<uint64_t, uint64_t>(g, (const uint64_t*)b.keys[buf], b.idx[buf],
-                                           (const uint64_t*)rows, kt, d, w, cand, cap, cnt, part, s);
 }
 
 // ------------------------------------------------------------------ verification
@@ -1102,7 +1087,6 @@ __global__ void k_allpairs(int64_t ns, int w, int64_t row_lo, int64_t row_hi, in
 __global__ void k_set_count(Counters* cnt, uint32_t v)
 {
     cnt->n_cand = v;
-    cnt->n_runs = 0;
 }
 
 hipError_t launch_allpairs(int64_t ns, int w, int64_t row_lo, int64_t row_hi, int64_t base,

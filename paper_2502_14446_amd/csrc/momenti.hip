@@ -149,10 +149,10 @@ static uint8_t to_e4m3_bits(double v)
 // ------------------------------------------------------------------ profiling
 // Optional per-kernel timing with HIP events recorded on the plan's stream
 // around each launch; folded into totals whenever the host synchronises.
-enum KernelId { KI_STATS, KI_RSAMPLE, KI_PROJ, KI_HIST, KI_SCAN, KI_SCATTER, KI_KEYTABLE, KI_ENUM,
+enum KernelId { KI_STATS, KI_RSAMPLE, KI_PROJ, KI_HIST, KI_SCAN, KI_SCATTER, KI_FPTABLE, KI_ENUM,
                 KI_VERIFY, KI_FILTER, KI_POOL, KI_ALLPAIRS, KI_COUNT };
 static const char* const kKernelNames[KI_COUNT] = {
-    "stats", "rsample", "proj", "sort_hist", "sort_scan", "sort_scatter", "keytable", "enum",
+    "stats", "rsample", "proj", "sort_hist", "sort_scan", "sort_scatter", "fptable", "enum",
     "verify", "pool_filter", "pool", "allpairs"};
 
 struct KTotal {
@@ -195,8 +195,8 @@ struct momenti_plan {
 
     // traversal buffers
     SortBufs sb{};
-    int sb_nseg = 0;
-    void* rows = nullptr;       // key table of a batch: [rep][window][dim], up to 8 B each
+    int sb_nseg = 0, sb_reps = 0;
+    uint32_t* fps = nullptr;    // fingerprint rows of a batch: [rep][window][fp_words(D)]
     unsigned long long* coll_part = nullptr;   // per-work-group collision counts
     int64_t coll_parts = 0;
     Cand* cand = nullptr;       // candidates of one launch batch
@@ -366,13 +366,14 @@ static void release_search(momenti_plan* p)
     }
     dfree(p, p->sb.hist, (size_t)p->sb_nseg * 256 * p->sb.tiles * 4);
     p->sb.hist = nullptr;
-    dfree(p, p->rows, (size_t)p->sb_nseg * p->ns * 8);
-    p->rows = nullptr;
+    dfree(p, p->fps, (size_t)p->sb_reps * fp_words(p->D) * p->ns * 4);
+    p->fps = nullptr;
     p->sb_nseg = 0;
+    p->sb_reps = 0;
     dfree(p, p->cand, (size_t)p->cap * sizeof(Cand));
     dfree(p, p->vrec, (size_t)p->cap * sizeof(VRec));
     p->cand = nullptr; p->vrec = nullptr; p->cap = 0;
-    dfree(p, p->coll_part, (size_t)p->coll_parts * 16);
+    dfree(p, p->coll_part, (size_t)p->coll_parts * 24);
     p->coll_part = nullptr; p->coll_parts = 0;
     dfree(p, p->store, (size_t)p->store_cap * sizeof(VRec));
     dfree(p, p->keep, (size_t)p->store_cap * 8);
@@ -757,26 +758,30 @@ static bool stop_holds(double dist_max, double r, int d, int i, int J, int K, in
 static Counters* st_counters(momenti_plan* p) { return (Counters*)p->status; }
 static PoolState* st_pool(momenti_plan* p) { return (PoolState*)(p->status + 64); }
 
-// double-buffered keys and indices, digit histograms, and the key table
-static size_t sort_bytes(int64_t nseg, int64_t ns, int64_t tiles)
+// double-buffered keys and indices and digit histograms of reps * Ds
+// segments, and the fingerprint rows of reps repetitions
+static size_t sort_bytes(int64_t reps, int64_t Ds, int64_t D, int64_t ns, int64_t tiles)
 {
-    return (size_t)nseg * ns * (8 + 8 + 4 + 4 + 8) + (size_t)nseg * 256 * tiles * 4;
+    return (size_t)(reps * Ds) * ns * (8 + 8 + 4 + 4) + (size_t)(reps * Ds) * 256 * tiles * 4 +
+           (size_t)reps * ns * 4 * fp_words((int)D);
 }
 static size_t cand_bytes(uint32_t cap) { return (size_t)cap * (sizeof(Cand) + sizeof(VRec)); }
 static size_t store_bytes(uint32_t cap) { return (size_t)cap * (sizeof(VRec) + 8); }
 
-static int alloc_sort(momenti_plan* p, int nseg)
+static int alloc_sort(momenti_plan* p, int reps, int Ds)
 {
     const int64_t tiles = (p->ns + kSortTile - 1) / kSortTile;
+    const int nseg = reps * Ds;
     int rc;
     p->sb.tiles = tiles;
+    p->sb_nseg = nseg;
+    p->sb_reps = reps;
     for (int q = 0; q < 2; ++q) {
         if ((rc = dalloc(p, &p->sb.keys[q], (size_t)nseg * p->ns * 8))) return rc;
         if ((rc = dalloc_t(p, &p->sb.idx[q], (size_t)nseg * p->ns * 4))) return rc;
     }
     if ((rc = dalloc_t(p, &p->sb.hist, (size_t)nseg * 256 * tiles * 4))) return rc;
-    if ((rc = dalloc(p, &p->rows, (size_t)nseg * p->ns * 8))) return rc;
-    p->sb_nseg = nseg;
+    if ((rc = dalloc_t(p, &p->fps, (size_t)reps * fp_words(p->D) * p->ns * 4))) return rc;
     return MOMENTI_OK;
 }
 
@@ -919,23 +924,27 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         return fail(MOMENTI_E_NOMEM, "pinned host allocation failed");
     if ((rc = alloc_pool(p, P, k, max_steps))) return rc;
     const int64_t tiles = (p->ns + kSortTile - 1) / kSortTile;
+    // A pair colliding in >= d dimensions has its lowest colliding dimension
+    // below D - d + 1, and only that dimension's segment reports it: the
+    // last d - 1 dimensions need no segments.
+    const int Ds = std::max(1, p->D - d + 1);
     const uint64_t left0 = p->mem_limit - p->bytes;
     uint32_t cap = 1u << 20;
-    while (cap > (1u << 14) && cand_bytes(cap) + store_bytes(cap) + sort_bytes(p->D, p->ns, tiles) > left0)
+    while (cap > (1u << 14) && cand_bytes(cap) + store_bytes(cap) + sort_bytes(1, Ds, p->D, p->ns, tiles) > left0)
         cap >>= 1;
     if ((rc = alloc_cand(p, cap))) return rc;
     if ((rc = grow_store(p, cap, 0))) return rc;
     int Bmax = p->o.batch_reps ? p->o.batch_reps : 16;
     Bmax = std::max(1, std::min({Bmax, p->L, 64}));
     int B = Bmax;
-    while (B > 1 && sort_bytes((int64_t)B * p->D, p->ns, tiles) > p->mem_limit - p->bytes) B >>= 1;
-    if ((rc = alloc_sort(p, B * p->D))) return rc;
+    while (B > 1 && sort_bytes(B, Ds, p->D, p->ns, tiles) > p->mem_limit - p->bytes) B >>= 1;
+    if ((rc = alloc_sort(p, B, Ds))) return rc;
     {
         StepGeom gmax{};
         gmax.ns = p->ns;
-        gmax.nseg = B * p->D;
+        gmax.nseg = B * Ds;
         p->coll_parts = enum_partials(gmax);
-        if ((rc = dalloc_t(p, &p->coll_part, (size_t)p->coll_parts * 16))) return rc;
+        if ((rc = dalloc_t(p, &p->coll_part, (size_t)p->coll_parts * 24))) return rc;
     }
     R.batch_reps = B;
 
@@ -950,6 +959,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         return v ? std::atoi(v) : 0;
     }();
     const double elem_x = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
+    unsigned long long n_screened = 0;
 
 restart:
     HIP_OK(launch_pool_reset(st_pool(p), p->st));
@@ -960,10 +970,10 @@ restart:
         const int s0 = (p->K - i_hi) * p->L;
         const int nsteps = (i_hi - i_lo + 1) * p->L;
         if (verbose) {
-            std::fprintf(stderr, "[momenti] rounds %d..%d: %.1f ms, steps %lld, collisions %lld, candidates %lld |",
+            std::fprintf(stderr, "[momenti] rounds %d..%d: %.1f ms, steps %lld, collisions %lld, screened %llu, candidates %lld |",
                          i_hi, i_lo,
                          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
-                         (long long)R.n_steps, (long long)R.n_collisions, (long long)R.n_cand);
+                         (long long)R.n_steps, (long long)R.n_collisions, n_screened, (long long)R.n_cand);
             for (int q = 0; q < KI_COUNT; ++q)
                 if (p->prof.tot[q].launches) std::fprintf(stderr, " %s %.1f", kKernelNames[q], p->prof.tot[q].ms);
             std::fprintf(stderr, "\n");
@@ -973,7 +983,7 @@ restart:
             const int Bc = std::min(B, p->L - j0);
             StepGeom g;
             g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
-            g.j0 = j0; g.nseg = Bc * p->D; g.i = i_hi; g.K = p->K; g.i_lo = i_lo;
+            g.j0 = j0; g.Ds = Ds; g.nseg = Bc * Ds; g.i = i_hi; g.K = p->K; g.i_lo = i_lo;
             HIP_OK(launch_zero(p->status, 64, p->st));
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
@@ -987,14 +997,14 @@ restart:
                 buf ^= 1;
             }
             const int kt = std::min(i_hi + 1, p->K);
-            const double rb = kt <= 4 ? 4.0 : 8.0;
-            HIP_OK(timed(p, KI_KEYTABLE, (double)Bc * p->ns * p->D * (8.0 + rb), 0.0, [&] {
-                return launch_keytable(p->H, g, Bc, kt, p->rows, p->st);
+            const int nw = fp_words(p->D);
+            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * nw), 0.0, [&] {
+                return launch_fptable(p->H, g, Bc, p->fps, p->st);
             }));
             int enum_slot = -1, verify_slot = -1;
             HIP_OK(timed(p, KI_ENUM, 0.0, 0.0, [&] {
-                return launch_enum(g, p->sb, buf, p->rows, kt, d, p->w, p->cand, p->cap, st_counters(p),
-                                   p->coll_part, p->st);
+                return launch_enum(g, p->sb, buf, p->H, p->fps, kt, d, p->w, p->cand, p->cap,
+                                   st_counters(p), p->coll_part, p->st);
             }, &enum_slot));
             HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
                 return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
@@ -1005,12 +1015,12 @@ restart:
             HIP_OK(hipStreamSynchronize(p->st));
             std::memcpy(&cnt, p->host_status, sizeof cnt);
             {
-                // sizes known only now: the enumeration staged every run member
-                // (key, index, key-table row) once per tile pair; verification
-                // read 2 D w samples per candidate
+                // sizes known only now: the enumeration read every key once and
+                // every run member's index and fingerprint row once (pairs that
+                // pass the screen re-read 4 D index words: negligible);
+                // verification read 2 D w samples per candidate
                 const uint32_t nc = std::min(cnt.n_cand, p->cap);
-                const double rbytes = (std::min(i_hi + 1, p->K) <= 4 ? 4.0 : 8.0) * p->D;
-                prof_set(p, enum_slot, elems * 2.0 * kb + (double)cnt.n_memb * (kb + 4.0 + rbytes), 0.0);
+                prof_set(p, enum_slot, elems * kb + (double)cnt.n_memb * (4.0 + 4.0 * nw), 0.0);
                 prof_set(p, verify_slot, (double)nc * (2.0 * p->D * p->w * elem_x + 32.0 * p->D + sizeof(VRec)),
                          (double)nc * 6.0 * p->D * p->w);
                 prof_flush(p);
@@ -1035,6 +1045,7 @@ restart:
                 stored += cnt.n_cand;
             }
             R.n_collisions += (int64_t)cnt.n_coll;
+            n_screened += cnt.n_screen;
             R.n_cand += cnt.n_cand;
             R.n_verified += cnt.n_cand;
             if (tracing && p->tr_cand && cnt.n_cand) {
