@@ -93,8 +93,13 @@ struct StepGeom {
     int i, K;            // highest round of the group; K
     int i_lo;            // lowest round of the group: segments are sorted by this prefix length
 };
-// 32-bit words of a window's fingerprint row (one byte per dimension)
-__host__ __device__ inline int fp_words(int D) { return (D + 3) / 4; }
+// 32-bit words of a window's fingerprint row: one byte per dimension, padded
+// with zero bytes to 1, 2, 4, 8 or a multiple of 8 words
+__host__ __device__ inline int fp_words(int D)
+{
+    const int w = (D + 3) / 4;
+    return w <= 1 ? 1 : w <= 2 ? 2 : w <= 4 ? 4 : (w + 7) / 8 * 8;
+}
 constexpr int kSortTile = 4096;
 
 // Stable LSD sort of every segment of the batch by its length-i hash prefix,

@@ -25,6 +25,8 @@
 //                   of the pool, recomputed after each repetition, with a
 //                   snapshot per repetition for the host's stopping check.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "internal.h"
@@ -341,13 +343,16 @@ __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H,
     const int jb = (int)(gid / g.ns);
     const int64_t a = gid - (int64_t)jb * g.ns;
     const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
-    uint32_t* fw = fps + gid * fp_words(g.D);
+    const int nw = fp_words(g.D);
+    uint32_t* fw = fps + gid * nw;
     uint32_t word = 0;
-    for (int f = 0; f < g.D; ++f) {
-        const uint32_t L = H[((int64_t)f * g.NF + l) * g.ns + a];
-        const uint32_t R = H[((int64_t)f * g.NF + g.NL + r) * g.ns + a];
-        word |= prefix_digest(make_key<uint64_t>(L, R, g.i_lo), g.i_lo) << (8 * (f & 3));
-        if ((f & 3) == 3 || f == g.D - 1) {
+    for (int f = 0; f < 4 * nw; ++f) {
+        if (f < g.D) {
+            const uint32_t L = H[((int64_t)f * g.NF + l) * g.ns + a];
+            const uint32_t R = H[((int64_t)f * g.NF + g.NL + r) * g.ns + a];
+            word |= prefix_digest(make_key<uint64_t>(L, R, g.i_lo), g.i_lo) << (8 * (f & 3));
+        }
+        if ((f & 3) == 3) {
             fw[f >> 2] = word;
             word = 0;
         }
@@ -369,20 +374,20 @@ __device__ inline int nonzero_bytes_28(uint32_t x)
     return __popc(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
 }
 
-constexpr int kFpRegs = 8;   // fingerprint rows up to this many words (32 dimensions) stay in registers
+constexpr int kFpRegs = 8;   // fingerprint words kept in registers (32 dimensions)
 
-// Sum over the words of nonzero_bytes_28(own ^ partner): the lane's own row
-// (first words in registers, the rest at own_tail) against the partner's
-// (pw). A pair has at least `need` equal bytes iff the sum is <= 32 nw - need.
-template <typename GetW>
-__device__ inline int screen(const uint32_t (&ofp)[kFpRegs], const uint32_t* own_tail, const GetW& pw,
-                             int nw)
+// Sum over the nw words of nonzero_bytes_28(own ^ partner): the lane's own
+// row (its first NW words in registers, the rest at own_tail) against the
+// partner's (pw). With D dimensions the rows have 4 nw - D padding bytes, zero
+// on both sides, so a pair has >= d equal digests iff the sum is
+// <= 28 nw + D - d.
+template <int NW, typename GetW>
+__device__ inline int screen(const uint32_t (&ofp)[NW], const uint32_t* own_tail, const GetW& pw, int nw)
 {
     int z = 0;
 #pragma unroll
-    for (int wd = 0; wd < kFpRegs; ++wd)
-        if (wd < nw) z += nonzero_bytes_28(ofp[wd] ^ pw(wd));
-    for (int wd = kFpRegs; wd < nw; ++wd) z += nonzero_bytes_28(own_tail[wd] ^ pw(wd));
+    for (int wd = 0; wd < NW; ++wd) z += nonzero_bytes_28(ofp[wd] ^ pw(wd));
+    for (int wd = NW; wd < nw; ++wd) z += nonzero_bytes_28(own_tail[wd] ^ pw(wd));
     return z;
 }
 
@@ -401,37 +406,37 @@ __device__ inline int common_symbols(uint64_t x, uint64_t y, int kt)
 // round i of the group at which it collides in f, iff W_i = #{f' : cp >= i}
 // >= d, no f' < f has cp >= i (it is reported once, from its lowest colliding
 // dimension) and, below round K, W_{i+1} < d (section 6.2: pairs seen one
-// symbol deeper are skipped). NLEV = rounds of the group + 1.
-template <int NLEV>
-__device__ void judge_pair(uint32_t a, uint32_t b, const uint32_t* __restrict__ H, const StepGeom& g,
-                           int f, int j, int kt, int d, Cand* __restrict__ cand, uint32_t cap,
-                           Counters* __restrict__ cnt)
+// symbol deeper are skipped).
+constexpr int kMaxLev = 6;   // rounds of a group + 1
+
+__device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __restrict__ H, const StepGeom& g,
+                                  int f, int j, int kt, int d, Cand* __restrict__ cand, uint32_t cap,
+                                  Counters* __restrict__ cnt)
 {
     const int l = j / g.m, r = j - l * g.m;
-    int atleast[NLEV], below[NLEV];
-#pragma unroll
-    for (int lv = 0; lv < NLEV; ++lv) { atleast[lv] = 0; below[lv] = 0; }
+    const int nlev = g.i - g.i_lo + 2;
+    // per level lv (round i_lo + lv), byte lv counts the dimensions colliding
+    // there (atl) and those among them below f (blw); D <= 128 fits a byte
+    uint64_t atl = 0, blw = 0;
     int cpf = 0;
     for (int fp = 0; fp < g.D; ++fp) {
         const uint32_t* Hl = H + ((int64_t)fp * g.NF + l) * g.ns;
         const uint32_t* Hr = H + ((int64_t)fp * g.NF + g.NL + r) * g.ns;
         const int cp = common_symbols(make_key<uint64_t>(Hl[a], Hr[a], kt), make_key<uint64_t>(Hl[b], Hr[b], kt), kt);
-#pragma unroll
-        for (int lv = 0; lv < NLEV; ++lv) {
-            const bool eq = cp >= g.i_lo + lv;
-            atleast[lv] += eq;
-            below[lv] += eq && fp < f;
-        }
+        int nl = cp - g.i_lo + 1;   // levels 0 .. nl - 1 collide
+        nl = nl < 0 ? 0 : (nl > nlev ? nlev : nl);
+        const uint64_t ones = nl ? 0x010101010101ull & (~0ull >> (64 - 8 * nl)) : 0ull;
+        atl += ones;
+        if (fp < f) blw += ones;
         if (fp == f) cpf = cp;
     }
-    if (atleast[0] < d) return;   // the digests agreed by chance
+    if ((int)(atl & 0xFF) < d) return;   // the digests agreed by chance
     const int top = cpf < g.i ? cpf : g.i;
-#pragma unroll
-    for (int lv = NLEV - 2; lv >= 0; --lv) {
+    for (int lv = nlev - 2; lv >= 0; --lv) {
         const int i = g.i_lo + lv;
-        if (i > top) continue;                    // rounds i_lo .. top
-        if (atleast[lv] < d || below[lv] > 0) continue;
-        if (i < g.K && atleast[lv + 1] >= d) continue;
+        if (i > top) continue;   // rounds i_lo .. min(top, i_hi)
+        if ((int)((atl >> (8 * lv)) & 0xFF) < d || ((blw >> (8 * lv)) & 0xFF) != 0) continue;
+        if (i < g.K && (int)((atl >> (8 * (lv + 1))) & 0xFF) >= d) continue;
         const uint32_t pos = atomicAdd(&cnt->n_cand, 1u);
         if (pos < cap) cand[pos] = Cand{a, b, (uint32_t)j, (uint32_t)i};
     }
@@ -454,7 +459,7 @@ __device__ void judge_pair(uint32_t a, uint32_t b, const uint32_t* __restrict__ 
 //    member u of P and walks its partners in tile Q >= P (all lanes read the
 //    same partner of Q at once: an LDS broadcast).
 // Pairs that pass the screen and are not trivial matches go to judge_pair.
-template <int NLEV>
+template <int NW>
 __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
                                                    const uint32_t* __restrict__ H,
@@ -466,9 +471,8 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ unsigned long long coll_sh[4], memb_sh[4], scr_sh[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nw = fp_words(g.D);
-    // equal bytes >= d + padding bytes (zero on both sides)
-    const int zmax = 32 * nw - (d + 4 * nw - g.D);
+    const int nw = fp_words(g.D);   // NW = min(nw, kFpRegs)
+    const int zmax = 28 * nw + g.D - d;
     uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * (3 * nw + 2);
     uint32_t* fpA = mine;                        // 2 TS rows: tile P twice
     uint32_t* fpB = fpA + (size_t)2 * TS * nw;   // TS rows: tile Q
@@ -515,9 +519,9 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
         if (inner_bits) {
             const uint32_t xu = valid ? is[t] : 0u;
             const uint32_t* ofw = fbase + (int64_t)xu * nw;
-            uint32_t ofp[kFpRegs];
+            uint32_t ofp[NW];
 #pragma unroll
-            for (int wd = 0; wd < kFpRegs; ++wd) ofp[wd] = (inner && wd < nw) ? ofw[wd] : 0u;
+            for (int wd = 0; wd < NW; ++wd) ofp[wd] = inner ? ofw[wd] : 0u;
             for (int s = 1;; ++s) {
                 const bool act = s <= npart;
                 if (!__ballot(act)) break;
@@ -526,18 +530,18 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
                 const int pl = act ? h + qs : lane;
                 const uint32_t y = __shfl(xu, pl, 64);
                 int z = 0;
-                if (nw <= kFpRegs) {
+                if (nw == NW) {
                     // every lane takes part in the permutes; only active lanes use them
-                    z = screen(ofp, ofw, [&](int wd) { return (uint32_t)__shfl(ofp[wd], pl, 64); }, nw);
+                    z = screen<NW>(ofp, ofw, [&](int wd) { return (uint32_t)__shfl(ofp[wd], pl, 64); }, nw);
                 } else if (act) {
                     const uint32_t* pfw = fbase + (int64_t)y * nw;
-                    z = screen(ofp, ofw, [&](int wd) { return pfw[wd]; }, nw);
+                    z = screen<NW>(ofp, ofw, [&](int wd) { return pfw[wd]; }, nw);
                 }
                 if (act && z <= zmax) {
                     const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
                     if (2 * (int64_t)(b - a) > (int64_t)w) {   // else a trivial match
                         ++nscr;
-                        judge_pair<NLEV>(a, b, H, g, f, j, kt, d, cand, cap, cnt);
+                        judge_pair(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     }
                 }
             }
@@ -589,23 +593,41 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
                 wave_sync_lds();
                 for (int u = lane; u < nA; u += 64) {
                     const uint32_t* ofw = fpA + (size_t)u * nw;
-                    uint32_t ofp[kFpRegs];
+                    uint32_t ofp[NW];
 #pragma unroll
-                    for (int wd = 0; wd < kFpRegs; ++wd) ofp[wd] = wd < nw ? ofw[wd] : 0u;
+                    for (int wd = 0; wd < NW; ++wd) ofp[wd] = ofw[wd];
                     // partners: u + 1 + v in P (v < nA / 2, the last one only for
                     // u < nA / 2 when nA is even), or every member v of Q
                     const uint32_t* P0 = same ? fpA + (size_t)(u + 1) * nw : fpB;
                     const int nv = same ? ((nA & 1) == 0 && u >= nA / 2 ? nA / 2 - 1 : nA / 2) : nB;
-                    for (int v = 0; v < nv; ++v) {
-                        const uint32_t* pfw = P0 + (size_t)v * nw;
-                        if (screen(ofp, ofw, [&](int wd) { return pfw[wd]; }, nw) > zmax) continue;
+                    auto check = [&](int v) {
                         int qq = same ? u + 1 + v : v;
-                        if (qq >= nA && same) qq -= nA;
+                        if (same && qq >= nA) qq -= nA;
                         const uint32_t xu = idA[u], y = same ? idA[qq] : idB[qq];
                         const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
-                        if (2 * (int64_t)(b - a) <= (int64_t)w) continue;   // trivial match
+                        if (2 * (int64_t)(b - a) <= (int64_t)w) return;   // trivial match
                         ++nscr;
-                        judge_pair<NLEV>(a, b, H, g, f, j, kt, d, cand, cap, cnt);
+                        judge_pair(a, b, H, g, f, j, kt, d, cand, cap, cnt);
+                    };
+                    int v = 0;
+                    // four partners per step: their LDS reads are in flight together
+                    for (; v + 4 <= nv; v += 4) {
+                        const uint32_t* p = P0 + (size_t)v * nw;
+                        const int z0 = screen<NW>(ofp, ofw, [&](int wd) { return p[wd]; }, nw);
+                        const int z1 = screen<NW>(ofp, ofw, [&](int wd) { return p[nw + wd]; }, nw);
+                        const int z2 = screen<NW>(ofp, ofw, [&](int wd) { return p[2 * nw + wd]; }, nw);
+                        const int z3 = screen<NW>(ofp, ofw, [&](int wd) { return p[3 * nw + wd]; }, nw);
+                        uint32_t hit = (uint32_t)(z0 <= zmax) | ((uint32_t)(z1 <= zmax) << 1) |
+                                       ((uint32_t)(z2 <= zmax) << 2) | ((uint32_t)(z3 <= zmax) << 3);
+                        while (hit) {
+                            const int bit = __ffs(hit) - 1;
+                            hit &= hit - 1;
+                            check(v + bit);
+                        }
+                    }
+                    for (; v < nv; ++v) {
+                        const uint32_t* p = P0 + (size_t)v * nw;
+                        if (screen<NW>(ofp, ofw, [&](int wd) { return p[wd]; }, nw) <= zmax) check(v);
                     }
                 }
             }
@@ -665,10 +687,22 @@ static int tile_size(int D)
     return ts < 16 ? 16 : (ts / 16) * 16;
 }
 
-constexpr int kEnumBlocks = 2048;   // persistent grid: 8 work-groups per CU
+constexpr int kEnumBlocks = 2048;   // persistent grid: at most 8 work-groups per CU
 int64_t enum_partials(const StepGeom&) { return kEnumBlocks; }
 
-template <int NLEV>
+// Work-groups that are resident at once (so that none waits for a slot):
+// CUs times the occupancy of the kernel at this LDS size, capped.
+static int resident_blocks(const void* fn, size_t lds)
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, lds) != hipSuccess || ncu < 1 || per < 1)
+        return kEnumBlocks;
+    return std::min(kEnumBlocks, ncu * std::min(per, 8));
+}
+
+template <int NW>
 static hipError_t go_enum(const StepGeom& g, const uint32_t* keys, const uint32_t* idx, const uint32_t* H,
                           const uint32_t* fps, int kt, int d, int w, Cand* cand, uint32_t cap,
                           Counters* cnt, unsigned long long* part, hipStream_t s)
@@ -676,11 +710,14 @@ static hipError_t go_enum(const StepGeom& g, const uint32_t* keys, const uint32_
     const int TS = tile_size(g.D);
     const size_t lds = (size_t)4 * TS * (3 * fp_words(g.D) + 2) * 4;   // 4 waves
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_enum_runs<NLEV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)k_enum_runs<NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-    hipLaunchKernelGGL((k_enum_runs<NLEV>), dim3(kEnumBlocks), dim3(256), lds, s, keys, idx, H, fps, g, kt, d,
-                       w, TS, cand, cap, cnt, part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, enum_partials(g), cnt);
+    static int nblk[kFpRegs + 1][2] = {};   // per instantiation and LDS regime (fixed per D)
+    int& nb = nblk[NW][lds > 65536];
+    if (!nb) nb = resident_blocks((const void*)k_enum_runs<NW>, lds);
+    hipLaunchKernelGGL((k_enum_runs<NW>), dim3(nb), dim3(256), lds, s, keys, idx, H, fps, g, kt, d, w, TS,
+                       cand, cap, cnt, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, (int64_t)nb, cnt);
     return hipGetLastError();
 }
 
@@ -688,15 +725,14 @@ hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint
                        const uint32_t* fps, int kt, int d, int w, Cand* cand, uint32_t cap,
                        Counters* cnt, unsigned long long* part, hipStream_t s)
 {
-    if (g.i_lo > 4) return hipErrorInvalidValue;   // keys are 32-bit: prefixes of at most 4 symbols
+    if (g.i_lo > 4) return hipErrorInvalidValue;          // keys are 32-bit: prefixes of <= 4 symbols
+    if (g.i - g.i_lo + 2 > kMaxLev) return hipErrorInvalidValue;
     const uint32_t* k = (const uint32_t*)b.keys[buf];
-    switch (g.i - g.i_lo + 2) {
+    switch (fp_words(g.D)) {
+    case 1: return go_enum<1>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
     case 2: return go_enum<2>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
-    case 3: return go_enum<3>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
     case 4: return go_enum<4>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
-    case 5: return go_enum<5>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
-    case 6: return go_enum<6>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
-    default: return hipErrorInvalidValue;   // groups span at most 5 rounds
+    default: return go_enum<kFpRegs>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
     }
 }
 
