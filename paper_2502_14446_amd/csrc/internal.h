@@ -43,7 +43,7 @@ struct Snap {
 // Device counters of one batch of traversal steps.
 struct Counters {
     uint32_t n_cand;             // candidates emitted (may exceed the buffer)
-    uint32_t pad;
+    uint32_t max_run;            // longest run that left its 64-element window
     unsigned long long n_coll;   // pairs of equal prefixes in the segments (trivial matches included)
     unsigned long long n_memb;   // elements in runs of >= 2
     unsigned long long n_screen; // non-trivial pairs that passed the fingerprint screen
@@ -100,6 +100,9 @@ __host__ __device__ inline int fp_words(int D)
     const int w = (D + 3) / 4;
     return w <= 1 ? 1 : w <= 2 ? 2 : w <= 4 ? 4 : (w + 7) / 8 * 8;
 }
+// 32-bit words of a window's second-stage fingerprint row: 16 bits per
+// dimension, padded with zero halfwords to whole 16-byte chunks
+__host__ __device__ inline int fq_words(int D) { return (D + 7) / 8 * 4; }
 constexpr int kSortTile = 4096;
 
 // Stable LSD sort of every segment of the batch by its length-i hash prefix,
@@ -112,15 +115,17 @@ hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& 
                           hipStream_t s);
 // Fingerprint rows of the batch, fps[jb][a][fp_words(D)]: byte f digests
 // dimension f's length-i_lo prefix (the prefix itself when i_lo = 1), padded
-// with zero bytes to whole words.
-hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, hipStream_t s);
+// with zero bytes to whole words; and second-stage rows fq[jb][a][fq_words(D)]
+// with a 16-bit digest per dimension (the prefix itself when i_lo <= 2).
+hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, uint32_t* fq,
+                          hipStream_t s);
 // Runs of >= 2 equal length-i_lo prefixes and the pairs of every run (one
 // launch); `part` holds enum_partials(g) per-work-group triples of counts
 // (pairs in runs, run members, screened pairs). kt = min(i_hi + 1, K).
 int64_t enum_partials(const StepGeom& g);
 hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint32_t* H,
-                       const uint32_t* fps, int kt, int d, int w, Cand* cand, uint32_t cap,
-                       Counters* cnt, unsigned long long* part, hipStream_t s);
+                       const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
+                       uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s);
 hipError_t launch_verify(const Cand* cand, uint32_t cap, const Counters* cnt, const void* x,
                          int dtype, int64_t n, int64_t ns, int D, int w, int d, const double* mu,
                          const double* isig, VRec* out, hipStream_t s);

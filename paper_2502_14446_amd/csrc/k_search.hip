@@ -325,45 +325,91 @@ hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& 
 // Fingerprint rows of a batch: for every repetition of the batch and every
 // window, one byte per dimension digesting that dimension's length-i_lo
 // prefix (equal prefixes give equal bytes), four to a word, padded with zero
-// bytes ([jb][a][fp_words(D)]). The pairs of a run are screened with them for
-// >= d colliding dimensions a word at a time; the few that pass have their
-// per-dimension prefixes rebuilt from the index and counted exactly.
-__device__ inline uint32_t prefix_digest(uint64_t prefix, int i_lo)
+// bytes ([jb][a][fp_words(D)]); and a second-stage row with a 16-bit digest
+// per dimension ([jb][a][fq_words(D)]). The pairs of a run are screened with
+// the bytes for >= d colliding dimensions a word at a time; those that pass
+// are screened again with the 16-bit digests (one contiguous row per
+// window), and the few left have their per-dimension prefixes rebuilt from
+// the index and counted exactly.
+__device__ inline uint32_t prefix_digest8(uint64_t prefix, int i_lo)
 {
     // one symbol is its own digest; longer prefixes are mixed by a
     // multiplicative (Fibonacci) hash and the top byte kept
     return i_lo == 1 ? (uint32_t)(prefix & 0xFFu) : (uint32_t)((prefix * 0x9E3779B97F4A7C15ull) >> 56);
 }
+__device__ inline uint32_t prefix_digest16(uint64_t prefix, int i_lo)
+{
+    return i_lo <= 2 ? (uint32_t)(prefix & 0xFFFFu) : (uint32_t)((prefix * 0x9E3779B97F4A7C15ull) >> 48);
+}
 
 __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H, StepGeom g, int reps,
-                                                 uint32_t* __restrict__ fps)
+                                                 uint32_t* __restrict__ fps, uint32_t* __restrict__ fq)
 {
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (gid >= (int64_t)reps * g.ns) return;
     const int jb = (int)(gid / g.ns);
     const int64_t a = gid - (int64_t)jb * g.ns;
     const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
-    const int nw = fp_words(g.D);
+    const int nw = fp_words(g.D), nq = fq_words(g.D);
     uint32_t* fw = fps + gid * nw;
+    uint4* qw = reinterpret_cast<uint4*>(fq + gid * nq);
     uint32_t word = 0;
-    for (int f = 0; f < 4 * nw; ++f) {
+    uint32_t q4[4] = {0, 0, 0, 0};
+    const int nf = 4 * nw > 2 * nq ? 4 * nw : 2 * nq;
+    for (int f = 0; f < nf; ++f) {
+        uint32_t d8 = 0, d16 = 0;
         if (f < g.D) {
             const uint32_t L = H[((int64_t)f * g.NF + l) * g.ns + a];
             const uint32_t R = H[((int64_t)f * g.NF + g.NL + r) * g.ns + a];
-            word |= prefix_digest(make_key<uint64_t>(L, R, g.i_lo), g.i_lo) << (8 * (f & 3));
+            const uint64_t pre = make_key<uint64_t>(L, R, g.i_lo);
+            d8 = prefix_digest8(pre, g.i_lo);
+            d16 = prefix_digest16(pre, g.i_lo);
         }
-        if ((f & 3) == 3) {
-            fw[f >> 2] = word;
-            word = 0;
+        if (f < 4 * nw) {
+            word |= d8 << (8 * (f & 3));
+            if ((f & 3) == 3) {
+                fw[f >> 2] = word;
+                word = 0;
+            }
+        }
+        if (f < 2 * nq) {
+            // halfword f of the row: word (f >> 1) of chunk (f >> 3)
+            const int wq = (f >> 1) & 3;
+            q4[wq] |= d16 << (16 * (f & 1));
+            if ((f & 7) == 7) {
+                qw[f >> 3] = make_uint4(q4[0], q4[1], q4[2], q4[3]);
+                q4[0] = q4[1] = q4[2] = q4[3] = 0;
+            }
         }
     }
 }
 
-hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, hipStream_t s)
+hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, uint32_t* fq,
+                          hipStream_t s)
 {
     const int64_t total = (int64_t)reps * g.ns;
-    hipLaunchKernelGGL(k_fptable, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, H, g, reps, fps);
+    hipLaunchKernelGGL(k_fptable, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, H, g, reps, fps,
+                       fq);
     return hipGetLastError();
+}
+
+// Second stage: do the 16-bit digest rows of windows a and b agree in >= d
+// dimensions? (SWAR per halfword as for bytes below; the rows carry
+// 2 nq - D zero halfwords of padding on both sides.)
+__device__ inline bool second_stage(const uint32_t* __restrict__ fq, int nq, int D, int d, uint32_t a,
+                                    uint32_t b)
+{
+    const uint4* ra = reinterpret_cast<const uint4*>(fq + (int64_t)a * nq);
+    const uint4* rb = reinterpret_cast<const uint4*>(fq + (int64_t)b * nq);
+    int z = 0;
+    for (int c = 0; c < nq / 4; ++c) {
+        const uint4 x = ra[c], y = rb[c];
+        const uint32_t v[4] = {x.x ^ y.x, x.y ^ y.y, x.z ^ y.z, x.w ^ y.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) z += __popc(((v[q] & 0x7FFF7FFFu) + 0x7FFF7FFFu) | v[q] | 0x7FFF7FFFu);
+    }
+    // z = 30 nq + non-zero halfwords; equal digests >= d iff non-zero <= D - d
+    return z <= 30 * nq + D - d;
 }
 
 // Bytes of x that are not zero, plus 28 (SWAR: the top bit of a byte of
@@ -463,7 +509,8 @@ template <int NW>
 __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
                                                    const uint32_t* __restrict__ H,
-                                                   const uint32_t* __restrict__ fps, StepGeom g, int kt,
+                                                   const uint32_t* __restrict__ fps,
+                                                   const uint32_t* __restrict__ fqs, StepGeom g, int kt,
                                                    int d, int w, int TS, Cand* __restrict__ cand,
                                                    uint32_t cap, Counters* __restrict__ cnt,
                                                    unsigned long long* __restrict__ coll_part)
@@ -472,6 +519,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
     __shared__ unsigned long long coll_sh[4], memb_sh[4], scr_sh[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nw = fp_words(g.D);   // NW = min(nw, kFpRegs)
+    const int nq = fq_words(g.D);
     const int zmax = 28 * nw + g.D - d;
     uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * (3 * nw + 2);
     uint32_t* fpA = mine;                        // 2 TS rows: tile P twice
@@ -480,6 +528,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
     uint32_t* idB = idA + TS;
 
     unsigned long long ncoll = 0, nmemb = 0, nscr = 0;
+    uint32_t maxrun = 0;
     const int64_t wins_per_seg = (g.ns + 63) / 64;
     const int64_t total_wins = wins_per_seg * g.nseg;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -495,6 +544,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
         const uint32_t* ks = keys + (int64_t)seg * g.ns;
         const uint32_t* is = idx + (int64_t)seg * g.ns;
         const uint32_t* fbase = fps + (int64_t)jb * g.ns * nw;
+        const uint32_t* qbase = fqs + (int64_t)jb * g.ns * nq;
 
         const int64_t t = base + lane;
         const bool valid = t < g.ns;
@@ -539,7 +589,8 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
                 }
                 if (act && z <= zmax) {
                     const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
-                    if (2 * (int64_t)(b - a) > (int64_t)w) {   // else a trivial match
+                    if (2 * (int64_t)(b - a) > (int64_t)w &&   // else a trivial match
+                        second_stage(qbase, nq, g.D, d, a, b)) {
                         ++nscr;
                         judge_pair(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     }
@@ -565,6 +616,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
         if (lane == 0) {
             nmemb += (unsigned long long)len;
             ncoll += (unsigned long long)len * (len - 1) / 2;
+            maxrun = maxrun > (uint32_t)len ? maxrun : (uint32_t)len;
         }
         const int T = (len + TS - 1) / TS;
         for (int tp = 0; tp < T; ++tp) {
@@ -606,6 +658,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
                         const uint32_t xu = idA[u], y = same ? idA[qq] : idB[qq];
                         const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
                         if (2 * (int64_t)(b - a) <= (int64_t)w) return;   // trivial match
+                        if (!second_stage(qbase, nq, g.D, d, a, b)) return;
                         ++nscr;
                         judge_pair(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     };
@@ -645,6 +698,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
         memb_sh[wave] = nmemb;
         scr_sh[wave] = nscr;
     }
+    if (lane == 0 && maxrun) atomicMax(&cnt->max_run, maxrun);   // one per wavefront
     __syncthreads();
     if (threadIdx.x == 0) {
         const int64_t b = blockIdx.x;
@@ -704,8 +758,8 @@ static int resident_blocks(const void* fn, size_t lds)
 
 template <int NW>
 static hipError_t go_enum(const StepGeom& g, const uint32_t* keys, const uint32_t* idx, const uint32_t* H,
-                          const uint32_t* fps, int kt, int d, int w, Cand* cand, uint32_t cap,
-                          Counters* cnt, unsigned long long* part, hipStream_t s)
+                          const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
+                          uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
     const int TS = tile_size(g.D);
     const size_t lds = (size_t)4 * TS * (3 * fp_words(g.D) + 2) * 4;   // 4 waves
@@ -715,24 +769,24 @@ static hipError_t go_enum(const StepGeom& g, const uint32_t* keys, const uint32_
     static int nblk[kFpRegs + 1][2] = {};   // per instantiation and LDS regime (fixed per D)
     int& nb = nblk[NW][lds > 65536];
     if (!nb) nb = resident_blocks((const void*)k_enum_runs<NW>, lds);
-    hipLaunchKernelGGL((k_enum_runs<NW>), dim3(nb), dim3(256), lds, s, keys, idx, H, fps, g, kt, d, w, TS,
-                       cand, cap, cnt, part);
+    hipLaunchKernelGGL((k_enum_runs<NW>), dim3(nb), dim3(256), lds, s, keys, idx, H, fps, fq, g, kt, d, w,
+                       TS, cand, cap, cnt, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, (int64_t)nb, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint32_t* H,
-                       const uint32_t* fps, int kt, int d, int w, Cand* cand, uint32_t cap,
-                       Counters* cnt, unsigned long long* part, hipStream_t s)
+                       const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
+                       uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
     if (g.i_lo > 4) return hipErrorInvalidValue;          // keys are 32-bit: prefixes of <= 4 symbols
     if (g.i - g.i_lo + 2 > kMaxLev) return hipErrorInvalidValue;
     const uint32_t* k = (const uint32_t*)b.keys[buf];
     switch (fp_words(g.D)) {
-    case 1: return go_enum<1>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
-    case 2: return go_enum<2>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
-    case 4: return go_enum<4>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
-    default: return go_enum<kFpRegs>(g, k, b.idx[buf], H, fps, kt, d, w, cand, cap, cnt, part, s);
+    case 1: return go_enum<1>(g, k, b.idx[buf], H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 2: return go_enum<2>(g, k, b.idx[buf], H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 4: return go_enum<4>(g, k, b.idx[buf], H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    default: return go_enum<kFpRegs>(g, k, b.idx[buf], H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
     }
 }
 

@@ -197,6 +197,7 @@ struct momenti_plan {
     SortBufs sb{};
     int sb_nseg = 0, sb_reps = 0;
     uint32_t* fps = nullptr;    // fingerprint rows of a batch: [rep][window][fp_words(D)]
+    uint32_t* fq = nullptr;     // second-stage rows of a batch: [rep][window][fq_words(D)]
     unsigned long long* coll_part = nullptr;   // per-work-group collision counts
     int64_t coll_parts = 0;
     Cand* cand = nullptr;       // candidates of one launch batch
@@ -367,7 +368,9 @@ static void release_search(momenti_plan* p)
     dfree(p, p->sb.hist, (size_t)p->sb_nseg * 256 * p->sb.tiles * 4);
     p->sb.hist = nullptr;
     dfree(p, p->fps, (size_t)p->sb_reps * fp_words(p->D) * p->ns * 4);
+    dfree(p, p->fq, (size_t)p->sb_reps * fq_words(p->D) * p->ns * 4);
     p->fps = nullptr;
+    p->fq = nullptr;
     p->sb_nseg = 0;
     p->sb_reps = 0;
     dfree(p, p->cand, (size_t)p->cap * sizeof(Cand));
@@ -759,11 +762,11 @@ static Counters* st_counters(momenti_plan* p) { return (Counters*)p->status; }
 static PoolState* st_pool(momenti_plan* p) { return (PoolState*)(p->status + 64); }
 
 // double-buffered keys and indices and digit histograms of reps * Ds
-// segments, and the fingerprint rows of reps repetitions
+// segments, and the two fingerprint rows of reps repetitions
 static size_t sort_bytes(int64_t reps, int64_t Ds, int64_t D, int64_t ns, int64_t tiles)
 {
     return (size_t)(reps * Ds) * ns * (8 + 8 + 4 + 4) + (size_t)(reps * Ds) * 256 * tiles * 4 +
-           (size_t)reps * ns * 4 * fp_words((int)D);
+           (size_t)reps * ns * 4 * (fp_words((int)D) + fq_words((int)D));
 }
 static size_t cand_bytes(uint32_t cap) { return (size_t)cap * (sizeof(Cand) + sizeof(VRec)); }
 static size_t store_bytes(uint32_t cap) { return (size_t)cap * (sizeof(VRec) + 8); }
@@ -782,6 +785,7 @@ static int alloc_sort(momenti_plan* p, int reps, int Ds)
     }
     if ((rc = dalloc_t(p, &p->sb.hist, (size_t)nseg * 256 * tiles * 4))) return rc;
     if ((rc = dalloc_t(p, &p->fps, (size_t)reps * fp_words(p->D) * p->ns * 4))) return rc;
+    if ((rc = dalloc_t(p, &p->fq, (size_t)reps * fq_words(p->D) * p->ns * 4))) return rc;
     return MOMENTI_OK;
 }
 
@@ -960,6 +964,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     }();
     const double elem_x = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
     unsigned long long n_screened = 0;
+    uint32_t max_run = 0;
 
 restart:
     HIP_OK(launch_pool_reset(st_pool(p), p->st));
@@ -970,10 +975,10 @@ restart:
         const int s0 = (p->K - i_hi) * p->L;
         const int nsteps = (i_hi - i_lo + 1) * p->L;
         if (verbose) {
-            std::fprintf(stderr, "[momenti] rounds %d..%d: %.1f ms, steps %lld, collisions %lld, screened %llu, candidates %lld |",
+            std::fprintf(stderr, "[momenti] rounds %d..%d: %.1f ms, steps %lld, collisions %lld, screened %llu, longest run %u, candidates %lld |",
                          i_hi, i_lo,
                          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
-                         (long long)R.n_steps, (long long)R.n_collisions, n_screened, (long long)R.n_cand);
+                         (long long)R.n_steps, (long long)R.n_collisions, n_screened, max_run, (long long)R.n_cand);
             for (int q = 0; q < KI_COUNT; ++q)
                 if (p->prof.tot[q].launches) std::fprintf(stderr, " %s %.1f", kKernelNames[q], p->prof.tot[q].ms);
             std::fprintf(stderr, "\n");
@@ -998,12 +1003,13 @@ restart:
             }
             const int kt = std::min(i_hi + 1, p->K);
             const int nw = fp_words(p->D);
-            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * nw), 0.0, [&] {
-                return launch_fptable(p->H, g, Bc, p->fps, p->st);
+            const int nq = fq_words(p->D);
+            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + nq)), 0.0, [&] {
+                return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->st);
             }));
             int enum_slot = -1, verify_slot = -1;
             HIP_OK(timed(p, KI_ENUM, 0.0, 0.0, [&] {
-                return launch_enum(g, p->sb, buf, p->H, p->fps, kt, d, p->w, p->cand, p->cap,
+                return launch_enum(g, p->sb, buf, p->H, p->fps, p->fq, kt, d, p->w, p->cand, p->cap,
                                    st_counters(p), p->coll_part, p->st);
             }, &enum_slot));
             HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
@@ -1046,6 +1052,7 @@ restart:
             }
             R.n_collisions += (int64_t)cnt.n_coll;
             n_screened += cnt.n_screen;
+            max_run = std::max(max_run, cnt.max_run);
             R.n_cand += cnt.n_cand;
             R.n_verified += cnt.n_cand;
             if (tracing && p->tr_cand && cnt.n_cand) {
@@ -1099,6 +1106,9 @@ restart:
                 *n_out = k;
                 R.i_stop = i;
                 R.j_stop = J;
+                if (verbose)
+                    std::fprintf(stderr, "[momenti] stop (%d, %d): collisions %lld, screened %llu, longest run %u\n",
+                                 i, J, (long long)R.n_collisions, n_screened, max_run);
                 R.peak_bytes = p->peak;
                 R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                 if (rep) *rep = R;
