@@ -119,7 +119,7 @@ typedef struct {
     int32_t fallback;         /* 1 when the exact all-pairs answer was returned */
     int32_t pool_overflow;    /* times the verified-pair pool had to be enlarged */
     int32_t batch_reps;       /* repetitions per launch actually used */
-    int32_t reserved;
+    int32_t first_group_lo;   /* rounds K .. first_group_lo were traversed from one sort */
 } momenti_report;
 
 /* Fill *o with the defaults (K = 8, L = 200, r estimated, F32 projection,

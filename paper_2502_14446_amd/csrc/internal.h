@@ -126,6 +126,10 @@ int64_t enum_partials(const StepGeom& g);
 hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint32_t* H,
                        const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
                        uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s);
+// Probe of one sorted batch: out[i - 1] = pairs of windows (in the batch's
+// segments) that share their length-i prefix, i = 1 .. g.i_lo, for segments
+// sorted by their length-g.i_lo prefix (8 counters, device memory).
+hipError_t launch_probe(const StepGeom& g, const SortBufs& b, int buf, unsigned long long* out, hipStream_t s);
 hipError_t launch_verify(const Cand* cand, uint32_t cap, const Counters* cnt, const void* x,
                          int dtype, int64_t n, int64_t ns, int D, int w, int d, const double* mu,
                          const double* isig, VRec* out, hipStream_t s);

@@ -127,6 +127,11 @@ __device__ inline SegPtr seg_words(const uint32_t* H, const StepGeom& g, int seg
     return p;
 }
 
+__global__ void k_zero64(unsigned long long* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
 // ------------------------------------------------------------------ radix sort
 template <typename KT, bool FIRST>
 __global__ __launch_bounds__(256) void k_hist(const KT* __restrict__ kin, const uint32_t* __restrict__ H,
@@ -453,7 +458,7 @@ __device__ inline int common_symbols(uint64_t x, uint64_t y, int kt)
 // >= d, no f' < f has cp >= i (it is reported once, from its lowest colliding
 // dimension) and, below round K, W_{i+1} < d (section 6.2: pairs seen one
 // symbol deeper are skipped).
-constexpr int kMaxLev = 6;   // rounds of a group + 1
+constexpr int kMaxLev = 8;   // rounds of a group + 1 (a group spans at most 7 rounds)
 
 __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __restrict__ H, const StepGeom& g,
                                   int f, int j, int kt, int d, Cand* __restrict__ cand, uint32_t cap,
@@ -471,7 +476,7 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
         const int cp = common_symbols(make_key<uint64_t>(Hl[a], Hr[a], kt), make_key<uint64_t>(Hl[b], Hr[b], kt), kt);
         int nl = cp - g.i_lo + 1;   // levels 0 .. nl - 1 collide
         nl = nl < 0 ? 0 : (nl > nlev ? nlev : nl);
-        const uint64_t ones = nl ? 0x010101010101ull & (~0ull >> (64 - 8 * nl)) : 0ull;
+        const uint64_t ones = nl ? 0x0101010101010101ull & (~0ull >> (64 - 8 * nl)) : 0ull;
         atl += ones;
         if (fp < f) blw += ones;
         if (fp == f) cpf = cp;
@@ -505,8 +510,8 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
 //    member u of P and walks its partners in tile Q >= P (all lanes read the
 //    same partner of Q at once: an LDS broadcast).
 // Pairs that pass the screen and are not trivial matches go to judge_pair.
-template <int NW>
-__global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ keys,
+template <typename KT, int NW>
+__global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
                                                    const uint32_t* __restrict__ H,
                                                    const uint32_t* __restrict__ fps,
@@ -541,14 +546,14 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
         const int64_t base = (win - (int64_t)seg * wins_per_seg) * 64;
         const int jb = seg / g.Ds, f = seg - jb * g.Ds;
         const int j = g.j0 + jb;
-        const uint32_t* ks = keys + (int64_t)seg * g.ns;
+        const KT* ks = keys + (int64_t)seg * g.ns;
         const uint32_t* is = idx + (int64_t)seg * g.ns;
         const uint32_t* fbase = fps + (int64_t)jb * g.ns * nw;
         const uint32_t* qbase = fqs + (int64_t)jb * g.ns * nq;
 
         const int64_t t = base + lane;
         const bool valid = t < g.ns;
-        const uint32_t k = valid ? ks[t] : 0u;
+        const KT k = valid ? ks[t] : (KT)0;
         const bool same_prev = valid && t > 0 && ks[t - 1] == k;
         const bool same_next = valid && t + 1 < g.ns && ks[t + 1] == k;
         const bool head = valid && !same_prev && same_next;
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const uint32_t* __restrict__ 
         const uint64_t open = __ballot(head && !tb);
         if (!open) continue;
         const int hl = __ffsll((unsigned long long)open) - 1;
-        const uint32_t hk = __shfl(k, hl, 64);
+        const KT hk = __shfl(k, hl, 64);
         int64_t pos = base + 64, end = -1;
         while (end < 0) {
             const int64_t ee = pos + lane;
@@ -756,38 +761,131 @@ static int resident_blocks(const void* fn, size_t lds)
     return std::min(kEnumBlocks, ncu * std::min(per, 8));
 }
 
-template <int NW>
-static hipError_t go_enum(const StepGeom& g, const uint32_t* keys, const uint32_t* idx, const uint32_t* H,
+template <typename KT, int NW>
+static hipError_t go_enum(const StepGeom& g, const KT* keys, const uint32_t* idx, const uint32_t* H,
                           const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
                           uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
     const int TS = tile_size(g.D);
     const size_t lds = (size_t)4 * TS * (3 * fp_words(g.D) + 2) * 4;   // 4 waves
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_enum_runs<NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)k_enum_runs<KT, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
     static int nblk[kFpRegs + 1][2] = {};   // per instantiation and LDS regime (fixed per D)
     int& nb = nblk[NW][lds > 65536];
-    if (!nb) nb = resident_blocks((const void*)k_enum_runs<NW>, lds);
-    hipLaunchKernelGGL((k_enum_runs<NW>), dim3(nb), dim3(256), lds, s, keys, idx, H, fps, fq, g, kt, d, w,
+    if (!nb) nb = resident_blocks((const void*)k_enum_runs<KT, NW>, lds);
+    hipLaunchKernelGGL((k_enum_runs<KT, NW>), dim3(nb), dim3(256), lds, s, keys, idx, H, fps, fq, g, kt, d, w,
                        TS, cand, cap, cnt, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, (int64_t)nb, cnt);
     return hipGetLastError();
+}
+
+template <typename KT>
+static hipError_t go_enum_nw(const StepGeom& g, const KT* k, const uint32_t* idx, const uint32_t* H,
+                             const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
+                             uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
+{
+    switch (fp_words(g.D)) {
+    case 1: return go_enum<KT, 1>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 2: return go_enum<KT, 2>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 4: return go_enum<KT, 4>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    default: return go_enum<KT, kFpRegs>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    }
 }
 
 hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint32_t* H,
                        const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
                        uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
-    if (g.i_lo > 4) return hipErrorInvalidValue;          // keys are 32-bit: prefixes of <= 4 symbols
     if (g.i - g.i_lo + 2 > kMaxLev) return hipErrorInvalidValue;
-    const uint32_t* k = (const uint32_t*)b.keys[buf];
-    switch (fp_words(g.D)) {
-    case 1: return go_enum<1>(g, k, b.idx[buf], H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    case 2: return go_enum<2>(g, k, b.idx[buf], H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    case 4: return go_enum<4>(g, k, b.idx[buf], H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    default: return go_enum<kFpRegs>(g, k, b.idx[buf], H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    if (g.i_lo <= 4)
+        return go_enum_nw<uint32_t>(g, (const uint32_t*)b.keys[buf], b.idx[buf], H, fps, fq, kt, d, w, cand,
+                                    cap, cnt, part, s);
+    return go_enum_nw<uint64_t>(g, (const uint64_t*)b.keys[buf], b.idx[buf], H, fps, fq, kt, d, w, cand, cap,
+                                cnt, part, s);
+}
+
+// ------------------------------------------------------------------ probe
+// Pairs of windows sharing their length-i prefix, for i = 1 .. kk, in
+// segments sorted by their length-kk prefix (a shorter prefix's runs are
+// unions of consecutive runs of the longer one). A run is followed for at
+// most kProbeCap members: the counts are exact below that, lower bounds
+// above it. out[i - 1] accumulates the count of level i.
+constexpr int64_t kProbeCap = 1 << 16;
+
+template <typename KT>
+__global__ __launch_bounds__(256) void k_probe_levels(const KT* __restrict__ keys, int64_t ns, int nseg, int kk,
+                                                      unsigned long long* __restrict__ out)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t lane_bit = 1ull << lane;
+    const uint64_t le_mask = lane_bit | (lane_bit - 1), ge_mask = ~(lane_bit - 1);
+    unsigned long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t wins_per_seg = (ns + 63) / 64;
+    const int64_t total_wins = wins_per_seg * nseg;
+    for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < total_wins; win += (int64_t)gridDim.x * 4) {
+        const int seg = (int)(win / wins_per_seg);
+        const int64_t base = (win - (int64_t)seg * wins_per_seg) * 64;
+        const KT* ks = keys + (int64_t)seg * ns;
+        const int64_t t = base + lane;
+        const bool valid = t < ns;
+        const KT kf = valid ? ks[t] : (KT)0;
+        const KT kp = valid && t > 0 ? ks[t - 1] : (KT)0;
+        const KT kn = valid && t + 1 < ns ? ks[t + 1] : (KT)0;
+#pragma unroll
+        for (int lv = 0; lv < 8; ++lv) {
+            if (lv >= kk) break;
+            const int sh = 8 * (kk - 1 - lv);   // level lv + 1
+            const KT k = kf >> sh;
+            const bool same_prev = valid && t > 0 && (KT)(kp >> sh) == k;
+            const bool same_next = valid && t + 1 < ns && (KT)(kn >> sh) == k;
+            const bool head = valid && !same_prev && same_next;
+            const uint64_t heads = __ballot(head);
+            if (!heads) continue;
+            const uint64_t tails = __ballot(valid && !same_next);
+            const uint64_t hb = heads & le_mask, tb = tails & ge_mask;
+            const bool inner = valid && (head || same_prev) && hb && tb;
+            const int h = 63 - __clzll((long long)(hb | 1ull));
+            const int e = __ffsll((unsigned long long)(tb | (1ull << 63)));
+            const int L = e - h, q = lane - h;
+            acc[lv] += inner ? (unsigned long long)((L - 1) / 2 + (((L & 1) == 0 && q < L / 2) ? 1 : 0)) : 0ull;
+            const uint64_t open = __ballot(head && !tb);
+            if (!open) continue;
+            const int hl = __ffsll((unsigned long long)open) - 1;
+            const KT hk = __shfl(k, hl, 64);
+            const int64_t start = base + hl;
+            int64_t pos = base + 64, end = -1;
+            while (end < 0 && pos - start < kProbeCap) {
+                const int64_t ee = pos + lane;
+                const bool stop = ee >= ns || (KT)(ks[ee < ns ? ee : ns - 1] >> sh) != hk;
+                const uint64_t m = __ballot(stop);
+                if (m) end = pos + __ffsll((unsigned long long)m) - 1;
+                pos += 64;
+            }
+            const int64_t len = end < 0 ? kProbeCap : end - start;
+            if (lane == 0) acc[lv] += (unsigned long long)(len * (len - 1) / 2);
+        }
     }
+#pragma unroll
+    for (int lv = 0; lv < 8; ++lv) {
+        unsigned long long v = acc[lv];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0 && v) atomicAdd(&out[lv], v);
+    }
+}
+
+hipError_t launch_probe(const StepGeom& g, const SortBufs& b, int buf, unsigned long long* out, hipStream_t s)
+{
+    if (g.i_lo < 1 || g.i_lo > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero64, dim3(1), dim3(64), 0, s, out, 8);
+    if (g.i_lo <= 4)
+        hipLaunchKernelGGL(k_probe_levels<uint32_t>, dim3(512), dim3(256), 0, s, (const uint32_t*)b.keys[buf],
+                           g.ns, g.nseg, g.i_lo, out);
+    else
+        hipLaunchKernelGGL(k_probe_levels<uint64_t>, dim3(512), dim3(256), 0, s, (const uint64_t*)b.keys[buf],
+                           g.ns, g.nseg, g.i_lo, out);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ verification

@@ -149,10 +149,10 @@ static uint8_t to_e4m3_bits(double v)
 // ------------------------------------------------------------------ profiling
 // Optional per-kernel timing with HIP events recorded on the plan's stream
 // around each launch; folded into totals whenever the host synchronises.
-enum KernelId { KI_STATS, KI_RSAMPLE, KI_PROJ, KI_HIST, KI_SCAN, KI_SCATTER, KI_FPTABLE, KI_ENUM,
+enum KernelId { KI_STATS, KI_RSAMPLE, KI_PROJ, KI_HIST, KI_SCAN, KI_SCATTER, KI_PROBE, KI_FPTABLE, KI_ENUM,
                 KI_VERIFY, KI_FILTER, KI_POOL, KI_ALLPAIRS, KI_COUNT };
 static const char* const kKernelNames[KI_COUNT] = {
-    "stats", "rsample", "proj", "sort_hist", "sort_scan", "sort_scatter", "fptable", "enum",
+    "stats", "rsample", "proj", "sort_hist", "sort_scan", "sort_scatter", "probe", "fptable", "enum",
     "verify", "pool_filter", "pool", "allpairs"};
 
 struct KTotal {
@@ -884,14 +884,19 @@ static void to_motifs(const std::vector<VRec>& v, int count, momenti_motif* out)
 static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out,
                           momenti_report* rep);
 
-// Rounds processed from one sort: a group is sorted by its lowest round's
-// prefix, whose runs contain every deeper round's runs. The first rounds,
-// where collisions are rare, share one sort; the deeper rounds, where
-// collisions multiply, are sorted one by one.
-static std::vector<std::pair<int, int>> round_groups(int K)
+// Rounds processed from one sort. A segment sorted by its length-i prefix
+// is sorted by every shorter prefix too, so one sort serves a group of
+// rounds [i_hi .. i_lo] when it is by the lowest round's prefix. The first
+// group reaches down to the lowest round whose colliding pairs are
+// estimated to cost less to enumerate than a sort pass (about 8 pairs per
+// segment element), at most 7 rounds; below it, where collisions multiply,
+// every round has a sort of its own. pairs_est[i] estimates the colliding
+// pairs of round i over all segments and repetitions.
+static std::vector<std::pair<int, int>> round_groups(int K, const double* pairs_est, double budget)
 {
+    int lo = K;
+    while (lo > 1 && K - lo + 2 <= 7 && pairs_est[lo - 1] <= budget) --lo;
     std::vector<std::pair<int, int>> g;
-    const int lo = std::max(1, K - 4);
     g.push_back({K, lo});
     for (int i = lo - 1; i >= 1; --i) g.push_back({i, i});
     return g;
@@ -915,10 +920,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     R.t_hash_ms = p->t_hash_ms;
 
     release_search(p);
-    const auto groups = round_groups(p->K);
-    int max_group = 0;
-    for (auto& gr : groups) max_group = std::max(max_group, gr.first - gr.second + 1);
-    const int max_steps = max_group * p->L;
+    const int max_steps = std::min(p->K, 7) * p->L;   // steps of the largest round group
     int P = p->o.pool_size ? p->o.pool_size : std::max(4096, 128 * k);
     P = std::max(P, k);
     int rc;
@@ -952,6 +954,36 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     }
     R.batch_reps = B;
 
+    // Probe: repetition 0 of the first (up to 8) segment dimensions, sorted by
+    // the full K-symbol prefix, gives the colliding pairs of every round;
+    // scaled to all segments and repetitions they choose the round groups.
+    double pairs_est[9] = {0};
+    {
+        const int Dp = std::min(Ds, 8);
+        StepGeom g;
+        g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
+        g.j0 = 0; g.Ds = Ds; g.nseg = Dp; g.i = p->K; g.K = p->K; g.i_lo = p->K;
+        int buf = 0;
+        const double elems = (double)Dp * p->ns, kb = p->K <= 4 ? 4.0 : 8.0;
+        for (int pass = 0; pass < p->K; ++pass) {
+            const double kin = pass == 0 ? 8.0 : kb;
+            HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
+            HIP_OK(timed(p, KI_SCAN, 8.0 * g.nseg * 256.0 * p->sb.tiles, 0.0, [&] { return launch_scan(g, p->sb, p->st); }));
+            HIP_OK(timed(p, KI_SCATTER, elems * (kin + (pass == 0 ? 0.0 : 4.0) + kb + 4.0), 0.0,
+                         [&] { return launch_scatter(g, p->H, p->sb, pass, buf, p->st); }));
+            buf ^= 1;
+        }
+        unsigned long long* dcnt = (unsigned long long*)(p->status + 2048);
+        HIP_OK(timed(p, KI_PROBE, elems * kb, 0.0, [&] { return launch_probe(g, p->sb, buf, dcnt, p->st); }));
+        HIP_OK(hipMemcpyAsync(p->host_status + 2048, dcnt, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, p->st));
+        HIP_OK(hipStreamSynchronize(p->st));
+        prof_flush(p);
+        const unsigned long long* hc = (const unsigned long long*)(p->host_status + 2048);
+        for (int i = 1; i <= p->K; ++i) pairs_est[i] = (double)hc[i - 1] * ((double)Ds / Dp) * p->L;
+    }
+    const auto groups = round_groups(p->K, pairs_est, 8.0 * (double)p->ns * Ds * p->L);
+    R.first_group_lo = groups[0].second;
+
     const bool tracing = p->tr_cand || p->tr_top_size;
     if (p->tr_count) *p->tr_count = 0;
     if (p->tr_top_size)
@@ -974,6 +1006,11 @@ restart:
         const int i_hi = gr.first, i_lo = gr.second;
         const int s0 = (p->K - i_hi) * p->L;
         const int nsteps = (i_hi - i_lo + 1) * p->L;
+        if (verbose && gr == groups[0]) {
+            std::fprintf(stderr, "[momenti] probe: estimated pairs per round");
+            for (int i = p->K; i >= 1; --i) std::fprintf(stderr, " %d:%.3g", i, pairs_est[i]);
+            std::fprintf(stderr, "\n");
+        }
         if (verbose) {
             std::fprintf(stderr, "[momenti] rounds %d..%d: %.1f ms, steps %lld, collisions %lld, screened %llu, longest run %u, candidates %lld |",
                          i_hi, i_lo,
