@@ -428,17 +428,18 @@ __device__ inline int nonzero_bytes_28(uint32_t x)
 constexpr int kFpRegs = 8;   // fingerprint words kept in registers (32 dimensions)
 
 // Sum over the nw words of nonzero_bytes_28(own ^ partner): the lane's own
-// row (its first NW words in registers, the rest at own_tail) against the
-// partner's (pw). With D dimensions the rows have 4 nw - D padding bytes, zero
-// on both sides, so a pair has >= d equal digests iff the sum is
-// <= 28 nw + D - d.
-template <int NW, typename GetW>
+// row (its first NW words in registers, the rest at own_tail, only when TAIL)
+// against the partner's (pw). With D dimensions the rows have 4 nw - D
+// padding bytes, zero on both sides, so a pair has >= d equal digests iff the
+// sum is <= 28 nw + D - d.
+template <int NW, bool TAIL, typename GetW>
 __device__ inline int screen(const uint32_t (&ofp)[NW], const uint32_t* own_tail, const GetW& pw, int nw)
 {
     int z = 0;
 #pragma unroll
     for (int wd = 0; wd < NW; ++wd) z += nonzero_bytes_28(ofp[wd] ^ pw(wd));
-    for (int wd = NW; wd < nw; ++wd) z += nonzero_bytes_28(own_tail[wd] ^ pw(wd));
+    if (TAIL)
+        for (int wd = NW; wd < nw; ++wd) z += nonzero_bytes_28(own_tail[wd] ^ pw(wd));
     return z;
 }
 
@@ -510,7 +511,7 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
 //    member u of P and walks its partners in tile Q >= P (all lanes read the
 //    same partner of Q at once: an LDS broadcast).
 // Pairs that pass the screen and are not trivial matches go to judge_pair.
-template <typename KT, int NW>
+template <typename KT, int NW, bool TAIL>
 __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
                                                    const uint32_t* __restrict__ H,
@@ -523,7 +524,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ unsigned long long coll_sh[4], memb_sh[4], scr_sh[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nw = fp_words(g.D);   // NW = min(nw, kFpRegs)
+    const int nw = TAIL ? fp_words(g.D) : NW;   // NW = min(nw, kFpRegs); TAIL iff nw > NW
     const int nq = fq_words(g.D);
     const int zmax = 28 * nw + g.D - d;
     uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * (3 * nw + 2);
@@ -585,12 +586,12 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                 const int pl = act ? h + qs : lane;
                 const uint32_t y = __shfl(xu, pl, 64);
                 int z = 0;
-                if (nw == NW) {
+                if (!TAIL) {
                     // every lane takes part in the permutes; only active lanes use them
-                    z = screen<NW>(ofp, ofw, [&](int wd) { return (uint32_t)__shfl(ofp[wd], pl, 64); }, nw);
+                    z = screen<NW, false>(ofp, ofw, [&](int wd) { return (uint32_t)__shfl(ofp[wd], pl, 64); }, nw);
                 } else if (act) {
                     const uint32_t* pfw = fbase + (int64_t)y * nw;
-                    z = screen<NW>(ofp, ofw, [&](int wd) { return pfw[wd]; }, nw);
+                    z = screen<NW, true>(ofp, ofw, [&](int wd) { return pfw[wd]; }, nw);
                 }
                 if (act && z <= zmax) {
                     const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
@@ -668,15 +669,22 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                         judge_pair(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     };
                     int v = 0;
-                    // four partners per step: their LDS reads are in flight together
+                    // four partners per step, their LDS reads issued together
                     for (; v + 4 <= nv; v += 4) {
                         const uint32_t* p = P0 + (size_t)v * nw;
-                        const int z0 = screen<NW>(ofp, ofw, [&](int wd) { return p[wd]; }, nw);
-                        const int z1 = screen<NW>(ofp, ofw, [&](int wd) { return p[nw + wd]; }, nw);
-                        const int z2 = screen<NW>(ofp, ofw, [&](int wd) { return p[2 * nw + wd]; }, nw);
-                        const int z3 = screen<NW>(ofp, ofw, [&](int wd) { return p[3 * nw + wd]; }, nw);
-                        uint32_t hit = (uint32_t)(z0 <= zmax) | ((uint32_t)(z1 <= zmax) << 1) |
-                                       ((uint32_t)(z2 <= zmax) << 2) | ((uint32_t)(z3 <= zmax) << 3);
+                        uint32_t pw[4][NW];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+#pragma unroll
+                            for (int wd = 0; wd < NW; ++wd) pw[c][wd] = p[c * nw + wd];
+                        uint32_t hit = 0;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const uint32_t* pc = p + c * nw;
+                            const int z = screen<NW, TAIL>(
+                                ofp, ofw, [&](int wd) { return wd < NW ? pw[c][wd < NW ? wd : 0] : pc[wd]; }, nw);
+                            hit |= (uint32_t)(z <= zmax) << c;
+                        }
                         while (hit) {
                             const int bit = __ffs(hit) - 1;
                             hit &= hit - 1;
@@ -685,7 +693,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                     }
                     for (; v < nv; ++v) {
                         const uint32_t* p = P0 + (size_t)v * nw;
-                        if (screen<NW>(ofp, ofw, [&](int wd) { return p[wd]; }, nw) <= zmax) check(v);
+                        if (screen<NW, TAIL>(ofp, ofw, [&](int wd) { return p[wd]; }, nw) <= zmax) check(v);
                     }
                 }
             }
@@ -749,9 +757,7 @@ static int tile_size(int D)
 constexpr int kEnumBlocks = 2048;   // persistent grid: at most 8 work-groups per CU
 int64_t enum_partials(const StepGeom&) { return kEnumBlocks; }
 
-// Work-groups that are resident at once (so that none waits for a slot):
-// CUs times the occupancy of the kernel at this LDS size, capped.
-static int resident_blocks(const void* fn, size_t lds)
+static int resident_blocks_query(const void* fn, size_t lds)
 {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -761,21 +767,34 @@ static int resident_blocks(const void* fn, size_t lds)
     return std::min(kEnumBlocks, ncu * std::min(per, 8));
 }
 
-template <typename KT, int NW>
+// Work-groups that are resident at once (so that none waits for a slot):
+// CUs times the occupancy of the kernel at this LDS size, capped.
+static int resident_blocks(const void* fn, size_t lds)
+{
+    // cached per (kernel, LDS size); a stale entry only changes the grid size
+    static thread_local const void* last_fn = nullptr;
+    static thread_local size_t last_lds = 0;
+    static thread_local int last_nb = 0;
+    if (fn == last_fn && lds == last_lds) return last_nb;
+    last_fn = fn;
+    last_lds = lds;
+    last_nb = resident_blocks_query(fn, lds);
+    return last_nb;
+}
+
+
+template <typename KT, int NW, bool TAIL>
 static hipError_t go_enum(const StepGeom& g, const KT* keys, const uint32_t* idx, const uint32_t* H,
                           const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
                           uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
     const int TS = tile_size(g.D);
     const size_t lds = (size_t)4 * TS * (3 * fp_words(g.D) + 2) * 4;   // 4 waves
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_enum_runs<KT, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-    static int nblk[kFpRegs + 1][2] = {};   // per instantiation and LDS regime (fixed per D)
-    int& nb = nblk[NW][lds > 65536];
-    if (!nb) nb = resident_blocks((const void*)k_enum_runs<KT, NW>, lds);
-    hipLaunchKernelGGL((k_enum_runs<KT, NW>), dim3(nb), dim3(256), lds, s, keys, idx, H, fps, fq, g, kt, d, w,
-                       TS, cand, cap, cnt, part);
+    const void* fn = (const void*)k_enum_runs<KT, NW, TAIL>;
+    if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int nb = resident_blocks(fn, lds);
+    hipLaunchKernelGGL((k_enum_runs<KT, NW, TAIL>), dim3(nb), dim3(256), lds, s, keys, idx, H, fps, fq, g, kt,
+                       d, w, TS, cand, cap, cnt, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, (int64_t)nb, cnt);
     return hipGetLastError();
 }
@@ -786,10 +805,11 @@ static hipError_t go_enum_nw(const StepGeom& g, const KT* k, const uint32_t* idx
                              uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
     switch (fp_words(g.D)) {
-    case 1: return go_enum<KT, 1>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    case 2: return go_enum<KT, 2>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    case 4: return go_enum<KT, 4>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    default: return go_enum<KT, kFpRegs>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 1: return go_enum<KT, 1, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 2: return go_enum<KT, 2, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 4: return go_enum<KT, 4, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 8: return go_enum<KT, 8, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    default: return go_enum<KT, kFpRegs, true>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
     }
 }
 
