@@ -1094,38 +1094,66 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ 
 
     for (int st = 0; st < nsteps; ++st) {
         const uint32_t beg = rc->step_off[st], end = rc->step_off[st + 1];
+        if (beg == end) {
+            // nothing new: the pool and TOP stand, the snapshot repeats (no
+            // shared state changes, so no barrier is needed)
+            if (tid == 0) {
+                Snap sn;
+                sn.top_n = s_topn;
+                sn.truncated = s_trunc;
+                sn.dist_max = s_topn == k ? top[k - 1].dist_max : 0.0;
+                snaps[st] = sn;
+            }
+            for (int q = tid; q < s_topn; q += kPoolThreads) snap_tops[(int64_t)st * k + q] = top[q];
+            continue;
+        }
         if (tid == 0) s_improved = 0;
         __syncthreads();
         for (uint32_t start = beg; start < end; start += kChunk) {
             const uint32_t cnum = min((uint32_t)kChunk, end - start);
+            double my_d = __builtin_huge_val();
+            uint32_t my_a = 0xFFFFFFFFu, my_b = 0xFFFFFFFFu, my_i = 0xFFFFFFFFu;
             if ((uint32_t)tid < cnum) {
-                const VRec& r = rec[order[start + tid]];
-                cd[tid] = r.dist_d;
-                ca[tid] = r.a;
-                cb[tid] = r.b;
-                ci[tid] = order[start + tid];
-            } else {
-                cd[tid] = __builtin_huge_val();
-                ca[tid] = 0xFFFFFFFFu;
-                cb[tid] = 0xFFFFFFFFu;
-                ci[tid] = 0xFFFFFFFFu;
+                my_i = order[start + tid];
+                const VRec& r = rec[my_i];
+                my_d = r.dist_d;
+                my_a = r.a;
+                my_b = r.b;
             }
-            __syncthreads();
-            // bitonic sort of the chunk by (dist_d, a, b)
-            for (int size = 2; size <= kChunk; size <<= 1) {
-                for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                    const int pa = tid ^ stride;
-                    if (pa > tid) {
-                        const bool up = (tid & size) == 0;
-                        const bool gt = key_less(cd[pa], ca[pa], cb[pa], cd[tid], ca[tid], cb[tid]);
-                        if (gt == up) {
-                            double td = cd[tid]; cd[tid] = cd[pa]; cd[pa] = td;
-                            uint32_t t1 = ca[tid]; ca[tid] = ca[pa]; ca[pa] = t1;
-                            uint32_t t2 = cb[tid]; cb[tid] = cb[pa]; cb[pa] = t2;
-                            uint32_t t3 = ci[tid]; ci[tid] = ci[pa]; ci[pa] = t3;
-                        }
+            if (cnum <= 256) {
+                // small chunk: rank by counting (ties, i.e. the same pair met
+                // twice, ordered by position), one scatter
+                kd[tid] = my_d; ka[tid] = my_a; kb2[tid] = my_b;
+                __syncthreads();
+                if ((uint32_t)tid < cnum) {
+                    int rank = 0;
+                    for (int q = 0; q < (int)cnum; ++q) {
+                        const bool less = key_less(kd[q], ka[q], kb2[q], my_d, my_a, my_b) ||
+                                          (q < tid && kd[q] == my_d && ka[q] == my_a && kb2[q] == my_b);
+                        rank += less;
                     }
-                    __syncthreads();
+                    cd[rank] = my_d; ca[rank] = my_a; cb[rank] = my_b; ci[rank] = my_i;
+                }
+                __syncthreads();
+            } else {
+                cd[tid] = my_d; ca[tid] = my_a; cb[tid] = my_b; ci[tid] = my_i;
+                __syncthreads();
+                // bitonic sort of the chunk by (dist_d, a, b)
+                for (int size = 2; size <= kChunk; size <<= 1) {
+                    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                        const int pa = tid ^ stride;
+                        if (pa > tid) {
+                            const bool up = (tid & size) == 0;
+                            const bool gt = key_less(cd[pa], ca[pa], cb[pa], cd[tid], ca[tid], cb[tid]);
+                            if (gt == up) {
+                                double td = cd[tid]; cd[tid] = cd[pa]; cd[pa] = td;
+                                uint32_t t1 = ca[tid]; ca[tid] = ca[pa]; ca[pa] = t1;
+                                uint32_t t2 = cb[tid]; cb[tid] = cb[pa]; cb[pa] = t2;
+                                uint32_t t3 = ci[tid]; ci[tid] = ci[pa]; ci[pa] = t3;
+                            }
+                        }
+                        __syncthreads();
+                    }
                 }
             }
             const int np = s_np;
