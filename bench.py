@@ -9,8 +9,10 @@ pool, stopping rule) over the resident synthetic series. Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -20,13 +22,62 @@ sys.path.insert(0, ROOT)
 PEAKS = {  # MI355X published peaks
     "hbm_GBps": 8000.0,
     "mfma_TFLOPs": {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0},
+    # 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one op per
+    # lane per clock (the fp32 figure, 157.3 TFLOP/s, counts an FMA as two
+    # and two ops per lane per clock)
+    "alu_TOPs": 256 * 4 * 16 * 2.4e9 / 1e12,
 }
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = {"enum": "paper_2502_14446_amd/csrc/k_search.hip",
+                  "proj": "paper_2502_14446_amd/csrc/k_hash.hip"}
 METRIC = "top-k motif time-to-solution (s) + hashed subseq·dims/s, BF16 vs FP32 path"
 HBM_KERNELS = ("sort_scatter", "sort_hist", "sort_scan", "enum", "verify", "stats")
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+def source_sha(kernel: str) -> str | None:
+    src = KERNEL_SOURCES.get(kernel)
+    if not src:
+        return None
+    with open(os.path.join(ROOT, src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str) -> float | None:
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or None when
+    there is none or the kernel's source changed since it was taken."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^- (\w+): (\S+)$", line.strip())
+            if m:
+                vals[m.group(1)] = m.group(2)
+    if vals.get("source_sha256") != source_sha(kernel):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy(nbytes: int, reps: int) -> int:
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+    return 0
 
 
 def cpu_baseline(series, p, seed: int, n_cpu: int) -> dict:
@@ -53,11 +104,15 @@ def main() -> int:
     ap.add_argument("--cpu-n", type=int, default=6000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the method has no multi-GPU path here); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         return 2
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy, 4)
 
     import torch
     from paper_2502_14446_amd import momenti as mm
@@ -124,18 +179,22 @@ def main() -> int:
         dom = ranked[0][1]
         v = prof[dom]
         avg_ms = v["ms"] / v["launches"]
+        sec = v["ms"] / 1000.0
         if dom == "proj":
-            ach = v["flops"] / (v["ms"] / 1000.0) / 1e12
-            peak = PEAKS["mfma_TFLOPs"][proj]
-            out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                               "frac": ach / peak, "traffic": None, "kernel": dom,
-                               "avg_launch_ms": avg_ms, "launches_per_step": v["launches"] / args.steps}
+            bound, unit, peak = "mfma", "TFLOP/s", PEAKS["mfma_TFLOPs"][proj]
+            ach = v["flops"] / sec / 1e12
+        elif dom == "enum":
+            # the pair screen is 32-bit integer VALU work
+            bound, unit, peak = "alu", "TOP/s", PEAKS["alu_TOPs"]
+            ach = v["flops"] / sec / 1e12
         else:
-            ach = v["bytes"] / (v["ms"] / 1000.0) / 1e9
-            peak = PEAKS["hbm_GBps"]
-            out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": peak, "unit": "GB/s",
-                               "frac": ach / peak, "traffic": None, "kernel": dom,
-                               "avg_launch_ms": avg_ms, "launches_per_step": v["launches"] / args.steps}
+            bound, unit, peak = "hbm", "GB/s", PEAKS["hbm_GBps"]
+            ach = v["bytes"] / sec / 1e9
+        out["roofline"] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                           "traffic": measured_traffic(dom, args.workload), "kernel": dom,
+                           "avg_launch_ms": avg_ms, "launches_per_step": v["launches"] / args.steps,
+                           "algorithmic_bytes_per_launch": v["bytes"] / v["launches"],
+                           "algorithmic_ops_per_launch": v["flops"] / v["launches"]}
         pj = prof.get("proj")
         if pj and pj["launches"]:
             ach = pj["flops"] / (pj["ms"] / 1000.0) / 1e12

@@ -91,11 +91,13 @@ typedef struct {
  * device time, and the algorithmic bytes moved / flops done by those launches
  * (what the method must read and write, not cache traffic). */
 typedef struct {
-    char name[24];
+    char name[24];        /* kernel family (stats, proj, sort_scatter, enum, ...) */
     int64_t launches;
-    double ms;
-    double bytes;
-    double flops;
+    double ms;            /* summed launch durations, HIP events on the plan's stream */
+    double bytes;         /* algorithmic device-memory bytes (minimum traffic) */
+    double flops;         /* algorithmic operations: floating-point for stats, proj and
+                             verify; for enum the integer screen operations, 5 per
+                             fingerprint word and one compare for every pair scanned */
 } momenti_kprof;
 
 typedef struct {

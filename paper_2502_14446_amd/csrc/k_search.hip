@@ -153,25 +153,49 @@ __global__ __launch_bounds__(256) void k_hist(const KT* __restrict__ kin, const 
         atomicAdd(&cnt[(uint32_t)(key >> (8 * pass)) & 255u], 1u);
     }
     __syncthreads();
-    hist[((int64_t)seg * 256 + threadIdx.x) * tiles + tile] = cnt[threadIdx.x];
+    hist[((int64_t)seg * tiles + tile) * 256 + threadIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of one segment's digit-major histogram (digit, tile).
+// Scatter offsets of one segment from its tile-major histogram [tile][digit]:
+// offset(t, dg) = (elements of digits < dg) + (elements of digit dg in tiles
+// < t), written in place. Four groups of 256 threads (one per digit) take a
+// quarter of the tiles each; every row of 256 counts is one coalesced access.
 __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ hist, int64_t tiles)
 {
+    __shared__ uint32_t part[4][256];
     __shared__ uint32_t sh[16];
-    uint32_t* h = hist + (int64_t)blockIdx.x * 256 * tiles;
-    const int64_t total = 256 * tiles;
-    const int64_t per = (total + 1023) / 1024;
-    const int64_t lo = (int64_t)threadIdx.x * per;
-    const int64_t hi = lo + per < total ? lo + per : total;
+    uint32_t* h = hist + (int64_t)blockIdx.x * tiles * 256;
+    const int grp = threadIdx.x >> 8, dg = threadIdx.x & 255;
+    const int64_t per = (tiles + 3) / 4;
+    const int64_t t0 = grp * per, t1 = t0 + per < tiles ? t0 + per : tiles;
     uint32_t s = 0;
-    for (int64_t q = lo; q < hi; ++q) s += h[q];
-    uint32_t tot;
-    uint32_t run = block_excl_scan<1024>(s, sh, &tot);
-    for (int64_t q = lo; q < hi; ++q) {
-        uint32_t v = h[q];
-        h[q] = run;
+    int64_t t = t0;
+    for (; t + 4 <= t1; t += 4)
+        s += h[t * 256 + dg] + h[(t + 1) * 256 + dg] + h[(t + 2) * 256 + dg] + h[(t + 3) * 256 + dg];
+    for (; t < t1; ++t) s += h[t * 256 + dg];
+    part[grp][dg] = s;
+    __syncthreads();
+    // per digit: total over the tiles, and the count before this group's tiles
+    uint32_t before = 0, total = 0;
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t v = part[q][dg];
+        before += q < grp ? v : 0u;
+        total += v;
+    }
+    // digit bases: exclusive scan of the totals over the 256 digits (group 0)
+    uint32_t base = 0;
+    {
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<1024>(grp == 0 ? total : 0u, sh, &tot);
+        __syncthreads();
+        if (grp == 0) part[0][dg] = ex;
+        __syncthreads();
+        base = part[0][dg];
+    }
+    uint32_t run = base + before;
+    for (t = t0; t < t1; ++t) {
+        const uint32_t v = h[t * 256 + dg];
+        h[t * 256 + dg] = run;
         run += v;
     }
 }
@@ -196,7 +220,7 @@ __global__ __launch_bounds__(256) void k_scatter(const KT* __restrict__ kin, con
     const int count = (int)((g.ns - base) < kSortTile ? (g.ns - base) : kSortTile);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int q = threadIdx.x; q < 4 * 256; q += 256) (&wcnt[0][0])[q] = 0;
-    gofs[threadIdx.x] = hist[((int64_t)seg * 256 + threadIdx.x) * tiles + tile];
+    gofs[threadIdx.x] = hist[((int64_t)seg * tiles + tile) * 256 + threadIdx.x];
     __syncthreads();
 
     SegPtr sp;

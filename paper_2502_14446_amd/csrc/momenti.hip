@@ -1063,7 +1063,8 @@ restart:
                 // pass the screen re-read 4 D index words: negligible);
                 // verification read 2 D w samples per candidate
                 const uint32_t nc = std::min(cnt.n_cand, p->cap);
-                prof_set(p, enum_slot, elems * kb + (double)cnt.n_memb * (4.0 + 4.0 * nw), 0.0);
+                prof_set(p, enum_slot, elems * kb + (double)cnt.n_memb * (4.0 + 4.0 * nw),
+                         (double)cnt.n_coll * (5.0 * nw + 1.0));
                 prof_set(p, verify_slot, (double)nc * (2.0 * p->D * p->w * elem_x + 32.0 * p->D + sizeof(VRec)),
                          (double)nc * 6.0 * p->D * p->w);
                 prof_flush(p);
