@@ -80,12 +80,12 @@ def calibrate_copy(nbytes: int, reps: int) -> int:
     return 0
 
 
-def cpu_baseline(series, p, seed: int, n_cpu: int) -> dict:
+def cpu_baseline(series, p, seed: int, n_cpu: int, r_scale: float) -> dict:
     import oracle
     x = series.x[:, :n_cpu]
     t0 = time.perf_counter()
     res = oracle.lsh_pipeline(x, p["w"], p["d"], p["k"], p["delta"], seed,
-                              mem_limit=p["mem_limit"], elem_bytes=4)
+                              mem_limit=p["mem_limit"], elem_bytes=4, r_scale=r_scale)
     dt = time.perf_counter() - t0
     ns = n_cpu - p["w"] + 1
     return {"value": ns * p["D"] / dt, "unit": "subseq·dims/s", "cores": 1, "kind": "oracle",
@@ -104,6 +104,10 @@ def main() -> int:
     ap.add_argument("--cpu-n", type=int, default=6000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--r-scale", type=float, default=0.0,
+                    help="r as a multiple of the section 6.1 estimate (default: the workload's)")
+    ap.add_argument("--max-pairs", type=float, default=5e13,
+                    help="work budget in colliding pairs per round group (0: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -127,8 +131,10 @@ def main() -> int:
         f"delta={p['delta']} proj={proj}")
     x = torch.from_numpy(s.as_dtype()).to("cuda:0")
     torch.cuda.synchronize()
+    r_scale = args.r_scale if args.r_scale > 0 else p.get("r_scale", 1.0)
     plan = mm.Plan(s.n, s.D, p["w"], "f32" if s.dtype == "f32" else "f64", p["mem_limit"],
-                   device_series=True, seed=seed, proj=proj, profile=not args.no_profile)
+                   device_series=True, seed=seed, proj=proj, profile=not args.no_profile,
+                   r_scale=r_scale, max_pairs=args.max_pairs)
 
     def step():
         plan.hash(x)
@@ -165,11 +171,11 @@ def main() -> int:
         "dtype": proj, "data": "synthetic",
         "config": {"workload": args.workload, "D": s.D, "n": s.n, "w": p["w"], "d": p["d"],
                    "k": p["k"], "delta": p["delta"], "mem_limit": p["mem_limit"],
-                   "series": s.dtype, "proj": proj, "K": 8, "L_used": prm["L"]},
+                   "series": s.dtype, "proj": proj, "K": 8, "L_used": prm["L"], "r_scale": r_scale},
         "tts_s": ms / 1000.0,
         "hash_subseq_dims_per_s": units / (sum(r["t_hash_ms"] for r in reps) / len(reps) / 1000.0),
         "hash_ms": sum(r["t_hash_ms"] for r in reps) / len(reps),
-        "stop": [rep["i_stop"], rep["j_stop"]], "r": prm["r"],
+        "stop": [rep["i_stop"], rep["j_stop"]], "r": prm["r"], "status": rc,
         "n_cand": rep["n_cand"], "n_collisions": rep["n_collisions"],
         "planted_recovered": f"{len(planted & found)}/{len(planted)}",
     }
@@ -202,7 +208,7 @@ def main() -> int:
                                 "frac": ach / PEAKS["mfma_TFLOPs"][proj]}
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on the first {args.cpu_n} points")
-        out["cpu_baseline"] = cpu_baseline(s, p, seed, args.cpu_n)
+        out["cpu_baseline"] = cpu_baseline(s, p, seed, args.cpu_n, r_scale)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -42,6 +42,8 @@ extern "C" {
 /* Status codes. */
 #define MOMENTI_OK 0             /* the search stopped under the stopping rule */
 #define MOMENTI_OK_FALLBACK 1    /* no round stopped: the exact all-pairs answer was returned */
+#define MOMENTI_OK_PARTIAL 2     /* opts.max_pairs ended the search before the stopping rule held:
+                                    out holds TOP as it stood (an anytime answer, no guarantee) */
 #define MOMENTI_E_ARG (-1)       /* invalid argument (see each function) */
 #define MOMENTI_E_NOMEM (-2)     /* mem_limit too small for the smallest index, or a device allocation failed */
 #define MOMENTI_E_DEVICE (-3)    /* a HIP runtime call failed */
@@ -78,12 +80,20 @@ typedef struct {
     int32_t K;                /* maximum concatenations: even, 2..8 (default 8, section 7 defaults) */
     int32_t L;                /* maximum repetitions, 1..1024 (default 200) */
     double r;                 /* quantisation width of Eq. drp; <= 0 estimates it (section 6.1) */
+    double r_scale;           /* with r <= 0: use r_scale times the estimate (<= 0 means 1).
+                                 Section 6.1 leaves r free (any r keeps the guarantee; section
+                                 7.4 varies it): a larger r makes the stopping rule hold at
+                                 longer prefixes for the same distances, at the price of more
+                                 collisions per round */
     int32_t proj;             /* MOMENTI_PROJ_* (default F32) */
     int32_t stop_rule;        /* MOMENTI_STOP_* (default TENSOR) */
     int32_t series_on_device; /* 1: the series pointer passed to momenti_hash is device memory */
     int32_t pool_size;        /* verified pairs kept on the device; 0 = max(4096, 64 k) */
     int32_t batch_reps;       /* repetitions traversed per launch; 0 = chosen from mem_limit */
     int32_t profile;          /* 1: time every kernel launch with HIP events (momenti_get_profile) */
+    double max_pairs;         /* work budget: a round group whose colliding pairs are estimated
+                                 (from one probed repetition) above this is not traversed and
+                                 the search returns MOMENTI_OK_PARTIAL; <= 0: no budget */
     void* stream;             /* hipStream_t, NULL = default stream */
 } momenti_opts;
 
@@ -114,7 +124,8 @@ typedef struct {
     int32_t L_used, K;        /* repetitions after the memory cap; concatenations */
     double r;                 /* quantisation width in use */
     int64_t n_steps;          /* (round, repetition) steps traversed */
-    int64_t n_collisions;     /* non-trivial one-dimensional colliding pairs scanned */
+    int64_t n_collisions;     /* pairs of windows with equal prefixes in the traversed segments
+                                 (one dimension each; trivial matches included) */
     int64_t n_cand;           /* candidate pairs emitted (W >= d, first time at this repetition) */
     int64_t n_verified;       /* dist_d evaluations */
     uint64_t peak_bytes;      /* device bytes held by the plan at its peak */
@@ -122,6 +133,8 @@ typedef struct {
     int32_t pool_overflow;    /* times the verified-pair pool had to be enlarged */
     int32_t batch_reps;       /* repetitions per launch actually used */
     int32_t first_group_lo;   /* rounds K .. first_group_lo were traversed from one sort */
+    int32_t budget_round;     /* MOMENTI_OK_PARTIAL: the highest round not traversed; else 0 */
+    int32_t reserved;
 } momenti_report;
 
 /* Fill *o with the defaults (K = 8, L = 200, r estimated, F32 projection,
@@ -157,8 +170,9 @@ int momenti_hash(momenti_plan* p, const void* series);
  * fewer non-overlapping non-trivial pairs exist). rep may be NULL.
  * d in [1, D], k in [1, 4096], delta in (0, 1).
  * Returns MOMENTI_OK, MOMENTI_OK_FALLBACK (exact answer, no step stopped),
- * or E_ARG, E_STATE (momenti_hash not called), E_NOMEM, E_DEVICE, E_UNSUPPORTED
- * (the exact fallback is limited to n - w + 1 <= 65536 windows). */
+ * MOMENTI_OK_PARTIAL (opts.max_pairs reached: TOP so far, possibly fewer than
+ * k pairs), or E_ARG, E_STATE (momenti_hash not called), E_NOMEM, E_DEVICE,
+ * E_UNSUPPORTED (the exact fallback is limited to n - w + 1 <= 65536 windows). */
 int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
                    int32_t* n_out, momenti_report* rep);
 

@@ -310,8 +310,10 @@ def lsh_search(x, w: int, d: int, k: int, delta: float, words, K: int, L: int, r
 
 def lsh_pipeline(x, w: int, d: int, k: int, delta: float, seed: int, K: int = 8,
                  L_max: int = 200, mem_limit: Optional[int] = None, elem_bytes: int = 8,
-                 r: Optional[float] = None, rule: int = STOP_TENSOR, trace: bool = False) -> Dict:
-    """The whole method: L under the memory cap, draws, r, hashes, packing, search."""
+                 r: Optional[float] = None, rule: int = STOP_TENSOR, trace: bool = False,
+                 r_scale: float = 1.0) -> Dict:
+    """The whole method: L under the memory cap, draws, r, hashes, packing, search.
+    Without an explicit r, r is r_scale times the section 6.1 estimate."""
     x = _f64(x)
     D, n = x.shape
     ns = n - w + 1
@@ -322,7 +324,7 @@ def lsh_pipeline(x, w: int, d: int, k: int, delta: float, seed: int, K: int = 8,
     NF = nl + nr
     Ccols = 4 * NF
     R, U = draw_projections(seed, D, w, Ccols)
-    rr = estimate_r(x, w, seed) if r is None else float(r)
+    rr = estimate_r(x, w, seed) * (r_scale if r_scale > 0 else 1.0) if r is None else float(r)
     by = np.zeros((D, ns, Ccols), dtype=np.uint8)
     for f in range(D):
         by[f], _, _ = hash_dim(x[f], w, R[f], U[f], rr, want_pre=False)

@@ -409,6 +409,8 @@ void momenti_default_opts(momenti_opts* o)
     o->K = 8;
     o->L = 200;
     o->r = 0.0;
+    o->r_scale = 1.0;
+    o->max_pairs = 0.0;
     o->proj = MOMENTI_PROJ_F32;
     o->stop_rule = MOMENTI_STOP_TENSOR;
 }
@@ -452,6 +454,8 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
     if (o.stop_rule != MOMENTI_STOP_TENSOR && o.stop_rule != MOMENTI_STOP_LEMMA52 &&
         o.stop_rule != MOMENTI_STOP_TENSOR_LITERAL)
         return fail(MOMENTI_E_ARG, "bad stop rule %d", o.stop_rule);
+    if (!std::isfinite(o.r_scale) || !std::isfinite(o.max_pairs) || !std::isfinite(o.r))
+        return fail(MOMENTI_E_ARG, "r, r_scale and max_pairs must be finite");
     if (o.pool_size < 0 || o.batch_reps < 0) return fail(MOMENTI_E_ARG, "negative pool/batch size");
 
     const int elem = dtype == MOMENTI_F64 ? 8 : 4;
@@ -610,6 +614,7 @@ int momenti_hash(momenti_plan* p, const void* series)
         }
         r = (hi - lo) / 256.0;
         if (!(r > 0.0) || !std::isfinite(r)) r = 1.0;
+        if (p->o.r_scale > 0.0) r *= p->o.r_scale;
     }
     p->r = r;
     {
@@ -983,6 +988,15 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     }
     const auto groups = round_groups(p->K, pairs_est, 8.0 * (double)p->ns * Ds * p->L);
     R.first_group_lo = groups[0].second;
+    static const int verbose = [] {
+        const char* v = std::getenv("MOMENTI_VERBOSE");
+        return v ? std::atoi(v) : 0;
+    }();
+    if (verbose) {
+        std::fprintf(stderr, "[momenti] probe: estimated pairs per round");
+        for (int i = p->K; i >= 1; --i) std::fprintf(stderr, " %d:%.3g", i, pairs_est[i]);
+        std::fprintf(stderr, "\n");
+    }
 
     const bool tracing = p->tr_cand || p->tr_top_size;
     if (p->tr_count) *p->tr_count = 0;
@@ -990,10 +1004,6 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         for (int64_t s = 0; s < p->tr_steps_cap; ++s) p->tr_top_size[s] = -1;
     std::vector<Cand> hcand;
     std::vector<VRec> hsnap;
-    static const int verbose = [] {
-        const char* v = std::getenv("MOMENTI_VERBOSE");
-        return v ? std::atoi(v) : 0;
-    }();
     const double elem_x = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
     unsigned long long n_screened = 0;
     uint32_t max_run = 0;
@@ -1006,10 +1016,27 @@ restart:
         const int i_hi = gr.first, i_lo = gr.second;
         const int s0 = (p->K - i_hi) * p->L;
         const int nsteps = (i_hi - i_lo + 1) * p->L;
-        if (verbose && gr == groups[0]) {
-            std::fprintf(stderr, "[momenti] probe: estimated pairs per round");
-            for (int i = p->K; i >= 1; --i) std::fprintf(stderr, " %d:%.3g", i, pairs_est[i]);
-            std::fprintf(stderr, "\n");
+        if (p->o.max_pairs > 0.0 && pairs_est[i_lo] > p->o.max_pairs) {
+            // over the work budget: answer with TOP as it stands (anytime)
+            PoolState ps;
+            HIP_OK(hipMemcpyAsync(p->host_status + 64, st_pool(p), sizeof ps, hipMemcpyDeviceToHost, p->st));
+            HIP_OK(hipStreamSynchronize(p->st));
+            std::memcpy(&ps, p->host_status + 64, sizeof ps);
+            const int nt = std::min(ps.top_n, k);
+            if (nt > 0) {
+                std::vector<VRec> tv(nt);
+                HIP_OK(hipMemcpy(tv.data(), p->top, (size_t)nt * sizeof(VRec), hipMemcpyDeviceToHost));
+                to_motifs(tv, nt, out);
+            }
+            *n_out = nt;
+            if (verbose)
+                std::fprintf(stderr, "[momenti] budget: rounds %d..%d estimated at %.3g pairs > %.3g; %d motifs so far\n",
+                             i_hi, i_lo, pairs_est[i_lo], p->o.max_pairs, nt);
+            R.budget_round = i_hi;
+            R.peak_bytes = p->peak;
+            R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rep) *rep = R;
+            return MOMENTI_OK_PARTIAL;
         }
         if (verbose) {
             std::fprintf(stderr, "[momenti] rounds %d..%d: %.1f ms, steps %lld, collisions %lld, screened %llu, longest run %u, candidates %lld |",

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmomenti.so")
 
-OK, OK_FALLBACK = 0, 1
+OK, OK_FALLBACK, OK_PARTIAL = 0, 1, 2
 E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 PROJ = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
@@ -31,9 +31,10 @@ EXPORTS = [
 
 class Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("K", C.c_int32), ("L", C.c_int32), ("r", C.c_double),
+                ("r_scale", C.c_double),
                 ("proj", C.c_int32), ("stop_rule", C.c_int32), ("series_on_device", C.c_int32),
                 ("pool_size", C.c_int32), ("batch_reps", C.c_int32), ("profile", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("max_pairs", C.c_double), ("stream", C.c_void_p)]
 
 
 class KProf(C.Structure):
@@ -52,7 +53,8 @@ class Report(C.Structure):
                 ("K", C.c_int32), ("r", C.c_double), ("n_steps", C.c_int64),
                 ("n_collisions", C.c_int64), ("n_cand", C.c_int64), ("n_verified", C.c_int64),
                 ("peak_bytes", C.c_uint64), ("fallback", C.c_int32), ("pool_overflow", C.c_int32),
-                ("batch_reps", C.c_int32), ("first_group_lo", C.c_int32)]
+                ("batch_reps", C.c_int32), ("first_group_lo", C.c_int32),
+                ("budget_round", C.c_int32), ("reserved", C.c_int32)]
 
 
 class MomentiError(RuntimeError):
@@ -105,10 +107,11 @@ def _check(rc: int) -> int:
 
 def make_opts(seed: int = 0x5EED, K: int = 8, L: int = 200, r: float = 0.0, proj: str = "f32",
               stop: str = "tensor", series_on_device: bool = False, pool_size: int = 0,
-              batch_reps: int = 0, profile: bool = False, stream: Optional[int] = None) -> Opts:
+              batch_reps: int = 0, profile: bool = False, stream: Optional[int] = None,
+              r_scale: float = 1.0, max_pairs: float = 0.0) -> Opts:
     o = Opts()
     lib().momenti_default_opts(C.byref(o))
-    o.seed, o.K, o.L, o.r = seed, K, L, r
+    o.seed, o.K, o.L, o.r, o.r_scale, o.max_pairs = seed, K, L, r, r_scale, max_pairs
     o.proj, o.stop_rule = PROJ[proj], STOP[stop]
     o.series_on_device = 1 if series_on_device else 0
     o.pool_size, o.batch_reps = pool_size, batch_reps
@@ -127,7 +130,7 @@ def _motifs(arr, count: int) -> List[Dict]:
 
 
 def _report(r: Report) -> Dict:
-    return {name: getattr(r, name) for name, _ in Report._fields_}
+    return {name: getattr(r, name) for name, _ in Report._fields_ if name != "reserved"}
 
 
 def _torch_stream_handle() -> Optional[int]:

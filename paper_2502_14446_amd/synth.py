@@ -140,13 +140,15 @@ WORKLOADS = {
     # plain method at scale: D=8, n=1e6, w=300, d=3, k=10, delta=0.05, 8 GB cap, fp32
     "rw8_1m": dict(D=8, n=1_000_000, w=300, d=3, k=10, delta=0.05, n_motifs=10,
                    motif_dims=3, dtype="f32", proj="f32", mem_limit=8_000_000_000),
-    # precision: D=32, n=4,194,304, w=1000, d=8, k=10, random walks + sinusoids
+    # precision: D=32, n=4,194,304, w=1000, d=8, k=10, random walks + sinusoids;
+    # r at r_scale times the estimate (with the estimate itself no step stops
+    # above round 1 for these distances and d)
     "rwsin32_4m": dict(D=32, n=4_194_304, w=1000, d=8, k=10, delta=0.05, n_motifs=10,
                        motif_dims=8, dtype="f32", proj="bf16", sinusoids=True,
-                       mem_limit=64_000_000_000),
+                       mem_limit=64_000_000_000, r_scale=4.0),
     # large fp8: D=128, n=1e6, w=500, d=16, k=50, delta=0.01, 64 GB cap
     "rw128_1m": dict(D=128, n=1_000_000, w=500, d=16, k=50, delta=0.01, n_motifs=50,
-                     motif_dims=16, dtype="f32", proj="fp8", mem_limit=64_000_000_000),
+                     motif_dims=16, dtype="f32", proj="fp8", mem_limit=64_000_000_000, r_scale=6.0),
 }
 
 DATA_SEED = {"tiny": 0xD00D01, "rw8_1m": 0xD00D02, "rwsin32_4m": 0xD00D03, "rw128_1m": 0xD00D05}

@@ -101,6 +101,42 @@ def test_stats_and_r_match_oracle(orc):
     plan.close()
 
 
+def test_r_scale_multiplies_the_estimate(orc):
+    # r = r_scale x the section 6.1 estimate, bit for bit, and the index at
+    # that r matches the oracle's (FP64 projection)
+    s, p = synth.workload("tiny")
+    seed = synth.LSH_SEED["tiny"]
+    plan, _ = _plan(s, p, "f64", seed, r_scale=2.5)
+    prm = plan.params()
+    r0 = orc.estimate_r(s.x, p["w"], seed)
+    assert prm["r"] == r0 * 2.5
+    R, U = orc.draw_projections(seed, s.D, p["w"], 4 * prm["NF"])
+    ref_sym, pre, sab = _oracle_symbols(orc, s.x, p["w"], R, U, prm["r"])
+    gsym = _unpack(plan.hashes(), 8)
+    bad_out, bad_in, near, diff = _check_symbols(gsym, ref_sym, pre, _band("f64", p["w"], pre, sab, prm["r"]), 8)
+    assert bad_out == 0 and bad_in == 0 and diff == 0
+    plan.close()
+
+
+def test_work_budget_returns_partial_answer(orc):
+    s, p = synth.workload("tiny")
+    seed = synth.LSH_SEED["tiny"]
+    # a budget below any round's collisions: nothing is traversed
+    plan, _ = _plan(s, p, "f64", seed, max_pairs=1e-6)
+    got, rep, rc = plan.search(p["d"], p["k"], p["delta"])
+    assert rc == mm.OK_PARTIAL and got == [] and rep["budget_round"] == 8 and rep["i_stop"] == 0
+    plan.close()
+    # a budget above every round's collisions changes nothing
+    plan, _ = _plan(s, p, "f64", seed, max_pairs=1e30)
+    got2, rep2, rc2 = plan.search(p["d"], p["k"], p["delta"])
+    plan.close()
+    plan, _ = _plan(s, p, "f64", seed)
+    got3, rep3, rc3 = plan.search(p["d"], p["k"], p["delta"])
+    plan.close()
+    assert rc2 == rc3 and rep2["budget_round"] == 0
+    assert [(m["a"], m["b"]) for m in got2] == [(m["a"], m["b"]) for m in got3]
+
+
 @pytest.mark.parametrize("w,n", [(4, 300), (63, 5000), (300, 12001), (1000, 9000)])
 def test_stats_match_oracle_across_window_lengths(orc, w, n):
     s = synth.make_series(11 + w, 3, n, w, 0, 0, dtype="f32")
