@@ -181,6 +181,32 @@ int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_
                  int32_t k, double delta, uint64_t mem_limit, const momenti_opts* opts,
                  momenti_motif* out, int32_t* n_out, momenti_report* rep);
 
+/* One independent series of a batch (momenti_topk_batch). series is [D][n],
+ * f32 or f64 (dtype), on the host or the device as opts->series_on_device
+ * says; it is borrowed for the duration of the call. */
+typedef struct {
+    const void* series;
+    int64_t n;
+    int32_t dtype;            /* MOMENTI_F64 or MOMENTI_F32 */
+    int32_t D, w, d, k;
+    double delta;
+} momenti_job;
+
+/* Many independent series (e.g. a fleet of sensors): job q is run exactly as
+ * momenti_topk(jobs[q]..., mem_limit, opts) would run it, with identical
+ * results; up to `workers` (1..16) jobs are in flight at once, each worker on
+ * its own stream with device blocks reused from one series to the next.
+ * mem_limit applies to each job (so up to workers x mem_limit are held);
+ * opts->stream is ignored. Device series must be ready when this is called.
+ * out receives job q's motifs at offset k_0 + ... + k_{q-1} (caller-owned,
+ * room for the sum of the k); n_out[q], status[q] and (if reps is not NULL)
+ * reps[q] receive what momenti_topk would return for it. Returns MOMENTI_OK
+ * when no job failed, else the first failing job's status (every job is
+ * still attempted; momenti_last_error names the job). */
+int momenti_topk_batch(const momenti_job* jobs, int32_t count, uint64_t mem_limit,
+                       const momenti_opts* opts, int32_t workers, momenti_motif* out,
+                       int32_t* n_out, int32_t* status, momenti_report* reps);
+
 /* Release every resource of the plan (NULL is ignored). */
 void momenti_destroy(momenti_plan* p);
 

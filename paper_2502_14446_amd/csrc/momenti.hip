@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -18,6 +19,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/momenti.h"
@@ -173,7 +176,54 @@ struct Profiler {
 };
 
 // ------------------------------------------------------------------ plan
+// Device blocks kept for reuse by the plans of one batch worker: a freed
+// block goes back here and is handed to the next request it fits (at most
+// twice the size asked for), so consecutive series stop paying for hipMalloc
+// and hipFree. Blocks are released when the worker ends.
+struct BlockCache {
+    std::vector<std::pair<size_t, void*>> idle;    // (capacity, block)
+    std::vector<std::pair<void*, size_t>> owned;   // every block, with its capacity
+    void* take(size_t bytes)
+    {
+        int best = -1;
+        for (int q = 0; q < (int)idle.size(); ++q)
+            if (idle[q].first >= bytes && idle[q].first <= 2 * bytes + (1u << 20) &&
+                (best < 0 || idle[q].first < idle[best].first))
+                best = q;
+        if (best < 0) return nullptr;
+        void* b = idle[best].second;
+        idle.erase(idle.begin() + best);
+        return b;
+    }
+    void give(void* b)
+    {
+        for (auto& o : owned)
+            if (o.first == b) {
+                idle.push_back({o.second, b});
+                return;
+            }
+        (void)hipFree(b);   // not ours
+    }
+    void trim()   // return idle blocks to the runtime
+    {
+        for (auto& b : idle) {
+            for (size_t q = 0; q < owned.size(); ++q)
+                if (owned[q].first == b.second) {
+                    owned.erase(owned.begin() + q);
+                    break;
+                }
+            (void)hipFree(b.second);
+        }
+        idle.clear();
+    }
+    ~BlockCache()
+    {
+        for (auto& o : owned) (void)hipFree(o.first);
+    }
+};
+
 struct momenti_plan {
+    BlockCache* cache = nullptr;   // set for plans run by a batch worker
     int64_t n = 0, ns = 0;
     int D = 0, w = 0, dtype = 1;
     uint64_t mem_limit = 0;
@@ -238,12 +288,23 @@ static int dalloc(momenti_plan* p, void** ptr, size_t bytes)
     if (p->bytes + bytes > p->mem_limit)
         return fail(MOMENTI_E_NOMEM, "device budget exceeded: %llu + %zu > %llu bytes",
                     (unsigned long long)p->bytes, bytes, (unsigned long long)p->mem_limit);
+    if (p->cache && (*ptr = p->cache->take(bytes)) != nullptr) {
+        p->bytes += bytes;
+        p->peak = std::max(p->peak, p->bytes);
+        return MOMENTI_OK;
+    }
     hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess && p->cache) {
+        (void)hipGetLastError();
+        p->cache->trim();   // idle blocks may be what is missing
+        e = hipMalloc(ptr, bytes);
+    }
     if (e != hipSuccess) {
         *ptr = nullptr;
         (void)hipGetLastError();
         return fail(MOMENTI_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
+    if (p->cache) p->cache->owned.push_back({*ptr, bytes});
     p->bytes += bytes;
     p->peak = std::max(p->peak, p->bytes);
     return MOMENTI_OK;
@@ -261,9 +322,21 @@ static int dalloc_t(momenti_plan* p, T** ptr, size_t bytes)
 static void dfree(momenti_plan* p, void* ptr, size_t bytes)
 {
     if (!ptr) return;
-    (void)hipFree(ptr);
+    if (p->cache)
+        p->cache->give(ptr);   // the worker's stream keeps later uses in order
+    else
+        (void)hipFree(ptr);
     if (bytes == 0) bytes = 16;
     p->bytes -= std::min<uint64_t>(p->bytes, bytes);
+}
+
+// Host <-> device copy ordered on the plan's stream (which may be a
+// non-blocking stream of a batch worker), complete on return.
+static hipError_t copy_sync(momenti_plan* p, void* dst, const void* src, size_t bytes, hipMemcpyKind kind)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, p->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+    return e;
 }
 
 static hipEvent_t prof_event(momenti_plan* p)
@@ -434,8 +507,17 @@ void momenti_destroy(momenti_plan* p)
     delete p;
 }
 
+static int prepare_impl(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t dtype,
+                        uint64_t mem_limit, const momenti_opts* opts, BlockCache* cache);
+
 int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t dtype,
                     uint64_t mem_limit, const momenti_opts* opts)
+{
+    return prepare_impl(out, n, D, w, dtype, mem_limit, opts, nullptr);
+}
+
+static int prepare_impl(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t dtype,
+                        uint64_t mem_limit, const momenti_opts* opts, BlockCache* cache)
 {
     g_err.clear();
     if (!out) return fail(MOMENTI_E_ARG, "out is NULL");
@@ -465,6 +547,7 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
 
     momenti_plan* p = new (std::nothrow) momenti_plan();
     if (!p) return fail(MOMENTI_E_NOMEM, "host allocation failed");
+    p->cache = cache;
     p->n = n; p->ns = n - w + 1; p->D = D; p->w = w; p->dtype = dtype; p->mem_limit = mem_limit;
     p->o = o; p->K = o.K; p->L = L;
     tensor_shape(L, &p->m, &p->NL, &p->NR);
@@ -500,12 +583,12 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
     }
     hipError_t e;
     if (o.proj == MOMENTI_PROJ_F64) {
-        e = hipMemcpy(p->R, R.data(), R.size() * 8, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(p->U, U.data(), U.size() * 8, hipMemcpyHostToDevice);
+        e = copy_sync(p, p->R, R.data(), R.size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = copy_sync(p, p->U, U.data(), U.size() * 8, hipMemcpyHostToDevice);
     } else if (o.proj == MOMENTI_PROJ_F32) {
         std::vector<float> Rf(R.begin(), R.end()), Uf(U.begin(), U.end());
-        e = hipMemcpy(p->R, Rf.data(), Rf.size() * 4, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(p->U, Uf.data(), Uf.size() * 4, hipMemcpyHostToDevice);
+        e = copy_sync(p, p->R, Rf.data(), Rf.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = copy_sync(p, p->U, Uf.data(), Uf.size() * 4, hipMemcpyHostToDevice);
     } else {
         // low precision: column-major [f][c][t] so that a lane loads consecutive t
         std::vector<float> Uf(U.begin(), U.end());
@@ -517,7 +600,7 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
                     for (int c = 0; c < p->Cpad; ++c)
                         Rq[((size_t)f * p->Cpad + c) * p->wpad + t] =
                             to_bf16_bits(R[((size_t)f * p->wpad + t) * p->Cpad + c]);
-            e = hipMemcpy(p->R, Rq.data(), cnt * 2, hipMemcpyHostToDevice);
+            e = copy_sync(p, p->R, Rq.data(), cnt * 2, hipMemcpyHostToDevice);
         } else {
             std::vector<uint8_t> Rq(cnt, 0);
             for (int f = 0; f < D; ++f)
@@ -525,9 +608,9 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
                     for (int c = 0; c < p->Cpad; ++c)
                         Rq[((size_t)f * p->Cpad + c) * p->wpad + t] =
                             to_e4m3_bits(R[((size_t)f * p->wpad + t) * p->Cpad + c]);
-            e = hipMemcpy(p->R, Rq.data(), cnt, hipMemcpyHostToDevice);
+            e = copy_sync(p, p->R, Rq.data(), cnt, hipMemcpyHostToDevice);
         }
-        if (e == hipSuccess) e = hipMemcpy(p->U, Uf.data(), Uf.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = copy_sync(p, p->U, Uf.data(), Uf.size() * 4, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         momenti_destroy(p);
@@ -656,8 +739,8 @@ int momenti_get_stats(momenti_plan* p, double* mu, double* inv_sigma, size_t cou
     if (!p->have_stats) return fail(MOMENTI_E_STATE, "no statistics yet");
     if (count != (size_t)p->D * p->ns) return fail(MOMENTI_E_ARG, "count must be D * n_s");
     HIP_OK(hipStreamSynchronize(p->st));
-    if (mu) HIP_OK(hipMemcpy(mu, p->mu, count * 8, hipMemcpyDeviceToHost));
-    if (inv_sigma) HIP_OK(hipMemcpy(inv_sigma, p->isig, count * 8, hipMemcpyDeviceToHost));
+    if (mu) HIP_OK(copy_sync(p, mu, p->mu, count * 8, hipMemcpyDeviceToHost));
+    if (inv_sigma) HIP_OK(copy_sync(p, inv_sigma, p->isig, count * 8, hipMemcpyDeviceToHost));
     return MOMENTI_OK;
 }
 
@@ -667,7 +750,7 @@ int momenti_get_hashes(momenti_plan* p, uint32_t* dst, size_t count)
     if (!p->hashed) return fail(MOMENTI_E_STATE, "no index yet");
     if (count != (size_t)p->D * p->NF * p->ns) return fail(MOMENTI_E_ARG, "count must be D * NF * n_s");
     HIP_OK(hipStreamSynchronize(p->st));
-    HIP_OK(hipMemcpy(dst, p->H, count * 4, hipMemcpyDeviceToHost));
+    HIP_OK(copy_sync(p, dst, p->H, count * 4, hipMemcpyDeviceToHost));
     return MOMENTI_OK;
 }
 
@@ -677,7 +760,7 @@ int momenti_set_hashes(momenti_plan* p, const uint32_t* src, size_t count)
     if (!p->have_stats) return fail(MOMENTI_E_STATE, "momenti_hash must run once first");
     if (count != (size_t)p->D * p->NF * p->ns) return fail(MOMENTI_E_ARG, "count must be D * NF * n_s");
     HIP_OK(hipStreamSynchronize(p->st));
-    HIP_OK(hipMemcpy(p->H, src, count * 4, hipMemcpyHostToDevice));
+    HIP_OK(copy_sync(p, p->H, src, count * 4, hipMemcpyHostToDevice));
     p->hashed = true;
     return MOMENTI_OK;
 }
@@ -1025,7 +1108,7 @@ restart:
             const int nt = std::min(ps.top_n, k);
             if (nt > 0) {
                 std::vector<VRec> tv(nt);
-                HIP_OK(hipMemcpy(tv.data(), p->top, (size_t)nt * sizeof(VRec), hipMemcpyDeviceToHost));
+                HIP_OK(copy_sync(p, tv.data(), p->top, (size_t)nt * sizeof(VRec), hipMemcpyDeviceToHost));
                 to_motifs(tv, nt, out);
             }
             *n_out = nt;
@@ -1122,7 +1205,7 @@ restart:
             R.n_verified += cnt.n_cand;
             if (tracing && p->tr_cand && cnt.n_cand) {
                 hcand.resize(cnt.n_cand);
-                HIP_OK(hipMemcpy(hcand.data(), p->cand, cnt.n_cand * sizeof(Cand), hipMemcpyDeviceToHost));
+                HIP_OK(copy_sync(p, hcand.data(), p->cand, cnt.n_cand * sizeof(Cand), hipMemcpyDeviceToHost));
                 for (const Cand& c : hcand) {
                     const int64_t s = (int64_t)(p->K - (int)c.pad) * p->L + c.j;
                     if (*p->tr_count < p->tr_cap) {
@@ -1139,7 +1222,7 @@ restart:
         if ((rc = replay(p, p->store, stored, p->keep, k, s0, nsteps))) return rc;
         if (tracing && p->tr_top_size) {
             hsnap.resize((size_t)nsteps * k);
-            HIP_OK(hipMemcpy(hsnap.data(), p->snap_tops, hsnap.size() * sizeof(VRec), hipMemcpyDeviceToHost));
+            HIP_OK(copy_sync(p, hsnap.data(), p->snap_tops, hsnap.size() * sizeof(VRec), hipMemcpyDeviceToHost));
             for (int st = 0; st < nsteps; ++st) {
                 const int64_t s = s0 + st;
                 if (s >= p->tr_steps_cap) continue;
@@ -1165,7 +1248,7 @@ restart:
             if (sn.top_n == k &&
                 stop_holds(sn.dist_max, p->r, d, i, J, p->K, p->L, p->m, p->o.stop_rule, delta)) {
                 std::vector<VRec> tv(k);
-                HIP_OK(hipMemcpy(tv.data(), p->snap_tops + (size_t)st * k, (size_t)k * sizeof(VRec),
+                HIP_OK(copy_sync(p, tv.data(), p->snap_tops + (size_t)st * k, (size_t)k * sizeof(VRec),
                                  hipMemcpyDeviceToHost));
                 to_motifs(tv, k, out);
                 *n_out = k;
@@ -1234,7 +1317,7 @@ static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int
             const int got = M <= 0 ? 0 : last.top_n;
             std::vector<VRec> tv(std::max(got, 1));
             if (got)
-                HIP_OK(hipMemcpy(tv.data(), p->snap_tops, (size_t)got * sizeof(VRec), hipMemcpyDeviceToHost));
+                HIP_OK(copy_sync(p, tv.data(), p->snap_tops, (size_t)got * sizeof(VRec), hipMemcpyDeviceToHost));
             to_motifs(tv, got, out);
             *n_out = got;
             return MOMENTI_OK;
@@ -1256,4 +1339,64 @@ extern "C" int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_
     if (rc == MOMENTI_OK) rc = momenti_search(p, d, k, delta, out, n_out, rep);
     momenti_destroy(p);
     return rc;
+}
+
+extern "C" int momenti_topk_batch(const momenti_job* jobs, int32_t count, uint64_t mem_limit,
+                                  const momenti_opts* opts, int32_t workers, momenti_motif* out,
+                                  int32_t* n_out, int32_t* status, momenti_report* reps)
+{
+    g_err.clear();
+    if (count < 0) return fail(MOMENTI_E_ARG, "count=%d is negative", count);
+    if (count == 0) return MOMENTI_OK;
+    if (!jobs || !out || !n_out || !status) return fail(MOMENTI_E_ARG, "NULL argument");
+    if (workers < 1 || workers > 16) return fail(MOMENTI_E_ARG, "workers=%d outside [1, 16]", workers);
+    std::vector<int64_t> off((size_t)count + 1, 0);
+    for (int q = 0; q < count; ++q) {
+        if (jobs[q].k < 1 || jobs[q].k > 4096) return fail(MOMENTI_E_ARG, "job %d: k=%d outside [1, 4096]", q, jobs[q].k);
+        off[q + 1] = off[q] + jobs[q].k;
+    }
+    momenti_opts base;
+    if (opts) base = *opts; else momenti_default_opts(&base);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MOMENTI_E_DEVICE, "no HIP device");
+    std::vector<std::string> errs((size_t)count);
+    std::atomic<int> next{0};
+    const int nw = std::min<int>(workers, count);
+    auto worker = [&]() {
+        (void)hipSetDevice(dev);
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+        BlockCache cache;
+        momenti_opts o = base;
+        o.stream = st;
+        for (int q; (q = next.fetch_add(1)) < count;) {
+            const momenti_job& jb = jobs[q];
+            momenti_report rr{};
+            n_out[q] = 0;
+            momenti_plan* p = nullptr;
+            int rc = prepare_impl(&p, jb.n, jb.D, jb.w, jb.dtype, mem_limit, &o, &cache);
+            if (rc == MOMENTI_OK) {
+                rc = momenti_hash(p, jb.series);
+                if (rc == MOMENTI_OK) rc = momenti_search(p, jb.d, jb.k, jb.delta, out + off[q], &n_out[q], &rr);
+                momenti_destroy(p);
+            }
+            status[q] = rc;
+            if (reps) reps[q] = rr;
+            if (rc < 0) errs[q] = g_err;
+        }
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int q = 1; q < nw; ++q) pool.emplace_back(worker);
+    worker();
+    for (auto& t : pool) t.join();
+    for (int q = 0; q < count; ++q)
+        if (status[q] < 0) {
+            g_err = "job " + std::to_string(q) + ": " + errs[q];
+            return status[q];
+        }
+    return MOMENTI_OK;
 }

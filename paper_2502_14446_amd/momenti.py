@@ -26,6 +26,7 @@ EXPORTS = [
     "momenti_default_opts", "momenti_prepare", "momenti_hash", "momenti_search", "momenti_topk",
     "momenti_destroy", "momenti_last_error", "momenti_get_params", "momenti_get_stats",
     "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace", "momenti_get_profile",
+    "momenti_topk_batch",
 ]
 
 
@@ -35,6 +36,11 @@ class Opts(C.Structure):
                 ("proj", C.c_int32), ("stop_rule", C.c_int32), ("series_on_device", C.c_int32),
                 ("pool_size", C.c_int32), ("batch_reps", C.c_int32), ("profile", C.c_int32),
                 ("max_pairs", C.c_double), ("stream", C.c_void_p)]
+
+
+class Job(C.Structure):
+    _fields_ = [("series", C.c_void_p), ("n", C.c_int64), ("dtype", C.c_int32), ("D", C.c_int32),
+                ("w", C.c_int32), ("d", C.c_int32), ("k", C.c_int32), ("delta", C.c_double)]
 
 
 class KProf(C.Structure):
@@ -90,6 +96,8 @@ def lib():
             "momenti_set_hashes": (i32, [vp, vp, C.c_size_t]),
             "momenti_set_trace": (i32, [vp, vp, i64, vp, vp, vp, i64, i32]),
             "momenti_get_profile": (i32, [vp, P(KProf), i32, P(i32), i32]),
+            "momenti_topk_batch": (i32, [P(Job), i32, u64, P(Opts), i32, P(Motif), P(i32), P(i32),
+                                         P(Report)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -267,3 +275,45 @@ def topk(series, w: int, d: int, k: int, delta: float, mem_limit: int = 8 << 30,
                                    arr.shape[1], arr.shape[0], w, d, k, delta, mem_limit,
                                    C.byref(o), out, C.byref(got), C.byref(rep)))
     return _motifs(out, got.value), _report(rep), rc
+
+
+def topk_batch(jobs, mem_limit: int = 8 << 30, workers: int = 4, dtype: str = "f32",
+               **opts) -> Tuple[List[Tuple[List[Dict], Dict, int]], int]:
+    """Many independent series at once (momenti_topk_batch). jobs: sequence of
+    dicts with keys series ([D][n] numpy array, or torch CUDA tensors for all
+    jobs), w, d, k, delta. Returns ([(motifs, report, status) per job], rc)."""
+    on_dev = [hasattr(j["series"], "is_cuda") and j["series"].is_cuda for j in jobs]
+    if any(on_dev) and not all(on_dev):
+        raise ValueError("either every series is a CUDA tensor or none is")
+    dev = bool(jobs) and all(on_dev)
+    keep = []
+    arr = (Job * max(len(jobs), 1))()
+    for q, j in enumerate(jobs):
+        x = j["series"]
+        if dev:
+            x = x.contiguous()
+            ptr = x.data_ptr()
+        else:
+            x = np.ascontiguousarray(x, dtype=np.float64 if dtype == "f64" else np.float32)
+            ptr = x.ctypes.data
+        keep.append(x)
+        arr[q] = Job(ptr, x.shape[1], F64 if dtype == "f64" else F32, x.shape[0], j["w"], j["d"],
+                     j["k"], j["delta"])
+    if dev:
+        import torch
+        torch.cuda.synchronize()
+    opts.pop("stream", None)
+    o = make_opts(series_on_device=dev, **opts)
+    total = sum(j["k"] for j in jobs)
+    out = (Motif * max(total, 1))()
+    n_out = (C.c_int32 * max(len(jobs), 1))()
+    status = (C.c_int32 * max(len(jobs), 1))()
+    reps = (Report * max(len(jobs), 1))()
+    rc = lib().momenti_topk_batch(arr, len(jobs), mem_limit, C.byref(o), workers, out, n_out, status, reps)
+    if rc in (E_ARG,):
+        _check(rc)
+    res, off = [], 0
+    for q, j in enumerate(jobs):
+        res.append((_motifs(out[off:off + j["k"]], n_out[q]), _report(reps[q]), int(status[q])))
+        off += j["k"]
+    return res, rc

@@ -166,15 +166,30 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> Tuple[
     return s, p
 
 
-def batch_workload(seed: int, count: int = 512, n_lo: int = 10_000, n_hi: int = 500_000):
-    """Many independent series of uneven length and width (w in {50,100,200}, d=ceil(D/4))."""
+def batch_workload(seed: int, count: int = 512, n_lo: int = 10_000, n_hi: int = 500_000,
+                   D_lo: int = 3, D_hi: int = 64, k: int = 5, n_motifs: int = 2):
+    """Many independent series of uneven length and width: n log-uniform in
+    [n_lo, n_hi], D uniform in [D_lo, D_hi], w in {50, 100, 200}, d = ceil(D/4),
+    n_motifs planted motifs each."""
     rng = np.random.default_rng(seed)
     out = []
     for s in range(count):
         n = int(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi))))
-        D = int(rng.integers(3, 65))
+        D = int(rng.integers(D_lo, D_hi + 1))
         w = int(rng.choice([50, 100, 200]))
         d = (D + 3) // 4
-        ser = make_series(seed + 1 + s, D, n, w, 2, d, dtype="f32")
-        out.append((ser, dict(D=D, n=n, w=w, d=d, k=5, delta=0.1)))
+        ser = make_series(seed + 1 + s, D, n, w, n_motifs, d, dtype="f32")
+        out.append((ser, dict(D=D, n=n, w=w, d=d, k=k, delta=0.1)))
     return out
+
+
+# The many-series workloads: the survey's generator (k = 5 with two planted
+# motifs, D up to 64: most searches need very long traversals), and a variant
+# whose series can stop (k = planted motifs = 3, D in 5..16 so that d >= 2,
+# r at 6 times the estimate: with the estimate itself half of them do not
+# stop above the exact fallback or the work budget).
+BATCHES = {
+    "batch64": dict(count=64, n_lo=10_000, n_hi=200_000, D_lo=5, D_hi=16, k=3, n_motifs=3, r_scale=6.0),
+    "batch64_survey": dict(count=64),
+}
+BATCH_SEED = 0xD00D04

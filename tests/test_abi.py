@@ -54,6 +54,26 @@ def test_argument_errors_are_reported_without_touching_a_gpu():
     assert lib.momenti_search(None, 1, 1, 0.1, out, ctypes.byref(n), None) == mm.E_ARG
 
 
+def test_batch_argument_errors_are_reported_without_touching_a_gpu():
+    from paper_2502_14446_amd import momenti as mm
+    lib = mm.lib()
+    o = mm.make_opts()
+    out = (mm.Motif * 4)()
+    n = (ctypes.c_int32 * 2)()
+    st = (ctypes.c_int32 * 2)()
+    jobs = (mm.Job * 2)()
+    # no jobs: nothing to do
+    assert lib.momenti_topk_batch(jobs, 0, 1 << 30, ctypes.byref(o), 2, out, n, st, None) == mm.OK
+    assert lib.momenti_topk_batch(jobs, -1, 1 << 30, ctypes.byref(o), 2, out, n, st, None) == mm.E_ARG
+    assert lib.momenti_topk_batch(None, 2, 1 << 30, ctypes.byref(o), 2, out, n, st, None) == mm.E_ARG
+    jobs[0].k = jobs[1].k = 2
+    assert lib.momenti_topk_batch(jobs, 2, 1 << 30, ctypes.byref(o), 0, out, n, st, None) == mm.E_ARG
+    assert b"workers" in lib.momenti_last_error()
+    jobs[1].k = 0
+    assert lib.momenti_topk_batch(jobs, 2, 1 << 30, ctypes.byref(o), 2, out, n, st, None) == mm.E_ARG
+    assert b"job 1" in lib.momenti_last_error()
+
+
 def test_binding_refuses_to_run_without_the_library(monkeypatch):
     from paper_2502_14446_amd import momenti as mm
     monkeypatch.setattr(mm, "LIB_PATH", "/nonexistent/libmomenti.so")

@@ -118,6 +118,35 @@ def test_r_scale_multiplies_the_estimate(orc):
     plan.close()
 
 
+def _batch_jobs():
+    # uneven series: lengths, widths, window lengths, d and k all differ
+    spec = [(61, 3, 3000, 40, 2, 2), (62, 6, 5200, 60, 2, 3), (63, 4, 2600, 50, 1, 1),
+            (64, 9, 4100, 32, 3, 2), (65, 5, 6400, 80, 2, 4), (66, 12, 3300, 45, 3, 2)]
+    jobs = []
+    for seed, D, n, w, d, k in spec:
+        s = synth.make_series(seed, D, n, w, 2, d, dtype="f32")
+        jobs.append(dict(series=s.as_dtype(), w=w, d=d, k=k, delta=0.1))
+    return jobs
+
+
+@pytest.mark.parametrize("on_device", [False, True])
+def test_batch_matches_one_series_at_a_time(on_device):
+    # every job of a batch gives exactly what a call of its own gives
+    jobs = _batch_jobs()
+    if on_device:
+        for j in jobs:
+            j["series"] = torch.from_numpy(j["series"]).to("cuda")
+    res, rc = mm.topk_batch(jobs, mem_limit=1 << 30, workers=3, seed=77)
+    assert rc == mm.OK
+    for j, (got, rep, st) in zip(jobs, res):
+        x = j["series"].cpu().numpy() if on_device else j["series"]
+        ref, rrep, rrc = mm.topk(x, j["w"], j["d"], j["k"], j["delta"], mem_limit=1 << 30, seed=77)
+        assert st == rrc
+        assert (rep["i_stop"], rep["j_stop"], rep["L_used"], rep["r"]) == \
+            (rrep["i_stop"], rrep["j_stop"], rrep["L_used"], rrep["r"])
+        assert got == ref   # indices, dims and FP64 distances bit for bit
+
+
 def test_work_budget_returns_partial_answer(orc):
     s, p = synth.workload("tiny")
     seed = synth.LSH_SEED["tiny"]
