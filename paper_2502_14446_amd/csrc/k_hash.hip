@@ -351,6 +351,17 @@ __global__ __launch_bounds__(256) void k_proj_f32(const T* __restrict__ x, int64
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+
+// LDS staging of the low-precision projection rows: chunks of kRT (bf16) or
+// kRT8 (fp8) steps of t, rows padded to kRS / kRS8 elements (16 bytes of
+// padding against bank conflicts; every row start stays 16-byte aligned).
+constexpr int kRT = 64, kRS = kRT + 8;
+constexpr int kRT8 = 64, kRS8 = kRT8 + 16;
+__host__ __device__ inline size_t lowp_stage_bytes(int proj, int Cpad)
+{
+    return proj == 2 ? (size_t)2 * Cpad * kRS * 2 : (size_t)2 * Cpad * kRS8;
+}
 
 template <typename T, int WB>
 __device__ inline double load_tile_offset(const T* __restrict__ xf, int64_t n, int64_t a_blk, int wpad,
@@ -391,7 +402,7 @@ __device__ inline void quantize_store(const floatx16 (&acc)[MB][NB], const float
 }
 
 template <typename T, int MB, int NB>
-__global__ __launch_bounds__(256) void k_proj_bf16(const T* __restrict__ x, int64_t n, int64_t ns,
+__global__ __launch_bounds__(256, 2) void k_proj_bf16(const T* __restrict__ x, int64_t n, int64_t ns,
                                                    int w, int wpad, const double* __restrict__ mu,
                                                    const double* __restrict__ isig,
                                                    const __bf16* __restrict__ R,
@@ -424,31 +435,65 @@ __global__ __launch_bounds__(256) void k_proj_bf16(const T* __restrict__ x, int6
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[mb][nb][q] = 0.0f;
+    // The projection rows are staged through LDS in chunks of kRT steps of t,
+    // shared by the block's four waves (each would otherwise re-read them
+    // from L2 for its own 64 windows); the next chunk is fetched into
+    // registers while the current one feeds the MFMAs.
     const __bf16* Rf = R + (int64_t)f * Cpad * wpad;
-    for (int t0 = 0; t0 < wpad; t0 += 16) {
-        const int tb = t0 + 8 * kk;
-        bf16x8 av[MB], bv[NB];
+    __bf16* rs = reinterpret_cast<__bf16*>(xs + WB + wpad);   // 2 x [MB * 32][kRS]
+    constexpr int PIECES = MB * 32 * (kRT / 8);                // 16-byte pieces per chunk
+    constexpr int ITEMS = (PIECES + 255) / 256;
+    bf16x8 pre[ITEMS];
+    auto fetch = [&](int t0) {
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-            av[mb] = *reinterpret_cast<const bf16x8*>(Rf + (int64_t)(mb * 32 + col) * wpad + tb);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const float* xp = xs + wbase + nb * 32 + col + tb;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) bv[nb][q] = (__bf16)fmaf(xp[q], sc[nb], off[nb]);
+        for (int it = 0; it < ITEMS; ++it) {
+            const int id = threadIdx.x + 256 * it, row = id / (kRT / 8), seg = id % (kRT / 8);
+            if (id < PIECES) pre[it] = *reinterpret_cast<const bf16x8*>(Rf + (int64_t)row * wpad + t0 + 8 * seg);
         }
+    };
+    auto stash = [&](int buf) {
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        for (int it = 0; it < ITEMS; ++it) {
+            const int id = threadIdx.x + 256 * it, row = id / (kRT / 8), seg = id % (kRT / 8);
+            if (id < PIECES) *reinterpret_cast<bf16x8*>(rs + ((size_t)buf * MB * 32 + row) * kRS + 8 * seg) = pre[it];
+        }
+    };
+    const int nchunks = wpad / kRT;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int cur = c & 1;
+        if (c + 1 < nchunks) fetch((c + 1) * kRT);
+        const __bf16* rb = rs + (size_t)cur * MB * 32 * kRS;
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+        for (int st = 0; st < kRT / 16; ++st) {
+            const int tl = st * 16 + 8 * kk, tb = c * kRT + tl;
+            bf16x8 av[MB], bv[NB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                av[mb] = *reinterpret_cast<const bf16x8*>(rb + (size_t)(mb * 32 + col) * kRS + tl);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float* xp = xs + wbase + nb * 32 + col + tb;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) bv[nb][q] = (__bf16)fmaf(xp[q], sc[nb], off[nb]);
+            }
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+        }
+        if (c + 1 < nchunks) stash(cur ^ 1);
+        __syncthreads();
     }
     quantize_store<MB, NB>(acc, U + (int64_t)f * Cpad, a_blk + wbase, col, kk, ns, NF, K, inv_r,
                            H + (int64_t)f * NF * ns);
 }
 
 template <typename T, int MB, int NB>
-__global__ __launch_bounds__(256) void k_proj_fp8(const T* __restrict__ x, int64_t n, int64_t ns,
+__global__ __launch_bounds__(256, 3) void k_proj_fp8(const T* __restrict__ x, int64_t n, int64_t ns,
                                                   int w, int wpad, const double* __restrict__ mu,
                                                   const double* __restrict__ isig,
                                                   const uint8_t* __restrict__ R,
@@ -481,13 +526,42 @@ __global__ __launch_bounds__(256) void k_proj_fp8(const T* __restrict__ x, int64
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[mb][nb][q] = 0.0f;
+    // projection rows staged through LDS as in the bf16 kernel (kRT8 steps of
+    // t per chunk, one byte each)
     const uint8_t* Rf = R + (int64_t)f * Cpad * wpad;
-    for (int t0 = 0; t0 < wpad; t0 += 64) {
-        const int tb = t0 + 32 * kk;
+    uint8_t* rs = reinterpret_cast<uint8_t*>(xs + WB + wpad);   // 2 x [MB * 32][kRS8]
+    constexpr int PIECES = MB * 32 * (kRT8 / 16);               // 16-byte pieces per chunk
+    constexpr int ITEMS = (PIECES + 255) / 256;
+    intx4 pre[ITEMS];
+    auto fetch = [&](int t0) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int id = threadIdx.x + 256 * it, row = id / (kRT8 / 16), seg = id % (kRT8 / 16);
+            if (id < PIECES) pre[it] = *reinterpret_cast<const intx4*>(Rf + (int64_t)row * wpad + t0 + 16 * seg);
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int id = threadIdx.x + 256 * it, row = id / (kRT8 / 16), seg = id % (kRT8 / 16);
+            if (id < PIECES) *reinterpret_cast<intx4*>(rs + ((size_t)buf * MB * 32 + row) * kRS8 + 16 * seg) = pre[it];
+        }
+    };
+    const int nchunks = wpad / kRT8;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int cur = c & 1;
+        if (c + 1 < nchunks) fetch((c + 1) * kRT8);
+        const uint8_t* rb = rs + (size_t)cur * MB * 32 * kRS8;
+#pragma unroll
+        for (int st = 0; st < kRT8 / 64; ++st) {
+        const int tl = st * 64 + 32 * kk, tb = c * kRT8 + tl;
         intx8 av[MB], bv[NB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
-            av[mb] = *reinterpret_cast<const intx8*>(Rf + (int64_t)(mb * 32 + col) * wpad + tb);
+            av[mb] = *reinterpret_cast<const intx8*>(rb + (size_t)(mb * 32 + col) * kRS8 + tl);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const float* xp = xs + wbase + nb * 32 + col + tb;
@@ -506,6 +580,9 @@ __global__ __launch_bounds__(256) void k_proj_fp8(const T* __restrict__ x, int64
             for (int nb = 0; nb < NB; ++nb)
                 acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[mb], bv[nb], acc[mb][nb],
                                                                              0, 0, 0, 127, 0, 127);
+        }
+        if (c + 1 < nchunks) stash(cur ^ 1);
+        __syncthreads();
     }
     quantize_store<MB, NB>(acc, U + (int64_t)f * Cpad, a_blk + wbase, col, kk, ns, NF, K, inv_r,
                            H + (int64_t)f * NF * ns);
@@ -516,16 +593,22 @@ static hipError_t go_lowp(int proj, const T* x, int64_t n, int64_t ns, int D, in
                           const double* mu, const double* isig, const void* R, const float* U,
                           int Cpad, int NF, int K, float inv_r, uint32_t* H, hipStream_t s)
 {
-    constexpr int NB = 2, WB = 4 * 32 * NB;
-    dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-    size_t lds = (size_t)(WB + wpad) * sizeof(float);
+    // windows per wave: 64 for bf16 (two 32-wide MFMA columns share each
+    // projection operand), 32 for fp8, whose Hankel operand costs four times
+    // the VALU work per MFMA (measured; either way two or more waves per SIMD)
     if (proj == 2) {
+        constexpr int NB = 2, WB = 4 * 32 * NB;
+        dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
+        const size_t lds = (size_t)(WB + wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void*)k_proj_bf16<T, MB, NB>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL((k_proj_bf16<T, MB, NB>), grid, dim3(256), lds, s, x, n, ns, w, wpad, mu,
                            isig, (const __bf16*)R, U, Cpad, NF, K, inv_r, H);
     } else {
+        constexpr int NB = 1, WB = 4 * 32 * NB;
+        dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
+        const size_t lds = (size_t)(WB + wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void*)k_proj_fp8<T, MB, NB>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
