@@ -89,8 +89,9 @@ def cpu_baseline(series, p, seed: int, n_cpu: int, r_scale: float) -> dict:
     dt = time.perf_counter() - t0
     ns = n_cpu - p["w"] + 1
     return {"value": ns * p["D"] / dt, "unit": "subseq·dims/s", "cores": 1, "kind": "oracle",
-            "sample": (f"first {n_cpu} points of the same series, same d/k/delta/K/L/seed; the "
-                       f"oracle's complete search (hash + traversal) took {dt:.2f} s, "
+            "sample": (f"first {n_cpu} points of the same series, same d/k/delta/K/L/seed/r; the "
+                       f"oracle's complete search (hash + traversal"
+                       f"{' + exact fallback' if res.get('fallback') else ''}) took {dt:.2f} s, "
                        f"stop ({res['i_stop']},{res['J_stop']}), single-threaded C")}
 
 
@@ -150,7 +151,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rw8_1m")
     ap.add_argument("--proj", default=None, help="projection precision (default: the workload's)")
-    ap.add_argument("--cpu-n", type=int, default=6000)
+    ap.add_argument("--cpu-n", type=int, default=2000,
+                    help="points of the series the CPU oracle is timed on (about 25 s on one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--r-scale", type=float, default=0.0,

@@ -24,6 +24,17 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+// LDS staging of the FP32 projection rows: chunks of kRT32 steps of t, each
+// a row of MB * 32 columns padded by 4 floats; the series tile in front of
+// them is rounded up to 16 bytes.
+constexpr int kRT32 = 16;
+template <typename T, int WB>
+__host__ __device__ inline size_t f32_series_bytes(int wpad)
+{
+    return ((size_t)(WB + wpad) * sizeof(T) + 15) / 16 * 16;
+}
+
+
 // ---------------------------------------------------------------------------
 // Rolling statistics. Each thread owns kStatsChunk consecutive windows: the
 // first by a direct two-pass sum, the rest by the sliding update
@@ -265,7 +276,7 @@ __global__ __launch_bounds__(256) void k_proj_f64(const T* __restrict__ x, int64
 // The normal form is computed in FP64 and rounded once to FP32.
 // ---------------------------------------------------------------------------
 template <typename T, int MB, int NB>
-__global__ __launch_bounds__(256) void k_proj_f32(const T* __restrict__ x, int64_t n, int64_t ns,
+__global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, int64_t n, int64_t ns,
                                                   int w, int wpad, const double* __restrict__ mu,
                                                   const double* __restrict__ isig,
                                                   const float* __restrict__ R,
@@ -300,21 +311,53 @@ __global__ __launch_bounds__(256) void k_proj_f32(const T* __restrict__ x, int64
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[mb][nb][q] = 0.0f;
+    // projection rows staged through LDS in chunks of kRT32 steps of t shared
+    // by the block's waves, the next chunk fetched into registers meanwhile
     const float* Rf = R + (int64_t)f * wpad * Cpad;
+    float* rs = reinterpret_cast<float*>(smem_raw + f32_series_bytes<T, WB>(wpad));   // 2 x [kRT32][MB*32 + 4]
+    constexpr int RW = MB * 32 + 4;                          // padded row (floats)
+    constexpr int PIECES = kRT32 * MB * 32 / 4;              // 16-byte pieces per chunk
+    constexpr int ITEMS = (PIECES + 255) / 256;
+    floatx4 pre[ITEMS];
+    auto fetch = [&](int t0) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int id = threadIdx.x + 256 * it, tr = id / (MB * 8), seg = id % (MB * 8);
+            if (id < PIECES) pre[it] = *reinterpret_cast<const floatx4*>(Rf + (int64_t)(t0 + tr) * Cpad + 4 * seg);
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int id = threadIdx.x + 256 * it, tr = id / (MB * 8), seg = id % (MB * 8);
+            if (id < PIECES) *reinterpret_cast<floatx4*>(rs + ((size_t)buf * kRT32 + tr) * RW + 4 * seg) = pre[it];
+        }
+    };
+    const int nchunks = wpad / kRT32;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int cur = c & 1;
+        if (c + 1 < nchunks) fetch((c + 1) * kRT32);
+        const float* rb = rs + (size_t)cur * kRT32 * RW;
 #pragma unroll 2
-    for (int t0 = 0; t0 < wpad; t0 += 2) {
-        const int t = t0 + kk;
-        float av[MB], bv[NB];
+        for (int tl0 = 0; tl0 < kRT32; tl0 += 2) {
+            const int tl = tl0 + kk, t = c * kRT32 + tl;
+            float av[MB], bv[NB];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) av[mb] = Rf[(int64_t)t * Cpad + mb * 32 + col];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-            bv[nb] = (float)(((double)xs[wbase + nb * 32 + col + t] - m_[nb]) * s_[nb]);
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+            for (int mb = 0; mb < MB; ++mb) av[mb] = rb[(size_t)tl * RW + mb * 32 + col];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+                bv[nb] = (float)(((double)xs[wbase + nb * 32 + col + t] - m_[nb]) * s_[nb]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+        }
+        if (c + 1 < nchunks) stash(cur ^ 1);
+        __syncthreads();
     }
     const int half = K / 2;
 #pragma unroll
@@ -641,7 +684,7 @@ static hipError_t go_f32(const T* x, int64_t n, int64_t ns, int D, int w, int wp
 {
     constexpr int NB = 2, WB = 4 * 32 * NB;
     dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-    size_t lds = (size_t)(WB + wpad) * sizeof(T);
+    size_t lds = f32_series_bytes<T, WB>(wpad) + (size_t)2 * kRT32 * (MB * 32 + 4) * sizeof(float);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_proj_f32<T, MB, NB>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
