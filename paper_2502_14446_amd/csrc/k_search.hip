@@ -560,22 +560,51 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
     unsigned long long ncoll = 0, nmemb = 0, nscr = 0;
     uint32_t maxrun = 0;
     const int64_t wins_per_seg = (g.ns + 63) / 64;
-    const int64_t total_wins = wins_per_seg * g.nseg;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const uint64_t lane_bit = 1ull << lane;
     const uint64_t le_mask = lane_bit | (lane_bit - 1);   // lanes <= this one
     const uint64_t ge_mask = ~(lane_bit - 1);             // lanes >= this one
-    // persistent: each wavefront strides over the 64-element windows of all segments
-    for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < total_wins; win += nwaves) {
-        const int seg = (int)(win / wins_per_seg);
-        const int64_t base = (win - (int64_t)seg * wins_per_seg) * 64;
+    // persistent: each wavefront strides over groups of four consecutive
+    // 64-element windows of all segments; the four windows' keys (and the
+    // two keys beyond each window's edges) are loaded together, neighbours
+    // inside a window come by lane shuffles
+    const int64_t quads_per_seg = (wins_per_seg + 3) / 4;
+    const int64_t total_quads = quads_per_seg * g.nseg;
+    for (int64_t qd = (int64_t)blockIdx.x * 4 + wave; qd < total_quads; qd += nwaves) {
+        const int seg = (int)(qd / quads_per_seg);
+        const int64_t qstart = (qd - (int64_t)seg * quads_per_seg) * 256;
         const int jb = seg / g.Ds, f = seg - jb * g.Ds;
         const int j = g.j0 + jb;
         const KT* ks = keys + (int64_t)seg * g.ns;
         const uint32_t* is = idx + (int64_t)seg * g.ns;
         const uint32_t* fbase = fps + (int64_t)jb * g.ns * nw;
         const uint32_t* qbase = fqs + (int64_t)jb * g.ns * nq;
-
+        {
+            // fast skip: most groups of windows hold no run at the lowest round
+            // of the first round group
+            KT kq[4], kedge[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t t = qstart + 64 * r + lane;
+                kq[r] = t < g.ns ? ks[t] : (KT)0;
+                // lane 0 holds the key before the window, lane 63 the one after it
+                const int64_t te = lane == 0 ? t - 1 : t + 1;
+                kedge[r] = ((lane == 0 || lane == 63) && te >= 0 && te < g.ns) ? ks[te] : (KT)0;
+            }
+            bool any = false;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t t = qstart + 64 * r + lane;
+                const KT kp = lane == 0 ? kedge[r] : (KT)__shfl_up(kq[r], 1, 64);
+                const KT kn = lane == 63 ? kedge[r] : (KT)__shfl_down(kq[r], 1, 64);
+                any |= t < g.ns && ((t > 0 && kp == kq[r]) || (t + 1 < g.ns && kn == kq[r]));
+            }
+            if (!__ballot(any)) continue;
+        }
+#pragma unroll 1
+        for (int r = 0; r < 4; ++r) {
+        const int64_t base = qstart + 64 * r;
+        if (base >= g.ns) break;
         const int64_t t = base + lane;
         const bool valid = t < g.ns;
         const KT k = valid ? ks[t] : (KT)0;
@@ -721,6 +750,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                     }
                 }
             }
+        }
         }
     }
     // pairs, run members and screened pairs: one triple of partial sums per
