@@ -1091,6 +1091,59 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     unsigned long long n_screened = 0;
     uint32_t max_run = 0;
 
+    // Steps [s0, s0 + nsteps) have just been replayed: record the trace, then
+    // test the stopping rule after each step in order. Returns 1 when it
+    // held (out and rep filled), 2 when the pool must grow and the search
+    // restart, 0 to go on, or an error code.
+    auto check_steps = [&](int s0, int nsteps) -> int {
+        if (tracing && p->tr_top_size) {
+            hsnap.resize((size_t)nsteps * k);
+            HIP_OK(copy_sync(p, hsnap.data(), p->snap_tops, hsnap.size() * sizeof(VRec), hipMemcpyDeviceToHost));
+            for (int st = 0; st < nsteps; ++st) {
+                const int64_t sg = s0 + st;
+                if (sg >= p->tr_steps_cap) continue;
+                p->tr_top_size[sg] = p->host_snaps[st].top_n;
+                for (int q = 0; q < p->host_snaps[st].top_n && q < p->tr_k; ++q) {
+                    p->tr_top_pairs[(sg * p->tr_k + q) * 2 + 0] = hsnap[(size_t)st * k + q].a;
+                    p->tr_top_pairs[(sg * p->tr_k + q) * 2 + 1] = hsnap[(size_t)st * k + q].b;
+                }
+            }
+        }
+        for (int st = 0; st < nsteps; ++st) {
+            const Snap& sn = p->host_snaps[st];
+            const int sg = s0 + st;
+            const int i = p->K - sg / p->L;
+            const int J = sg % p->L + 1;
+            ++R.n_steps;
+            if (sn.top_n < k && sn.truncated) {
+                // the pool dropped pairs that TOP may still need: redo with a larger pool
+                ++R.pool_overflow;
+                P *= 2;
+                int e;
+                if ((e = alloc_pool(p, P, k, max_steps))) return e;
+                return 2;
+            }
+            if (sn.top_n == k &&
+                stop_holds(sn.dist_max, p->r, d, i, J, p->K, p->L, p->m, p->o.stop_rule, delta)) {
+                std::vector<VRec> tv(k);
+                HIP_OK(copy_sync(p, tv.data(), p->snap_tops + (size_t)st * k, (size_t)k * sizeof(VRec),
+                                 hipMemcpyDeviceToHost));
+                to_motifs(tv, k, out);
+                *n_out = k;
+                R.i_stop = i;
+                R.j_stop = J;
+                if (verbose)
+                    std::fprintf(stderr, "[momenti] stop (%d, %d): collisions %lld, screened %llu, longest run %u\n",
+                                 i, J, (long long)R.n_collisions, n_screened, max_run);
+                R.peak_bytes = p->peak;
+                R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                if (rep) *rep = R;
+                return 1;
+            }
+        }
+        return 0;
+    };
+
 restart:
     HIP_OK(launch_pool_reset(st_pool(p), p->st));
     R.n_steps = 0;
@@ -1131,6 +1184,9 @@ restart:
             std::fprintf(stderr, "\n");
         }
         uint32_t stored = 0;
+        // a single-round group replays each batch as soon as it is verified,
+        // so that it stops at the first repetition where the rule holds
+        const bool incremental = i_hi == i_lo;
         for (int j0 = 0; j0 < p->L;) {
             const int Bc = std::min(B, p->L - j0);
             StepGeom g;
@@ -1216,52 +1272,23 @@ restart:
                     ++*p->tr_count;
                 }
             }
+            if (incremental) {
+                if ((rc = replay(p, p->store, stored, p->keep, k, s0 + j0, Bc))) return rc;
+                stored = 0;   // the pool holds what the next steps need
+                const int cs = check_steps(s0 + j0, Bc);
+                if (cs < 0) return cs;
+                if (cs == 1) return MOMENTI_OK;
+                if (cs == 2) goto restart;
+            }
             j0 += Bc;
         }
-        // replay the group's verified records in step order through the pool
-        if ((rc = replay(p, p->store, stored, p->keep, k, s0, nsteps))) return rc;
-        if (tracing && p->tr_top_size) {
-            hsnap.resize((size_t)nsteps * k);
-            HIP_OK(copy_sync(p, hsnap.data(), p->snap_tops, hsnap.size() * sizeof(VRec), hipMemcpyDeviceToHost));
-            for (int st = 0; st < nsteps; ++st) {
-                const int64_t s = s0 + st;
-                if (s >= p->tr_steps_cap) continue;
-                p->tr_top_size[s] = p->host_snaps[st].top_n;
-                for (int q = 0; q < p->host_snaps[st].top_n && q < p->tr_k; ++q) {
-                    p->tr_top_pairs[(s * p->tr_k + q) * 2 + 0] = hsnap[(size_t)st * k + q].a;
-                    p->tr_top_pairs[(s * p->tr_k + q) * 2 + 1] = hsnap[(size_t)st * k + q].b;
-                }
-            }
-        }
-        for (int st = 0; st < nsteps; ++st) {
-            const Snap& sn = p->host_snaps[st];
-            const int i = i_hi - st / p->L;
-            const int J = st % p->L + 1;
-            ++R.n_steps;
-            if (sn.top_n < k && sn.truncated) {
-                // the pool dropped pairs that TOP may still need: redo with a larger pool
-                ++R.pool_overflow;
-                P *= 2;
-                if ((rc = alloc_pool(p, P, k, max_steps))) return rc;
-                goto restart;
-            }
-            if (sn.top_n == k &&
-                stop_holds(sn.dist_max, p->r, d, i, J, p->K, p->L, p->m, p->o.stop_rule, delta)) {
-                std::vector<VRec> tv(k);
-                HIP_OK(copy_sync(p, tv.data(), p->snap_tops + (size_t)st * k, (size_t)k * sizeof(VRec),
-                                 hipMemcpyDeviceToHost));
-                to_motifs(tv, k, out);
-                *n_out = k;
-                R.i_stop = i;
-                R.j_stop = J;
-                if (verbose)
-                    std::fprintf(stderr, "[momenti] stop (%d, %d): collisions %lld, screened %llu, longest run %u\n",
-                                 i, J, (long long)R.n_collisions, n_screened, max_run);
-                R.peak_bytes = p->peak;
-                R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                if (rep) *rep = R;
-                return MOMENTI_OK;
-            }
+        // multi-round group: replay its verified records in step order now
+        if (!incremental) {
+            if ((rc = replay(p, p->store, stored, p->keep, k, s0, nsteps))) return rc;
+            const int cs = check_steps(s0, nsteps);
+            if (cs < 0) return cs;
+            if (cs == 1) return MOMENTI_OK;
+            if (cs == 2) goto restart;
         }
     }
     rc = exact_fallback(p, d, k, out, n_out, &R);
