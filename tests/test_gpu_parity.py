@@ -329,6 +329,84 @@ def test_end_to_end_close_motif_stops_like_the_oracle(orc):
     plan.close()
 
 
+@pytest.mark.parametrize("D,n,w,d,k,K,L", [
+    (1, 700, 20, 1, 2, 8, 30),     # one dimension
+    (3, 800, 24, 3, 2, 8, 20),     # d = D
+    (3, 700, 24, 2, 2, 2, 6),      # K = 2: rounds 2 and 1 only
+    (4, 900, 30, 2, 1, 6, 1),      # a single repetition
+    (2, 21, 20, 1, 1, 8, 10),      # n = w + 1: two windows, one trivial pair, nothing to find
+])
+def test_degenerate_shapes_match_oracle(orc, D, n, w, d, k, K, L):
+    s = synth.make_series(70 + D + n, D, n, w, 1 if n >= 10 * w else 0, d, dtype="f64")
+    p = dict(w=w, mem_limit=1 << 30)
+    seed = 0x77
+    plan, _ = _plan(s, p, "f64", seed, K=K, L=L)
+    got, rep, rc = plan.search(d, k, 0.1)
+    ref = orc.lsh_pipeline(s.x, w, d, k, 0.1, seed, K=K, L_max=L, mem_limit=1 << 30)
+    assert rc == (mm.OK_FALLBACK if ref["fallback"] else mm.OK)
+    assert (rep["i_stop"], rep["j_stop"]) == (ref["i_stop"], ref["J_stop"])
+    assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ref["motifs"]]
+    for g, o in zip(got, ref["motifs"]):
+        assert g["dist_d"] == pytest.approx(o["dist_d"], rel=1e-9)
+        assert g["dims"] == o["dims"]
+    plan.close()
+
+
+def test_full_size_bench_workload_sampled(orc):
+    # the benchmark's own workload and launch configuration (rw8_1m: D=8,
+    # n=1e6, w=300, FP32 projection, 8 GB cap), checked where the oracle can
+    # evaluate outputs one by one
+    s, p = synth.workload("rw8_1m")
+    seed = synth.LSH_SEED["rw8_1m"]
+    w, D = p["w"], s.D
+    plan, _ = _plan(s, p, "f32", seed, profile=True)
+    prm = plan.params()
+    x = s.x.astype(np.float64)
+    assert prm["L"] == orc.L_used(s.n, D, w, 200, 4, p["mem_limit"])
+    assert prm["r"] == orc.estimate_r(x, w, seed)
+    ns = s.n - w + 1
+    rng = np.random.default_rng(2024)
+    fs = rng.integers(0, D, 256)
+    aa = np.concatenate([rng.integers(0, ns, 250), [0, 1, ns - 2, ns - 1, ns // 2, 4095]])
+    # window statistics (sliding FP64 updates over 1e6 windows: 1e-11 of the scale)
+    mu, isg = plan.stats()
+    for f, a in zip(fs, aa):
+        m, sg, flat = orc.window_stats(x[f, a:a + w])
+        assert abs(mu[f, a] - m) <= 1e-11 * (abs(m) + sg)
+        assert not flat and abs(isg[f, a] * sg - 1.0) <= 1e-10
+    # hash symbols, within the FP32 band of the oracle's exact pre-floor value
+    words = plan.hashes()
+    R, U = orc.draw_projections(seed, D, w, 4 * prm["NF"])
+    C = 4 * prm["NF"]
+    gsym = np.zeros((1, len(aa), C), dtype=np.uint8)
+    osym = np.zeros((1, len(aa), C), dtype=np.uint8)
+    pre = np.zeros((1, len(aa), C)); sab = np.zeros((1, len(aa), C))
+    for q, (f, a) in enumerate(zip(fs, aa)):
+        by, pr, sb = orc.hash_one(x[f], w, int(a), R[f], U[f], prm["r"])
+        osym[0, q], pre[0, q], sab[0, q] = by, pr, sb
+        for c in range(C):
+            wd = int(words[f, c // 4, a])
+            gsym[0, q, c] = (wd >> (24 - 8 * (c % 4))) & 0xFF
+    bad_out, bad_in, near, diff = _check_symbols(gsym, osym, pre, _band("f32", w, pre, sab, prm["r"]), 8)
+    assert bad_out == 0 and bad_in == 0
+    # the search: every reported distance recomputed by the oracle, the picks
+    # in (dist_d, a, b) order, non-trivial and pairwise non-overlapping
+    got, rep, rc = plan.search(p["d"], p["k"], p["delta"])
+    assert rc == mm.OK and len(got) == p["k"] and rep["i_stop"] >= 1
+    for g in got:
+        dd, dm, dims, per = orc.distd(x, w, g["a"], g["b"], p["d"])
+        assert g["dist_d"] == pytest.approx(dd, rel=1e-9) and g["dist_max"] == pytest.approx(dm, rel=1e-9)
+        assert g["dims"] == dims and 2 * (g["b"] - g["a"]) > w
+    keys = [(g["dist_d"], g["a"], g["b"]) for g in got]
+    assert keys == sorted(keys)
+    for q, g in enumerate(got):
+        for h in got[:q]:
+            for u in (g["a"], g["b"]):
+                for v in (h["a"], h["b"]):
+                    assert 2 * abs(u - v) > w
+    plan.close()
+
+
 def test_fallback_returns_exact_top_k(orc):
     # LEMMA52 with a vanishing delta never stops: the exact answer is returned
     s = synth.make_series(41, 3, 700, 24, 2, 2, dtype="f64")
