@@ -91,6 +91,9 @@ typedef struct {
     int32_t pool_size;        /* verified pairs kept on the device; 0 = max(4096, 64 k) */
     int32_t batch_reps;       /* repetitions traversed per launch; 0 = chosen from mem_limit */
     int32_t profile;          /* 1: time every kernel launch with HIP events (momenti_get_profile) */
+    double merge_pairs;       /* rounds join the first round group (one sort) while their colliding
+                                 pairs are estimated at most this many per segment element;
+                                 <= 0 means 8 (about the cost of one sort pass) */
     double max_pairs;         /* work budget: a round group whose colliding pairs are estimated
                                  (from one probed repetition) above this is not traversed and
                                  the search returns MOMENTI_OK_PARTIAL; <= 0: no budget */

@@ -92,7 +92,13 @@ struct StepGeom {
     int Ds;              // dimensions that get segments: seg = rep * Ds + f, f < Ds
     int i, K;            // highest round of the group; K
     int i_lo;            // lowest round of the group: segments are sorted by this prefix length
+    int hashed;          // 1: sorted by a 24-bit hash of that prefix instead (equal prefixes
+                         // stay adjacent; the rare equal hashes of different prefixes only
+                         // add members to a run, and the exact test rejects them)
 };
+// Sort keys of a segment element: the length-i_lo prefix, or its 24-bit hash.
+inline bool sort_keys_32(const StepGeom& g) { return g.hashed || g.i_lo <= 4; }
+inline int sort_passes(const StepGeom& g) { return g.hashed ? 3 : g.i_lo; }
 // 32-bit words of a window's fingerprint row: one byte per dimension, padded
 // with zero bytes to 1, 2, 4, 8 or a multiple of 8 words
 __host__ __device__ inline int fp_words(int D)

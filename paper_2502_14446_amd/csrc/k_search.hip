@@ -107,6 +107,15 @@ __device__ inline KT make_key(uint32_t L, uint32_t R, int i)
     return (KT)(full >> (8 * (8 - i)));
 }
 
+// Sort key of a segment element: the prefix itself, or (g.hashed) the top 24
+// bits of its multiplicative (Fibonacci) hash
+template <typename KT>
+__device__ inline KT sort_key(uint32_t L, uint32_t R, const StepGeom& g)
+{
+    if (g.hashed) return (KT)((make_key<uint64_t>(L, R, g.i_lo) * 0x9E3779B97F4A7C15ull) >> 40);
+    return make_key<KT>(L, R, g.i_lo);
+}
+
 __device__ inline uint32_t top_mask(int nbytes)
 {
     return nbytes <= 0 ? 0u : (nbytes >= 4 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (32 - 8 * nbytes)));
@@ -149,7 +158,7 @@ __global__ __launch_bounds__(256) void k_hist(const KT* __restrict__ kin, const 
     if (FIRST) sp = seg_words(H, g, seg);
     const KT* ks = kin + (int64_t)seg * g.ns;
     for (int64_t e = base + threadIdx.x; e < end; e += 256) {
-        KT key = FIRST ? make_key<KT>(sp.Lw[e], sp.Rw[e], g.i_lo) : ks[e];
+        KT key = FIRST ? sort_key<KT>(sp.Lw[e], sp.Rw[e], g) : ks[e];
         atomicAdd(&cnt[(uint32_t)(key >> (8 * pass)) & 255u], 1u);
     }
     __syncthreads();
@@ -238,7 +247,7 @@ __global__ __launch_bounds__(256) void k_scatter(const KT* __restrict__ kin, con
         if (valid) {
             const int64_t ge = base + e;
             if (FIRST) {
-                key = make_key<KT>(sp.Lw[ge], sp.Rw[ge], g.i_lo);
+                key = sort_key<KT>(sp.Lw[ge], sp.Rw[ge], g);
                 id = (uint32_t)ge;
             } else {
                 key = ks[ge];
@@ -302,7 +311,7 @@ hipError_t launch_hist(const StepGeom& g, const uint32_t* H, const SortBufs& b, 
                        hipStream_t s)
 {
     dim3 grid((unsigned)b.tiles, (unsigned)g.nseg);
-    if (g.i_lo <= 4) {
+    if (sort_keys_32(g)) {
         const uint32_t* kin = (const uint32_t*)b.keys[cur];
         if (pass == 0)
             hipLaunchKernelGGL((k_hist<uint32_t, true>), grid, dim3(256), 0, s, kin, H, g, pass, b.tiles, b.hist);
@@ -328,7 +337,7 @@ hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& 
                           hipStream_t s)
 {
     dim3 grid((unsigned)b.tiles, (unsigned)g.nseg);
-    if (g.i_lo <= 4) {
+    if (sort_keys_32(g)) {
         const uint32_t* kin = (const uint32_t*)b.keys[cur];
         uint32_t* kout = (uint32_t*)b.keys[cur ^ 1];
         if (pass == 0)
@@ -507,6 +516,7 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
         if (fp == f) cpf = cp;
     }
     if ((int)(atl & 0xFF) < d) return;   // the digests agreed by chance
+    if (cpf < g.i_lo) return;            // equal sort-key hashes, different prefixes
     const int top = cpf < g.i ? cpf : g.i;
     for (int lv = nlev - 2; lv >= 0; --lv) {
         const int i = g.i_lo + lv;
@@ -872,7 +882,7 @@ hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint
                        uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
     if (g.i - g.i_lo + 2 > kMaxLev) return hipErrorInvalidValue;
-    if (g.i_lo <= 4)
+    if (sort_keys_32(g))
         return go_enum_nw<uint32_t>(g, (const uint32_t*)b.keys[buf], b.idx[buf], H, fps, fq, kt, d, w, cand,
                                     cap, cnt, part, s);
     return go_enum_nw<uint64_t>(g, (const uint64_t*)b.keys[buf], b.idx[buf], H, fps, fq, kt, d, w, cand, cap,
@@ -953,7 +963,7 @@ hipError_t launch_probe(const StepGeom& g, const SortBufs& b, int buf, unsigned 
 {
     if (g.i_lo < 1 || g.i_lo > 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero64, dim3(1), dim3(64), 0, s, out, 8);
-    if (g.i_lo <= 4)
+    if (sort_keys_32(g))
         hipLaunchKernelGGL(k_probe_levels<uint32_t>, dim3(512), dim3(256), 0, s, (const uint32_t*)b.keys[buf],
                            g.ns, g.nseg, g.i_lo, out);
     else

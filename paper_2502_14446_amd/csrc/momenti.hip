@@ -484,6 +484,7 @@ void momenti_default_opts(momenti_opts* o)
     o->r = 0.0;
     o->r_scale = 1.0;
     o->max_pairs = 0.0;
+    o->merge_pairs = 8.0;
     o->proj = MOMENTI_PROJ_F32;
     o->stop_rule = MOMENTI_STOP_TENSOR;
 }
@@ -536,8 +537,9 @@ static int prepare_impl(momenti_plan** out, int64_t n, int32_t D, int32_t w, int
     if (o.stop_rule != MOMENTI_STOP_TENSOR && o.stop_rule != MOMENTI_STOP_LEMMA52 &&
         o.stop_rule != MOMENTI_STOP_TENSOR_LITERAL)
         return fail(MOMENTI_E_ARG, "bad stop rule %d", o.stop_rule);
-    if (!std::isfinite(o.r_scale) || !std::isfinite(o.max_pairs) || !std::isfinite(o.r))
-        return fail(MOMENTI_E_ARG, "r, r_scale and max_pairs must be finite");
+    if (!std::isfinite(o.r_scale) || !std::isfinite(o.max_pairs) || !std::isfinite(o.r) ||
+        !std::isfinite(o.merge_pairs))
+        return fail(MOMENTI_E_ARG, "r, r_scale, merge_pairs and max_pairs must be finite");
     if (o.pool_size < 0 || o.batch_reps < 0) return fail(MOMENTI_E_ARG, "negative pool/batch size");
 
     const int elem = dtype == MOMENTI_F64 ? 8 : 4;
@@ -1050,7 +1052,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         const int Dp = std::min(Ds, 8);
         StepGeom g;
         g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
-        g.j0 = 0; g.Ds = Ds; g.nseg = Dp; g.i = p->K; g.K = p->K; g.i_lo = p->K;
+        g.j0 = 0; g.Ds = Ds; g.nseg = Dp; g.i = p->K; g.K = p->K; g.i_lo = p->K; g.hashed = 0;
         int buf = 0;
         const double elems = (double)Dp * p->ns, kb = p->K <= 4 ? 4.0 : 8.0;
         for (int pass = 0; pass < p->K; ++pass) {
@@ -1069,7 +1071,8 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         const unsigned long long* hc = (const unsigned long long*)(p->host_status + 2048);
         for (int i = 1; i <= p->K; ++i) pairs_est[i] = (double)hc[i - 1] * ((double)Ds / Dp) * p->L;
     }
-    const auto groups = round_groups(p->K, pairs_est, 8.0 * (double)p->ns * Ds * p->L);
+    const double per_elem = p->o.merge_pairs > 0.0 ? p->o.merge_pairs : 8.0;
+    const auto groups = round_groups(p->K, pairs_est, per_elem * (double)p->ns * Ds * p->L);
     R.first_group_lo = groups[0].second;
     static const int verbose = [] {
         const char* v = std::getenv("MOMENTI_VERBOSE");
@@ -1192,11 +1195,12 @@ restart:
             StepGeom g;
             g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
             g.j0 = j0; g.Ds = Ds; g.nseg = Bc * Ds; g.i = i_hi; g.K = p->K; g.i_lo = i_lo;
+            g.hashed = i_lo > 4;   // longer prefixes are grouped by a 24-bit hash (3 passes)
             HIP_OK(launch_zero(p->status, 64, p->st));
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
-            const double kb = i_lo <= 4 ? 4.0 : 8.0;
-            for (int pass = 0; pass < i_lo; ++pass) {
+            const double kb = sort_keys_32(g) ? 4.0 : 8.0;
+            for (int pass = 0; pass < sort_passes(g); ++pass) {
                 const double kin = pass == 0 ? 8.0 : kb;   // pass 0 reads two index words
                 HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
                 HIP_OK(timed(p, KI_SCAN, 8.0 * g.nseg * 256.0 * p->sb.tiles, 0.0, [&] { return launch_scan(g, p->sb, p->st); }));

@@ -35,7 +35,7 @@ class Opts(C.Structure):
                 ("r_scale", C.c_double),
                 ("proj", C.c_int32), ("stop_rule", C.c_int32), ("series_on_device", C.c_int32),
                 ("pool_size", C.c_int32), ("batch_reps", C.c_int32), ("profile", C.c_int32),
-                ("max_pairs", C.c_double), ("stream", C.c_void_p)]
+                ("merge_pairs", C.c_double), ("max_pairs", C.c_double), ("stream", C.c_void_p)]
 
 
 class Job(C.Structure):
@@ -116,10 +116,11 @@ def _check(rc: int) -> int:
 def make_opts(seed: int = 0x5EED, K: int = 8, L: int = 200, r: float = 0.0, proj: str = "f32",
               stop: str = "tensor", series_on_device: bool = False, pool_size: int = 0,
               batch_reps: int = 0, profile: bool = False, stream: Optional[int] = None,
-              r_scale: float = 1.0, max_pairs: float = 0.0) -> Opts:
+              r_scale: float = 1.0, max_pairs: float = 0.0, merge_pairs: float = 0.0) -> Opts:
     o = Opts()
     lib().momenti_default_opts(C.byref(o))
     o.seed, o.K, o.L, o.r, o.r_scale, o.max_pairs = seed, K, L, r, r_scale, max_pairs
+    o.merge_pairs = merge_pairs
     o.proj, o.stop_rule = PROJ[proj], STOP[stop]
     o.series_on_device = 1 if series_on_device else 0
     o.pool_size, o.batch_reps = pool_size, batch_reps

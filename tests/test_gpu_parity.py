@@ -227,13 +227,13 @@ def _oracle_sets(cand):
     return sets
 
 
-def _check_traversal(orc, s, p, seed, K, L, k, d, delta, rule):
-    plan, _ = _plan(s, p, "f64", seed, K=K, L=L, stop=rule, batch_reps=4)
+def _check_traversal(orc, s, p, seed, K, L, k, d, delta, rule, **kw):
+    plan, _ = _plan(s, p, "f64", seed, K=K, L=L, stop=rule, batch_reps=4, **kw)
     prm = plan.params()
     Lu = prm["L"]
     R, U = orc.draw_projections(seed, s.D, p["w"], 4 * prm["NF"])
     r = prm["r"]
-    assert r == orc.estimate_r(s.x, p["w"], seed)
+    assert r == orc.estimate_r(s.x, p["w"], seed) * kw.get("r_scale", 1.0)
     ref_sym, _, _ = _oracle_symbols(orc, s.x, p["w"], R, U, r)
     words = orc.pack(ref_sym, prm["NF"], K)
     plan.set_hashes(words)                       # traverse the oracle's own index
@@ -281,6 +281,17 @@ def test_traversal_matches_oracle_deep_rounds(orc):
     s = synth.make_series(31, 3, 1500, 30, 2, 2, dtype="f64")
     p = dict(w=30, mem_limit=1 << 30)
     _check_traversal(orc, s, p, 8, 4, 9, 2, 2, 1e-3, "lemma52")
+
+
+def test_traversal_matches_oracle_hashed_sort_keys(orc):
+    # every round in a group of its own: rounds 8..5 sort their segments by
+    # a 24-bit hash of the prefix (wide r: many equal short prefixes, so the
+    # hashed runs are long); every step must still match the oracle
+    s = synth.make_series(81, 4, 1800, 40, 2, 2, dtype="f64")
+    p = dict(w=40, mem_limit=1 << 30)
+    rep, ref = _check_traversal(orc, s, p, 21, 8, 12, 2, 2, 1e-8, "lemma52", r_scale=15.0,
+                                merge_pairs=1e-12)
+    assert rep["first_group_lo"] == 8 and ref["i_stop"] <= 2
 
 
 def test_traversal_matches_oracle_wide_rows_stop(orc):
