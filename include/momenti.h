@@ -137,7 +137,8 @@ typedef struct {
     int32_t batch_reps;       /* repetitions per launch actually used */
     int32_t first_group_lo;   /* rounds K .. first_group_lo were traversed from one sort */
     int32_t budget_round;     /* MOMENTI_OK_PARTIAL: the highest round not traversed; else 0 */
-    int32_t reserved;
+    int32_t max_run;          /* most windows sharing a prefix in one segment, among the runs
+                                 that crossed a 64-window boundary (enumerated in tiles) */
 } momenti_report;
 
 /* Fill *o with the defaults (K = 8, L = 200, r estimated, F32 projection,

@@ -1261,6 +1261,7 @@ restart:
             R.n_collisions += (int64_t)cnt.n_coll;
             n_screened += cnt.n_screen;
             max_run = std::max(max_run, cnt.max_run);
+            R.max_run = (int32_t)max_run;
             R.n_cand += cnt.n_cand;
             R.n_verified += cnt.n_cand;
             if (tracing && p->tr_cand && cnt.n_cand) {

@@ -60,7 +60,7 @@ class Report(C.Structure):
                 ("n_collisions", C.c_int64), ("n_cand", C.c_int64), ("n_verified", C.c_int64),
                 ("peak_bytes", C.c_uint64), ("fallback", C.c_int32), ("pool_overflow", C.c_int32),
                 ("batch_reps", C.c_int32), ("first_group_lo", C.c_int32),
-                ("budget_round", C.c_int32), ("reserved", C.c_int32)]
+                ("budget_round", C.c_int32), ("max_run", C.c_int32)]
 
 
 class MomentiError(RuntimeError):
@@ -139,7 +139,7 @@ def _motifs(arr, count: int) -> List[Dict]:
 
 
 def _report(r: Report) -> Dict:
-    return {name: getattr(r, name) for name, _ in Report._fields_ if name != "reserved"}
+    return {name: getattr(r, name) for name, _ in Report._fields_}
 
 
 def _torch_stream_handle() -> Optional[int]:

@@ -311,6 +311,16 @@ def test_traversal_matches_oracle_wide_rows_all_rounds(orc):
     assert ref["i_stop"] == 0
 
 
+def test_traversal_matches_oracle_long_runs_many_dims(orc):
+    # D = 32, d = 8: a wide r makes the round-1 runs cross several 64-window
+    # boundaries, so they are enumerated tile by tile from LDS; no step
+    # stops, so every round is compared
+    s = synth.make_series(53, 32, 1500, 30, 2, 8, dtype="f64")
+    p = dict(w=30, mem_limit=1 << 30)
+    rep, ref = _check_traversal(orc, s, p, 9, 8, 12, 2, 8, 1e-4, "lemma52", r_scale=8.0)
+    assert ref["i_stop"] == 0 and rep["max_run"] > 64
+
+
 # --------------------------------------------------------------------------- end to end
 def test_end_to_end_tiny_matches_oracle_and_exact(orc):
     s, p = synth.workload("tiny")
