@@ -460,6 +460,9 @@ __device__ inline int nonzero_bytes_28(uint32_t x)
 
 constexpr int kFpRegs = 8;   // fingerprint words kept in registers (32 dimensions)
 
+// Words between consecutive fingerprint rows in LDS: nw rounded up to odd.
+__host__ __device__ inline int lds_row_words(int nw) { return nw | 1; }
+
 // Sum over the nw words of nonzero_bytes_28(own ^ partner): the lane's own
 // row (its first NW words in registers, the rest at own_tail, only when TAIL)
 // against the partner's (pw). With D dimensions the rows have 4 nw - D
@@ -561,10 +564,13 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
     const int nw = TAIL ? fp_words(g.D) : NW;   // NW = min(nw, kFpRegs); TAIL iff nw > NW
     const int nq = fq_words(g.D);
     const int zmax = 28 * nw + g.D - d;
-    uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * (3 * nw + 2);
-    uint32_t* fpA = mine;                        // 2 TS rows: tile P twice
-    uint32_t* fpB = fpA + (size_t)2 * TS * nw;   // TS rows: tile Q
-    uint32_t* idA = fpB + (size_t)TS * nw;
+    // LDS rows of fingerprint words at an odd stride, so that lanes reading
+    // consecutive rows hit distinct banks
+    const int ldw = lds_row_words(nw);
+    uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * (3 * ldw + 2);
+    uint32_t* fpA = mine;                         // 2 TS rows: tile P twice
+    uint32_t* fpB = fpA + (size_t)2 * TS * ldw;   // TS rows: tile Q
+    uint32_t* idA = fpB + (size_t)TS * ldw;
     uint32_t* idB = idA + TS;
 
     unsigned long long ncoll = 0, nmemb = 0, nscr = 0;
@@ -696,8 +702,8 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                 idA[r] = a;
                 for (int wd = 0; wd < nw; ++wd) {
                     const uint32_t v = fbase[(int64_t)a * nw + wd];
-                    fpA[(size_t)r * nw + wd] = v;
-                    fpA[(size_t)(r + nA) * nw + wd] = v;
+                    fpA[(size_t)r * ldw + wd] = v;
+                    fpA[(size_t)(r + nA) * ldw + wd] = v;
                 }
             }
             for (int tq = tp; tq < T; ++tq) {
@@ -708,18 +714,18 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                     for (int r = lane; r < nB; r += 64) {
                         const uint32_t b = is[start + tq * TS + r];
                         idB[r] = b;
-                        for (int wd = 0; wd < nw; ++wd) fpB[(size_t)r * nw + wd] = fbase[(int64_t)b * nw + wd];
+                        for (int wd = 0; wd < nw; ++wd) fpB[(size_t)r * ldw + wd] = fbase[(int64_t)b * nw + wd];
                     }
                 }
                 wave_sync_lds();
                 for (int u = lane; u < nA; u += 64) {
-                    const uint32_t* ofw = fpA + (size_t)u * nw;
+                    const uint32_t* ofw = fpA + (size_t)u * ldw;
                     uint32_t ofp[NW];
 #pragma unroll
                     for (int wd = 0; wd < NW; ++wd) ofp[wd] = ofw[wd];
                     // partners: u + 1 + v in P (v < nA / 2, the last one only for
                     // u < nA / 2 when nA is even), or every member v of Q
-                    const uint32_t* P0 = same ? fpA + (size_t)(u + 1) * nw : fpB;
+                    const uint32_t* P0 = same ? fpA + (size_t)(u + 1) * ldw : fpB;
                     const int nv = same ? ((nA & 1) == 0 && u >= nA / 2 ? nA / 2 - 1 : nA / 2) : nB;
                     auto check = [&](int v) {
                         int qq = same ? u + 1 + v : v;
@@ -734,16 +740,16 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                     int v = 0;
                     // four partners per step, their LDS reads issued together
                     for (; v + 4 <= nv; v += 4) {
-                        const uint32_t* p = P0 + (size_t)v * nw;
+                        const uint32_t* p = P0 + (size_t)v * ldw;
                         uint32_t pw[4][NW];
 #pragma unroll
                         for (int c = 0; c < 4; ++c)
 #pragma unroll
-                            for (int wd = 0; wd < NW; ++wd) pw[c][wd] = p[c * nw + wd];
+                            for (int wd = 0; wd < NW; ++wd) pw[c][wd] = p[c * ldw + wd];
                         uint32_t hit = 0;
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
-                            const uint32_t* pc = p + c * nw;
+                            const uint32_t* pc = p + c * ldw;
                             const int z = screen<NW, TAIL>(
                                 ofp, ofw, [&](int wd) { return wd < NW ? pw[c][wd < NW ? wd : 0] : pc[wd]; }, nw);
                             hit |= (uint32_t)(z <= zmax) << c;
@@ -755,7 +761,7 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                         }
                     }
                     for (; v < nv; ++v) {
-                        const uint32_t* p = P0 + (size_t)v * nw;
+                        const uint32_t* p = P0 + (size_t)v * ldw;
                         if (screen<NW, TAIL>(ofp, ofw, [&](int wd) { return p[wd]; }, nw) <= zmax) check(v);
                     }
                 }
@@ -810,10 +816,10 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const unsigned long long*
 }
 
 // Members per tile: a wave's region (tile P twice, tile Q, indices) stays
-// within ~12 KB, so that several work-groups stay resident per CU.
+// within 13 KB, so that three work-groups (52 KB each) fit a CU's LDS.
 static int tile_size(int D)
 {
-    int ts = 12288 / (4 * (3 * fp_words(D) + 2));
+    int ts = 13312 / (4 * (3 * lds_row_words(fp_words(D)) + 2));
     ts = ts > 64 ? 64 : ts;
     return ts < 16 ? 16 : (ts / 16) * 16;
 }
@@ -853,7 +859,7 @@ static hipError_t go_enum(const StepGeom& g, const KT* keys, const uint32_t* idx
                           uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
     const int TS = tile_size(g.D);
-    const size_t lds = (size_t)4 * TS * (3 * fp_words(g.D) + 2) * 4;   // 4 waves
+    const size_t lds = (size_t)4 * TS * (3 * lds_row_words(fp_words(g.D)) + 2) * 4;   // 4 waves
     const void* fn = (const void*)k_enum_runs<KT, NW, TAIL>;
     if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int nb = resident_blocks(fn, lds);

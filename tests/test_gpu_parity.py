@@ -321,6 +321,16 @@ def test_traversal_matches_oracle_long_runs_many_dims(orc):
     assert ref["i_stop"] == 0 and rep["max_run"] > 64
 
 
+def test_traversal_matches_oracle_rows_beyond_registers(orc):
+    # D = 40: 16 fingerprint words per row, more than a lane keeps in
+    # registers, so the rest of its own row is read back from LDS in long
+    # runs and from memory in short ones; the round-1 runs span several tiles
+    s = synth.make_series(54, 40, 1200, 30, 2, 10, dtype="f64")
+    p = dict(w=30, mem_limit=1 << 30)
+    rep, ref = _check_traversal(orc, s, p, 9, 8, 12, 2, 10, 1e-4, "lemma52", r_scale=8.0)
+    assert ref["i_stop"] == 0 and rep["max_run"] > 64
+
+
 # --------------------------------------------------------------------------- end to end
 def test_end_to_end_tiny_matches_oracle_and_exact(orc):
     s, p = synth.workload("tiny")
