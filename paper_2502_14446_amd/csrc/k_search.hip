@@ -549,7 +549,7 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
 //    same partner of Q at once: an LDS broadcast).
 // Pairs that pass the screen and are not trivial matches go to judge_pair.
 template <typename KT, int NW, bool TAIL>
-__global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
+__global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
                                                    const uint32_t* __restrict__ H,
                                                    const uint32_t* __restrict__ fps,
@@ -738,22 +738,33 @@ __global__ __launch_bounds__(256) void k_enum_runs(const KT* __restrict__ keys,
                         judge_pair(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     };
                     int v = 0;
-                    // four partners per step, their LDS reads issued together
-                    for (; v + 4 <= nv; v += 4) {
+                    // UP partners per step, their LDS reads issued together
+                    // (two for rows of 8 words and more, to stay within 128 VGPRs)
+                    constexpr int UP = NW >= 8 ? 2 : 4;
+                    for (; v + UP <= nv; v += UP) {
                         const uint32_t* p = P0 + (size_t)v * ldw;
-                        uint32_t pw[4][NW];
+                        uint32_t pw[UP][NW];
 #pragma unroll
-                        for (int c = 0; c < 4; ++c)
+                        for (int c = 0; c < UP; ++c)
 #pragma unroll
                             for (int wd = 0; wd < NW; ++wd) pw[c][wd] = p[c * ldw + wd];
+                        int z[UP];
+#pragma unroll
+                        for (int c = 0; c < UP; ++c) {
+                            z[c] = 0;
+#pragma unroll
+                            for (int wd = 0; wd < NW; ++wd) z[c] += nonzero_bytes_28(ofp[wd] ^ pw[c][wd]);
+                        }
+                        if (TAIL)
+                            // the rest of the lane's own row is read once for the UP partners
+                            for (int wd = NW; wd < nw; ++wd) {
+                                const uint32_t o = ofw[wd];
+#pragma unroll
+                                for (int c = 0; c < UP; ++c) z[c] += nonzero_bytes_28(o ^ p[c * ldw + wd]);
+                            }
                         uint32_t hit = 0;
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            const uint32_t* pc = p + c * ldw;
-                            const int z = screen<NW, TAIL>(
-                                ofp, ofw, [&](int wd) { return wd < NW ? pw[c][wd < NW ? wd : 0] : pc[wd]; }, nw);
-                            hit |= (uint32_t)(z <= zmax) << c;
-                        }
+                        for (int c = 0; c < UP; ++c) hit |= (uint32_t)(z[c] <= zmax) << c;
                         while (hit) {
                             const int bit = __ffs(hit) - 1;
                             hit &= hit - 1;
