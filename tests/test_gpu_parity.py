@@ -331,6 +331,32 @@ def test_traversal_matches_oracle_rows_beyond_registers(orc):
     assert ref["i_stop"] == 0 and rep["max_run"] > 64
 
 
+def test_example_4_1_on_device(orc):
+    # the paper's worked example (section 4, Example 4.1) with its index
+    # injected: the device stops at the same step with the same TOP; below
+    # round K it emits only pairs not already seen one symbol deeper, so
+    # the rounds-3 steps emit nothing new
+    from example_4_1 import example_4_1_scenario
+    fx, s, words, r, pairs, top = example_4_1_scenario(orc)
+    prm, ex = fx["parameters"], fx["expected"]
+    K, L = prm["K"], prm["L"]
+    p = dict(w=40, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, "f64", 0xE41, K=K, L=L, r=r, stop="lemma52")
+    assert plan.params()["r"] == r and plan.params()["L"] == L
+    plan.set_hashes(words)
+    plan.set_trace(200_000, prm["k"])   # steps past the stop may be traversed in the same group
+    got, rep, rc = plan.search(prm["d"], prm["k"], prm["delta"])
+    tr = plan.trace()
+    plan.close()
+    assert rc == mm.OK and [rep["i_stop"], rep["j_stop"]] == ex["stops_at"]
+    assert [(g["a"], g["b"]) for g in got] == [pairs[top]]
+    gsets = _oracle_sets(tr["cand"])
+    assert gsets.get(0, set()) == set(pairs) and gsets.get(1, set()) == set(pairs)
+    assert not gsets.get(2) and not gsets.get(3)
+    for step in range(4):
+        assert tr["top_size"][step] == 1 and tuple(tr["top_pairs"][step, 0]) == pairs[top]
+
+
 # --------------------------------------------------------------------------- end to end
 def test_end_to_end_tiny_matches_oracle_and_exact(orc):
     s, p = synth.workload("tiny")

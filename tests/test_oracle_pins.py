@@ -369,3 +369,28 @@ def test_lsh_recall_is_at_least_one_minus_delta(orc):
         hits += (res["motifs"][0]["a"], res["motifs"][0]["b"]) == (ex[0]["a"], ex[0]["b"])
     # failure count is at most Binomial(runs, delta); allow 3 standard deviations
     assert runs - hits <= runs * delta + 3 * math.sqrt(runs * delta * (1 - delta))
+
+
+# ----------------------------------------------------------------------------- Example 4.1
+from example_4_1 import example_4_1_scenario  # noqa: E402
+
+
+def test_example_4_1_control_flow(orc):
+    fx, s, words, r, pairs, top = example_4_1_scenario(orc)
+    prm, ex = fx["parameters"], fx["expected"]
+    K, L = prm["K"], prm["L"]
+    res = orc.lsh_search(s.x, 40, prm["d"], prm["k"], prm["delta"], words, K, L, r,
+                         rule=orc.STOP_LEMMA52, trace=True)
+    assert [res["i_stop"], res["J_stop"]] == ex["stops_at"]
+    assert [(m["a"], m["b"]) for m in res["motifs"]] == [pairs[top]]
+    p = orc.collision_prob(res["motifs"][0]["dist_max"], r) ** prm["d"]
+    for i, J in ex["rule_does_not_hold_at"]:
+        assert orc.fail_bound(p, i, J, K, L, orc.STOP_LEMMA52) > prm["delta"]
+    # every traversed step sees both motifs (weight 2) and keeps the closer one
+    last = (K - res["i_stop"]) * L + res["J_stop"] - 1
+    cand = res["cand"]
+    for step in range(last + 1):
+        got = {(int(x), int(y)) for _, x, y in cand[cand[:, 0] == step]}
+        assert got == set(pairs), step
+        assert res["top_size"][step] == 1
+        assert tuple(res["top_pairs"][step, 0]) == pairs[top]
