@@ -360,7 +360,7 @@ def test_lsh_search_stops_on_a_close_planted_motif(orc):
 
 def test_lsh_recall_is_at_least_one_minus_delta(orc):
     # Lemma 5.3: each returned motif is the true one with probability >= 1 - delta.
-    delta, hits, runs = 0.2, 0, 24
+    delta, hits, runs = 0.2, 0, 200
     for seed in range(runs):
         s = synth.make_series(1000 + seed, 3, 500, 24, 1, 2)
         res = orc.lsh_pipeline(s.x, 24, 2, 1, delta, seed=seed, K=8, L_max=16,
