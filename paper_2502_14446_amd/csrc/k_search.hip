@@ -462,6 +462,13 @@ constexpr int kFpRegs = 8;   // fingerprint words kept in registers (32 dimensio
 
 // Words between consecutive fingerprint rows in LDS: nw rounded up to odd.
 __host__ __device__ inline int lds_row_words(int nw) { return nw | 1; }
+// LDS words per member of a tile: tile P (stored twice unless the rows are
+// wider than the registers: then its circulant partners wrap explicitly),
+// tile Q, and the two index arrays.
+__host__ __device__ inline int tile_member_words(int nw)
+{
+    return (nw > kFpRegs ? 2 : 3) * lds_row_words(nw) + 2;
+}
 
 // Sum over the nw words of nonzero_bytes_28(own ^ partner): the lane's own
 // row (its first NW words in registers, the rest at own_tail, only when TAIL)
@@ -567,9 +574,9 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
     // LDS rows of fingerprint words at an odd stride, so that lanes reading
     // consecutive rows hit distinct banks
     const int ldw = lds_row_words(nw);
-    uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * (3 * ldw + 2);
-    uint32_t* fpA = mine;                         // 2 TS rows: tile P twice
-    uint32_t* fpB = fpA + (size_t)2 * TS * ldw;   // TS rows: tile Q
+    uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * tile_member_words(nw);
+    uint32_t* fpA = mine;                                    // tile P (twice unless TAIL)
+    uint32_t* fpB = fpA + (size_t)(TAIL ? 1 : 2) * TS * ldw;   // TS rows: tile Q
     uint32_t* idA = fpB + (size_t)TS * ldw;
     uint32_t* idB = idA + TS;
 
@@ -703,7 +710,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
                 for (int wd = 0; wd < nw; ++wd) {
                     const uint32_t v = fbase[(int64_t)a * nw + wd];
                     fpA[(size_t)r * ldw + wd] = v;
-                    fpA[(size_t)(r + nA) * ldw + wd] = v;
+                    if (!TAIL) fpA[(size_t)(r + nA) * ldw + wd] = v;
                 }
             }
             for (int tq = tp; tq < T; ++tq) {
@@ -727,6 +734,13 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
                     // u < nA / 2 when nA is even), or every member v of Q
                     const uint32_t* P0 = same ? fpA + (size_t)(u + 1) * ldw : fpB;
                     const int nv = same ? ((nA & 1) == 0 && u >= nA / 2 ? nA / 2 - 1 : nA / 2) : nB;
+                    // row of partner v (tile P is stored once when TAIL: wrap)
+                    auto prow = [&](int v) -> const uint32_t* {
+                        if (!TAIL || !same) return P0 + (size_t)v * ldw;
+                        int qq = u + 1 + v;
+                        if (qq >= nA) qq -= nA;
+                        return fpA + (size_t)qq * ldw;
+                    };
                     auto check = [&](int v) {
                         int qq = same ? u + 1 + v : v;
                         if (same && qq >= nA) qq -= nA;
@@ -742,12 +756,14 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
                     // (two for rows of 8 words and more, to stay within 128 VGPRs)
                     constexpr int UP = NW >= 8 ? 2 : 4;
                     for (; v + UP <= nv; v += UP) {
-                        const uint32_t* p = P0 + (size_t)v * ldw;
+                        const uint32_t* pr[UP];
+#pragma unroll
+                        for (int c = 0; c < UP; ++c) pr[c] = prow(v + c);
                         uint32_t pw[UP][NW];
 #pragma unroll
                         for (int c = 0; c < UP; ++c)
 #pragma unroll
-                            for (int wd = 0; wd < NW; ++wd) pw[c][wd] = p[c * ldw + wd];
+                            for (int wd = 0; wd < NW; ++wd) pw[c][wd] = pr[c][wd];
                         int z[UP];
 #pragma unroll
                         for (int c = 0; c < UP; ++c) {
@@ -760,7 +776,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
                             for (int wd = NW; wd < nw; ++wd) {
                                 const uint32_t o = ofw[wd];
 #pragma unroll
-                                for (int c = 0; c < UP; ++c) z[c] += nonzero_bytes_28(o ^ p[c * ldw + wd]);
+                                for (int c = 0; c < UP; ++c) z[c] += nonzero_bytes_28(o ^ pr[c][wd]);
                             }
                         uint32_t hit = 0;
 #pragma unroll
@@ -772,7 +788,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
                         }
                     }
                     for (; v < nv; ++v) {
-                        const uint32_t* p = P0 + (size_t)v * ldw;
+                        const uint32_t* p = prow(v);
                         if (screen<NW, TAIL>(ofp, ofw, [&](int wd) { return p[wd]; }, nw) <= zmax) check(v);
                     }
                 }
@@ -830,7 +846,7 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const unsigned long long*
 // within 13 KB, so that three work-groups (52 KB each) fit a CU's LDS.
 static int tile_size(int D)
 {
-    int ts = 13312 / (4 * (3 * lds_row_words(fp_words(D)) + 2));
+    int ts = 13312 / (4 * tile_member_words(fp_words(D)));
     ts = ts > 64 ? 64 : ts;
     return ts < 16 ? 16 : (ts / 16) * 16;
 }
@@ -870,7 +886,7 @@ static hipError_t go_enum(const StepGeom& g, const KT* keys, const uint32_t* idx
                           uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
 {
     const int TS = tile_size(g.D);
-    const size_t lds = (size_t)4 * TS * (3 * lds_row_words(fp_words(g.D)) + 2) * 4;   // 4 waves
+    const size_t lds = (size_t)4 * TS * tile_member_words(fp_words(g.D)) * 4;   // 4 waves
     const void* fn = (const void*)k_enum_runs<KT, NW, TAIL>;
     if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int nb = resident_blocks(fn, lds);
