@@ -460,6 +460,26 @@ __device__ inline int nonzero_bytes_28(uint32_t x)
 
 constexpr int kFpRegs = 8;   // fingerprint words kept in registers (32 dimensions)
 
+// NW consecutive words of a fingerprint row (at a multiple of NW words from
+// an aligned base) in as few vector loads as possible; zeros when !take.
+template <int NW>
+__device__ inline void load_row(uint32_t (&o)[NW], const uint32_t* src, bool take)
+{
+    if constexpr (NW % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < NW / 4; ++q) {
+            const uint4 v = take ? reinterpret_cast<const uint4*>(src)[q] : make_uint4(0u, 0u, 0u, 0u);
+            o[4 * q] = v.x; o[4 * q + 1] = v.y; o[4 * q + 2] = v.z; o[4 * q + 3] = v.w;
+        }
+    } else if constexpr (NW == 2) {
+        const uint2 v = take ? *reinterpret_cast<const uint2*>(src) : make_uint2(0u, 0u);
+        o[0] = v.x; o[1] = v.y;
+    } else {
+#pragma unroll
+        for (int wd = 0; wd < NW; ++wd) o[wd] = take ? src[wd] : 0u;
+    }
+}
+
 // Words between consecutive fingerprint rows in LDS: nw rounded up to odd.
 __host__ __device__ inline int lds_row_words(int nw) { return nw | 1; }
 // LDS words per member of a tile: tile P (stored twice unless the rows are
@@ -551,7 +571,8 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
 //  * The one run that leaves the window has its end found 64 keys at a time
 //    and is cut into tiles of TS members, staged (window index, fingerprint
 //    row) in the wave's LDS region; tile P is stored twice in a row so that
-//    the circulant partners u + 1 + v of member u need no wrap. Lane u owns
+//    the circulant partners u + 1 + v of member u need no wrap (once, with an
+//    explicit wrap, when the rows are wider than the registers). Lane u owns
 //    member u of P and walks its partners in tile Q >= P (all lanes read the
 //    same partner of Q at once: an LDS broadcast).
 // Pairs that pass the screen and are not trivial matches go to judge_pair.
@@ -652,8 +673,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
             const uint32_t xu = valid ? is[t] : 0u;
             const uint32_t* ofw = fbase + (int64_t)xu * nw;
             uint32_t ofp[NW];
-#pragma unroll
-            for (int wd = 0; wd < NW; ++wd) ofp[wd] = inner ? ofw[wd] : 0u;
+            load_row<NW>(ofp, ofw, inner);
             for (int s = 1;; ++s) {
                 const bool act = s <= npart;
                 if (!__ballot(act)) break;
@@ -707,10 +727,14 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
             for (int r = lane; r < nA; r += 64) {
                 const uint32_t a = is[start + tp * TS + r];
                 idA[r] = a;
-                for (int wd = 0; wd < nw; ++wd) {
-                    const uint32_t v = fbase[(int64_t)a * nw + wd];
-                    fpA[(size_t)r * ldw + wd] = v;
-                    if (!TAIL) fpA[(size_t)(r + nA) * ldw + wd] = v;
+                for (int w0 = 0; w0 < nw; w0 += NW) {
+                    uint32_t v[NW];
+                    load_row<NW>(v, fbase + (int64_t)a * nw + w0, true);
+#pragma unroll
+                    for (int wd = 0; wd < NW; ++wd) {
+                        fpA[(size_t)r * ldw + w0 + wd] = v[wd];
+                        if (!TAIL) fpA[(size_t)(r + nA) * ldw + w0 + wd] = v[wd];
+                    }
                 }
             }
             for (int tq = tp; tq < T; ++tq) {
@@ -721,7 +745,12 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
                     for (int r = lane; r < nB; r += 64) {
                         const uint32_t b = is[start + tq * TS + r];
                         idB[r] = b;
-                        for (int wd = 0; wd < nw; ++wd) fpB[(size_t)r * ldw + wd] = fbase[(int64_t)b * nw + wd];
+                        for (int w0 = 0; w0 < nw; w0 += NW) {
+                            uint32_t v[NW];
+                            load_row<NW>(v, fbase + (int64_t)b * nw + w0, true);
+#pragma unroll
+                            for (int wd = 0; wd < NW; ++wd) fpB[(size_t)r * ldw + w0 + wd] = v[wd];
+                        }
                     }
                 }
                 wave_sync_lds();
