@@ -47,12 +47,19 @@ struct Counters {
     unsigned long long n_coll;   // pairs of equal prefixes in the segments (trivial matches included)
     unsigned long long n_memb;   // elements in runs of >= 2
     unsigned long long n_screen; // non-trivial pairs that passed the fingerprint screen
+    uint32_t n_units;            // tile rows of long runs queued for the tile kernel
+    uint32_t pad_;
 };
 
-// A run of equal prefixes inside one sorted segment.
+// One tile row of a run of equal prefixes inside a sorted segment: tile tp of
+// the run is paired with itself and with every later tile.
 struct RunRec {
-    uint32_t seg, start, len, pad;
+    uint32_t seg, start, len, tp;
 };
+// Tile rows a batch of nseg segments can queue at most: a run is queued only
+// when it leaves its 64-element window (at most one per window), and cut into
+// tiles of at least 16 members.
+inline int64_t units_bound(int64_t nseg, int64_t ns) { return nseg * ((ns + 15) / 16 + (ns + 63) / 64 + 1); }
 
 // Control block of one replay of verified records in step order.
 constexpr int kMaxSteps = 8 * 1024;
@@ -84,6 +91,8 @@ struct SortBufs {
     uint32_t* idx[2];
     uint32_t* hist;
     int64_t tiles;
+    RunRec* units;       // tile rows of long runs, units_bound(nseg, ns) of them
+    uint32_t ucap;
 };
 struct StepGeom {
     int64_t ns;

@@ -558,6 +558,36 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
     }
 }
 
+// Queue a wavefront's pending long runs (seg, start, len) as tile rows: one
+// atomic reserves the rows of all of them, lane i writes run i's rows.
+__device__ inline void flush_runs(const uint32_t (*pend)[3], int npend, int TS, int lane,
+                                  Counters* __restrict__ cnt, RunRec* __restrict__ units, uint32_t ucap)
+{
+    wave_sync_lds();
+    uint32_t seg = 0, start = 0, len = 0, T = 0;
+    if (lane < npend) {
+        seg = pend[lane][0];
+        start = pend[lane][1];
+        len = pend[lane][2];
+        T = (len + (uint32_t)TS - 1) / (uint32_t)TS;
+    }
+    // inclusive prefix sum of T over the lanes
+    uint32_t incl = T;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&cnt->n_units, total);
+    base = (uint32_t)__shfl((int)base, 0, 64);
+    const uint32_t first = base + incl - T;
+    for (uint32_t tp = 0; tp < T; ++tp)
+        if ((uint64_t)first + tp < ucap) units[first + tp] = RunRec{seg, start, len, tp};
+    wave_sync_lds();
+}
+
 // Enumeration, fused with run detection. Segments are sorted by their
 // length-i_lo prefix (the group's lowest round), so every deeper round's runs
 // lie inside its runs. Each wavefront owns 64 consecutive elements of one
@@ -577,30 +607,23 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
 //    same partner of Q at once: an LDS broadcast).
 // Pairs that pass the screen and are not trivial matches go to judge_pair.
 template <typename KT, int NW, bool TAIL>
-__global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ keys,
+__global__ __launch_bounds__(256, NW >= 8 ? 4 : 5) void k_enum_runs(const KT* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
                                                    const uint32_t* __restrict__ H,
                                                    const uint32_t* __restrict__ fps,
                                                    const uint32_t* __restrict__ fqs, StepGeom g, int kt,
                                                    int d, int w, int TS, Cand* __restrict__ cand,
                                                    uint32_t cap, Counters* __restrict__ cnt,
-                                                   unsigned long long* __restrict__ coll_part)
+                                                   unsigned long long* __restrict__ coll_part,
+                                                   RunRec* __restrict__ units, uint32_t ucap)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ unsigned long long coll_sh[4], memb_sh[4], scr_sh[4];
+    __shared__ uint32_t pend[4][64][3];   // per wavefront: long runs waiting to be queued
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nw = TAIL ? fp_words(g.D) : NW;   // NW = min(nw, kFpRegs); TAIL iff nw > NW
     const int nq = fq_words(g.D);
     const int zmax = 28 * nw + g.D - d;
-    // LDS rows of fingerprint words at an odd stride, so that lanes reading
-    // consecutive rows hit distinct banks
-    const int ldw = lds_row_words(nw);
-    uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * tile_member_words(nw);
-    uint32_t* fpA = mine;                                    // tile P (twice unless TAIL)
-    uint32_t* fpB = fpA + (size_t)(TAIL ? 1 : 2) * TS * ldw;   // TS rows: tile Q
-    uint32_t* idA = fpB + (size_t)TS * ldw;
-    uint32_t* idB = idA + TS;
-
+    int npend = 0;   // uniform across the wavefront
     unsigned long long ncoll = 0, nmemb = 0, nscr = 0;
     uint32_t maxrun = 0;
     const int64_t wins_per_seg = (g.ns + 63) / 64;
@@ -720,8 +743,89 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
             ncoll += (unsigned long long)len * (len - 1) / 2;
             maxrun = maxrun > (uint32_t)len ? maxrun : (uint32_t)len;
         }
+        // queued for k_enum_tiles, 64 runs at a time
+        if (lane == 0) {
+            pend[wave][npend][0] = (uint32_t)seg;
+            pend[wave][npend][1] = (uint32_t)start;
+            pend[wave][npend][2] = (uint32_t)len;
+        }
+        if (++npend == 64) {
+            flush_runs(pend[wave], npend, TS, lane, cnt, units, ucap);
+            npend = 0;
+        }
+        }
+    }
+    if (npend) flush_runs(pend[wave], npend, TS, lane, cnt, units, ucap);
+    // pairs, run members and screened pairs: one triple of partial sums per
+    // work-group, no atomics
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        ncoll += __shfl_xor(ncoll, o, 64);
+        nscr += __shfl_xor(nscr, o, 64);
+    }
+    if (lane == 0) {
+        coll_sh[wave] = ncoll;
+        memb_sh[wave] = nmemb;
+        scr_sh[wave] = nscr;
+    }
+    if (lane == 0 && maxrun) atomicMax(&cnt->max_run, maxrun);   // one per wavefront
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t b = blockIdx.x;
+        coll_part[3 * b] = coll_sh[0] + coll_sh[1] + coll_sh[2] + coll_sh[3];
+        coll_part[3 * b + 1] = memb_sh[0] + memb_sh[1] + memb_sh[2] + memb_sh[3];
+        coll_part[3 * b + 2] = scr_sh[0] + scr_sh[1] + scr_sh[2] + scr_sh[3];
+    }
+}
+
+// Long runs, one tile row at a time: unit (segment, run start, run length,
+// tp) pairs tile tp of the run with itself (circulant partners) and with
+// every later tile of the run. Tiles are staged in the wave's LDS region:
+// window indices and fingerprint rows at an odd stride (lanes reading
+// consecutive rows hit distinct banks); tile P is stored twice so that the
+// circulant partners u + 1 + v of member u need no wrap (once, with an
+// explicit wrap, when the rows are wider than the registers). Lane u owns
+// member u of P and walks its partners in tile Q >= P (all lanes read the
+// same partner of Q at once: an LDS broadcast). Wavefronts take units in a
+// fixed stride; a run's rows are consecutive units, so long runs spread over
+// many wavefronts.
+template <int NW, bool TAIL>
+__global__ __launch_bounds__(256, 4) void k_enum_tiles(const uint32_t* __restrict__ idx,
+                                                    const uint32_t* __restrict__ H,
+                                                    const uint32_t* __restrict__ fps,
+                                                    const uint32_t* __restrict__ fqs, StepGeom g, int kt,
+                                                    int d, int w, int TS, const RunRec* __restrict__ units,
+                                                    uint32_t ucap, Cand* __restrict__ cand, uint32_t cap,
+                                                    Counters* __restrict__ cnt)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = TAIL ? fp_words(g.D) : NW;   // NW = min(nw, kFpRegs); TAIL iff nw > NW
+    const int nq = fq_words(g.D);
+    const int zmax = 28 * nw + g.D - d;
+    // LDS rows of fingerprint words at an odd stride, so that lanes reading
+    // consecutive rows hit distinct banks
+    const int ldw = lds_row_words(nw);
+    uint32_t* mine = reinterpret_cast<uint32_t*>(smem_raw) + (size_t)wave * TS * tile_member_words(nw);
+    uint32_t* fpA = mine;                                    // tile P (twice unless TAIL)
+    uint32_t* fpB = fpA + (size_t)(TAIL ? 1 : 2) * TS * ldw;   // TS rows: tile Q
+    uint32_t* idA = fpB + (size_t)TS * ldw;
+    uint32_t* idB = idA + TS;
+
+    unsigned long long nscr = 0;
+    const uint32_t nunits = min(cnt->n_units, ucap);
+    const uint32_t nwaves = gridDim.x * 4;
+    for (uint32_t uq = blockIdx.x * 4 + wave; uq < nunits; uq += nwaves) {
+        const RunRec un = units[uq];
+        const int seg = (int)un.seg, len = (int)un.len, tp = (int)un.tp;
+        const int64_t start = un.start;
+        const int jb = seg / g.Ds, f = seg - jb * g.Ds;
+        const int j = g.j0 + jb;
+        const uint32_t* is = idx + (int64_t)seg * g.ns;
+        const uint32_t* fbase = fps + (int64_t)jb * g.ns * nw;
+        const uint32_t* qbase = fqs + (int64_t)jb * g.ns * nq;
         const int T = (len + TS - 1) / TS;
-        for (int tp = 0; tp < T; ++tp) {
+        {
             const int nA = min(TS, len - tp * TS);
             wave_sync_lds();
             for (int r = lane; r < nA; r += 64) {
@@ -823,28 +927,11 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
                 }
             }
         }
-        }
     }
-    // pairs, run members and screened pairs: one triple of partial sums per
-    // work-group, no atomics
+    // screened pairs: one atomic per wavefront
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        ncoll += __shfl_xor(ncoll, o, 64);
-        nscr += __shfl_xor(nscr, o, 64);
-    }
-    if (lane == 0) {
-        coll_sh[wave] = ncoll;
-        memb_sh[wave] = nmemb;
-        scr_sh[wave] = nscr;
-    }
-    if (lane == 0 && maxrun) atomicMax(&cnt->max_run, maxrun);   // one per wavefront
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t b = blockIdx.x;
-        coll_part[3 * b] = coll_sh[0] + coll_sh[1] + coll_sh[2] + coll_sh[3];
-        coll_part[3 * b + 1] = memb_sh[0] + memb_sh[1] + memb_sh[2] + memb_sh[3];
-        coll_part[3 * b + 2] = scr_sh[0] + scr_sh[1] + scr_sh[2] + scr_sh[3];
-    }
+    for (int o = 32; o >= 1; o >>= 1) nscr += __shfl_xor(nscr, o, 64);
+    if (lane == 0 && nscr) atomicAdd(&cnt->n_screen, nscr);
 }
 
 __global__ __launch_bounds__(1024) void k_sum_partials(const unsigned long long* __restrict__ part,
@@ -898,44 +985,57 @@ static int resident_blocks_query(const void* fn, size_t lds)
 static int resident_blocks(const void* fn, size_t lds)
 {
     // cached per (kernel, LDS size); a stale entry only changes the grid size
-    static thread_local const void* last_fn = nullptr;
-    static thread_local size_t last_lds = 0;
-    static thread_local int last_nb = 0;
-    if (fn == last_fn && lds == last_lds) return last_nb;
-    last_fn = fn;
-    last_lds = lds;
-    last_nb = resident_blocks_query(fn, lds);
-    return last_nb;
+    struct Entry {
+        const void* fn;
+        size_t lds;
+        int nb;
+    };
+    static thread_local Entry cache[8] = {};
+    static thread_local int next = 0;
+    for (const Entry& e : cache)
+        if (e.fn == fn && e.lds == lds) return e.nb;
+    const int nb = resident_blocks_query(fn, lds);
+    cache[next] = Entry{fn, lds, nb};
+    next = (next + 1) & 7;
+    return nb;
 }
 
 
+// The windows' short runs (queueing the long ones as tile rows), then the
+// tile rows, then the sum of the first kernel's partial counts.
 template <typename KT, int NW, bool TAIL>
 static hipError_t go_enum(const StepGeom& g, const KT* keys, const uint32_t* idx, const uint32_t* H,
                           const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
-                          uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
+                          uint32_t cap, Counters* cnt, unsigned long long* part, RunRec* units,
+                          uint32_t ucap, hipStream_t s)
 {
     const int TS = tile_size(g.D);
+    const void* fa = (const void*)k_enum_runs<KT, NW, TAIL>;
+    const int nba = resident_blocks(fa, 0);
+    hipLaunchKernelGGL((k_enum_runs<KT, NW, TAIL>), dim3(nba), dim3(256), 0, s, keys, idx, H, fps, fq, g, kt,
+                       d, w, TS, cand, cap, cnt, part, units, ucap);
     const size_t lds = (size_t)4 * TS * tile_member_words(fp_words(g.D)) * 4;   // 4 waves
-    const void* fn = (const void*)k_enum_runs<KT, NW, TAIL>;
-    if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    const int nb = resident_blocks(fn, lds);
-    hipLaunchKernelGGL((k_enum_runs<KT, NW, TAIL>), dim3(nb), dim3(256), lds, s, keys, idx, H, fps, fq, g, kt,
-                       d, w, TS, cand, cap, cnt, part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, (int64_t)nb, cnt);
+    const void* fb = (const void*)k_enum_tiles<NW, TAIL>;
+    if (lds > 65536) (void)hipFuncSetAttribute(fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int nbb = resident_blocks(fb, lds);
+    hipLaunchKernelGGL((k_enum_tiles<NW, TAIL>), dim3(nbb), dim3(256), lds, s, idx, H, fps, fq, g, kt, d, w, TS,
+                       units, ucap, cand, cap, cnt);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, part, (int64_t)nba, cnt);
     return hipGetLastError();
 }
 
 template <typename KT>
 static hipError_t go_enum_nw(const StepGeom& g, const KT* k, const uint32_t* idx, const uint32_t* H,
                              const uint32_t* fps, const uint32_t* fq, int kt, int d, int w, Cand* cand,
-                             uint32_t cap, Counters* cnt, unsigned long long* part, hipStream_t s)
+                             uint32_t cap, Counters* cnt, unsigned long long* part, RunRec* u, uint32_t uc,
+                             hipStream_t s)
 {
     switch (fp_words(g.D)) {
-    case 1: return go_enum<KT, 1, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    case 2: return go_enum<KT, 2, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    case 4: return go_enum<KT, 4, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    case 8: return go_enum<KT, 8, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
-    default: return go_enum<KT, kFpRegs, true>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, s);
+    case 1: return go_enum<KT, 1, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, u, uc, s);
+    case 2: return go_enum<KT, 2, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, u, uc, s);
+    case 4: return go_enum<KT, 4, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, u, uc, s);
+    case 8: return go_enum<KT, 8, false>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, u, uc, s);
+    default: return go_enum<KT, kFpRegs, true>(g, k, idx, H, fps, fq, kt, d, w, cand, cap, cnt, part, u, uc, s);
     }
 }
 
@@ -946,9 +1046,9 @@ hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint
     if (g.i - g.i_lo + 2 > kMaxLev) return hipErrorInvalidValue;
     if (sort_keys_32(g))
         return go_enum_nw<uint32_t>(g, (const uint32_t*)b.keys[buf], b.idx[buf], H, fps, fq, kt, d, w, cand,
-                                    cap, cnt, part, s);
+                                    cap, cnt, part, b.units, b.ucap, s);
     return go_enum_nw<uint64_t>(g, (const uint64_t*)b.keys[buf], b.idx[buf], H, fps, fq, kt, d, w, cand, cap,
-                                cnt, part, s);
+                                cnt, part, b.units, b.ucap, s);
 }
 
 // ------------------------------------------------------------------ probe

@@ -440,6 +440,9 @@ static void release_search(momenti_plan* p)
     }
     dfree(p, p->sb.hist, (size_t)p->sb_nseg * 256 * p->sb.tiles * 4);
     p->sb.hist = nullptr;
+    dfree(p, p->sb.units, (size_t)p->sb.ucap * sizeof(RunRec));
+    p->sb.units = nullptr;
+    p->sb.ucap = 0;
     dfree(p, p->fps, (size_t)p->sb_reps * fp_words(p->D) * p->ns * 4);
     dfree(p, p->fq, (size_t)p->sb_reps * fq_words(p->D) * p->ns * 4);
     p->fps = nullptr;
@@ -856,7 +859,8 @@ static PoolState* st_pool(momenti_plan* p) { return (PoolState*)(p->status + 64)
 static size_t sort_bytes(int64_t reps, int64_t Ds, int64_t D, int64_t ns, int64_t tiles)
 {
     return (size_t)(reps * Ds) * ns * (8 + 8 + 4 + 4) + (size_t)(reps * Ds) * 256 * tiles * 4 +
-           (size_t)reps * ns * 4 * (fp_words((int)D) + fq_words((int)D));
+           (size_t)reps * ns * 4 * (fp_words((int)D) + fq_words((int)D)) +
+           (size_t)units_bound(reps * Ds, ns) * sizeof(RunRec);
 }
 static size_t cand_bytes(uint32_t cap) { return (size_t)cap * (sizeof(Cand) + sizeof(VRec)); }
 static size_t store_bytes(uint32_t cap) { return (size_t)cap * (sizeof(VRec) + 8); }
@@ -874,6 +878,10 @@ static int alloc_sort(momenti_plan* p, int reps, int Ds)
         if ((rc = dalloc_t(p, &p->sb.idx[q], (size_t)nseg * p->ns * 4))) return rc;
     }
     if ((rc = dalloc_t(p, &p->sb.hist, (size_t)nseg * 256 * tiles * 4))) return rc;
+    const int64_t ucap = units_bound(nseg, p->ns);
+    if (ucap > 0xFFFFFFFFll) return fail(MOMENTI_E_UNSUPPORTED, "too many segment elements per batch");
+    if ((rc = dalloc_t(p, &p->sb.units, (size_t)ucap * sizeof(RunRec)))) return rc;
+    p->sb.ucap = (uint32_t)ucap;
     if ((rc = dalloc_t(p, &p->fps, (size_t)reps * fp_words(p->D) * p->ns * 4))) return rc;
     if ((rc = dalloc_t(p, &p->fq, (size_t)reps * fq_words(p->D) * p->ns * 4))) return rc;
     return MOMENTI_OK;
@@ -1239,6 +1247,8 @@ restart:
                          (double)nc * 6.0 * p->D * p->w);
                 prof_flush(p);
             }
+            if (cnt.n_units > p->sb.ucap)   // cannot happen: ucap bounds the tile rows of a batch
+                return fail(MOMENTI_E_DEVICE, "%u tile rows queued, room for %u", cnt.n_units, p->sb.ucap);
             if (cnt.n_cand > p->cap) {
                 // more candidates than room: fewer repetitions per launch, then a larger buffer
                 if (Bc > 1) {
