@@ -911,13 +911,19 @@ __global__ __launch_bounds__(256, 4) void k_enum_tiles(const uint32_t* __restric
 #pragma unroll
                                 for (int c = 0; c < UP; ++c) z[c] += nonzero_bytes_28(o ^ pr[c][wd]);
                             }
-                        uint32_t hit = 0;
+                        // most steps pass no partner: one test of the smallest count first
+                        int zmin = z[0];
 #pragma unroll
-                        for (int c = 0; c < UP; ++c) hit |= (uint32_t)(z[c] <= zmax) << c;
-                        while (hit) {
-                            const int bit = __ffs(hit) - 1;
-                            hit &= hit - 1;
-                            check(v + bit);
+                        for (int c = 1; c < UP; ++c) zmin = min(zmin, z[c]);
+                        if (zmin <= zmax) {
+                            uint32_t hit = 0;
+#pragma unroll
+                            for (int c = 0; c < UP; ++c) hit |= (uint32_t)(z[c] <= zmax) << c;
+                            while (hit) {
+                                const int bit = __ffs(hit) - 1;
+                                hit &= hit - 1;
+                                check(v + bit);
+                            }
                         }
                     }
                     for (; v < nv; ++v) {
