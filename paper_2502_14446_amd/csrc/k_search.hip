@@ -965,11 +965,14 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const unsigned long long*
 }
 
 // Members per tile: a wave's region (tile P twice, tile Q, indices) stays
-// within 13 KB, so that three work-groups (52 KB each) fit a CU's LDS.
+// within 13 KB, so that three work-groups (52 KB each) fit a CU's LDS; up to
+// 128 members for rows of at most 2 words (fewer tile rows per run, each
+// lane owning two members of P), 64 otherwise.
 static int tile_size(int D)
 {
+    const int cap = fp_words(D) <= 2 ? 128 : 64;
     int ts = 13312 / (4 * tile_member_words(fp_words(D)));
-    ts = ts > 64 ? 64 : ts;
+    ts = ts > cap ? cap : ts;
     return ts < 16 ? 16 : (ts / 16) * 16;
 }
 
