@@ -90,7 +90,9 @@ typedef struct {
     int32_t series_on_device; /* 1: the series pointer passed to momenti_hash is device memory */
     int32_t pool_size;        /* verified pairs kept on the device; 0 = max(4096, 64 k) */
     int32_t batch_reps;       /* repetitions traversed per launch; 0 = chosen from mem_limit */
-    int32_t profile;          /* 1: time every kernel launch with HIP events (momenti_get_profile) */
+    int32_t profile;          /* 1: time every kernel launch with HIP events (momenti_get_profile);
+                                 2: time only the pair enumeration (the dominant kernel, least
+                                 overhead); 0: off */
     double merge_pairs;       /* rounds join the first round group (one sort) while their colliding
                                  pairs are estimated at most this many per segment element;
                                  <= 0 means 8 (about the cost of one sort pass) */
@@ -249,6 +251,10 @@ int momenti_set_trace(momenti_plan* p, int64_t* cand, int64_t cand_cap, int64_t*
  * since the plan was prepared or the profile was last cleared; *n gets the
  * number of kernels. clear != 0 resets the totals afterwards. */
 int momenti_get_profile(momenti_plan* p, momenti_kprof* out, int32_t cap, int32_t* n, int32_t clear);
+
+/* Change the profiling mode of a prepared plan (values as opts.profile);
+ * totals already collected are kept. */
+int momenti_set_profile(momenti_plan* p, int32_t mode);
 
 #ifdef __cplusplus
 }

@@ -165,6 +165,7 @@ struct KTotal {
 
 struct Profiler {
     bool on = false;
+    bool enum_only = false;   // time only the pair enumeration
     struct Pending {
         int id;
         hipEvent_t a, b;
@@ -358,7 +359,7 @@ template <class F>
 static hipError_t timed(momenti_plan* p, int id, double bytes, double flops, F&& fn, int* slot = nullptr)
 {
     if (slot) *slot = -1;
-    if (!p->prof.on) return fn();
+    if (!p->prof.on || (p->prof.enum_only && id != KI_ENUM)) return fn();
     hipEvent_t a = prof_event(p), b = prof_event(p);
     (void)hipEventRecord(a, p->st);
     hipError_t e = fn();
@@ -562,6 +563,7 @@ static int prepare_impl(momenti_plan** out, int64_t n, int32_t D, int32_t w, int
     p->wpad = ((w + 63) / 64) * 64;
     p->st = (hipStream_t)o.stream;
     p->prof.on = o.profile != 0;
+    p->prof.enum_only = o.profile == 2;
     if (hipGetDevice(&p->dev) != hipSuccess) {
         delete p;
         return fail(MOMENTI_E_DEVICE, "no HIP device");
@@ -786,6 +788,15 @@ int momenti_get_profile(momenti_plan* p, momenti_kprof* out, int32_t cap, int32_
     }
     if (clear)
         for (auto& t : p->prof.tot) t = KTotal();
+    return MOMENTI_OK;
+}
+
+int momenti_set_profile(momenti_plan* p, int32_t mode)
+{
+    if (!p) return fail(MOMENTI_E_ARG, "plan is NULL");
+    if (mode < 0 || mode > 2) return fail(MOMENTI_E_ARG, "profile mode %d outside [0, 2]", mode);
+    p->prof.on = mode != 0;
+    p->prof.enum_only = mode == 2;
     return MOMENTI_OK;
 }
 

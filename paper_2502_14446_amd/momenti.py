@@ -26,6 +26,7 @@ EXPORTS = [
     "momenti_default_opts", "momenti_prepare", "momenti_hash", "momenti_search", "momenti_topk",
     "momenti_destroy", "momenti_last_error", "momenti_get_params", "momenti_get_stats",
     "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace", "momenti_get_profile",
+    "momenti_set_profile",
     "momenti_topk_batch",
 ]
 
@@ -96,6 +97,7 @@ def lib():
             "momenti_set_hashes": (i32, [vp, vp, C.c_size_t]),
             "momenti_set_trace": (i32, [vp, vp, i64, vp, vp, vp, i64, i32]),
             "momenti_get_profile": (i32, [vp, P(KProf), i32, P(i32), i32]),
+            "momenti_set_profile": (i32, [vp, i32]),
             "momenti_topk_batch": (i32, [P(Job), i32, u64, P(Opts), i32, P(Motif), P(i32), P(i32),
                                          P(Report)]),
         }
@@ -115,7 +117,7 @@ def _check(rc: int) -> int:
 
 def make_opts(seed: int = 0x5EED, K: int = 8, L: int = 200, r: float = 0.0, proj: str = "f32",
               stop: str = "tensor", series_on_device: bool = False, pool_size: int = 0,
-              batch_reps: int = 0, profile: bool = False, stream: Optional[int] = None,
+              batch_reps: int = 0, profile: int = 0, stream: Optional[int] = None,
               r_scale: float = 1.0, max_pairs: float = 0.0, merge_pairs: float = 0.0) -> Opts:
     o = Opts()
     lib().momenti_default_opts(C.byref(o))
@@ -124,7 +126,7 @@ def make_opts(seed: int = 0x5EED, K: int = 8, L: int = 200, r: float = 0.0, proj
     o.proj, o.stop_rule = PROJ[proj], STOP[stop]
     o.series_on_device = 1 if series_on_device else 0
     o.pool_size, o.batch_reps = pool_size, batch_reps
-    o.profile = 1 if profile else 0
+    o.profile = int(profile)
     o.stream = stream
     return o
 
@@ -238,6 +240,10 @@ class Plan:
         _check(lib().momenti_get_profile(self.h, recs, 32, C.byref(n), 1 if clear else 0))
         return {r.name.decode(): dict(launches=r.launches, ms=r.ms, bytes=r.bytes, flops=r.flops)
                 for r in recs[:n.value]}
+
+    def set_profile(self, mode: int) -> None:
+        """0 off, 1 every kernel launch, 2 only the pair enumeration."""
+        _check(lib().momenti_set_profile(self.h, int(mode)))
 
     def set_trace(self, cand_cap: int, k: int) -> None:
         K, L = self.opts.K, self.params()["L"]
