@@ -38,18 +38,24 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_sha(kernel: str) -> str | None:
+def code_sha(kernel: str) -> str | None:
+    """SHA-256 of the kernel's source with comments removed and whitespace
+    collapsed: an edit to comments alone leaves it (and the compiled code)
+    unchanged."""
     src = KERNEL_SOURCES.get(kernel)
     if not src:
         return None
-    with open(os.path.join(ROOT, src), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    with open(os.path.join(ROOT, src), encoding="utf-8") as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
 
 
 def measured_traffic(kernel: str, workload: str) -> float | None:
     """HBM bytes per launch from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or None when
-    there is none or the kernel's source changed since it was taken."""
+    there is none or the kernel's code changed since it was taken."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}_pmc.md")
     if not os.path.exists(path):
         return None
@@ -59,7 +65,7 @@ def measured_traffic(kernel: str, workload: str) -> float | None:
             m = re.match(r"^- (\w+): (\S+)$", line.strip())
             if m:
                 vals[m.group(1)] = m.group(2)
-    if vals.get("source_sha256") != source_sha(kernel):
+    if vals.get("code_sha256") != code_sha(kernel):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])

@@ -785,10 +785,10 @@ __global__ __launch_bounds__(256, NW >= 8 ? 4 : 5) void k_enum_runs(const KT* __
 // consecutive rows hit distinct banks); tile P is stored twice so that the
 // circulant partners u + 1 + v of member u need no wrap (once, with an
 // explicit wrap, when the rows are wider than the registers). Lane u owns
-// member u of P and walks its partners in tile Q >= P (all lanes read the
-// same partner of Q at once: an LDS broadcast). Wavefronts take units in a
-// fixed stride; a run's rows are consecutive units, so long runs spread over
-// many wavefronts.
+// members u, u + 64, ... of P and walks their partners in tile Q >= P (all
+// lanes read the same partner of Q at once: an LDS broadcast). Wavefronts
+// take units in a fixed stride; a run's rows are consecutive units, so long
+// runs spread over many wavefronts.
 template <int NW, bool TAIL>
 __global__ __launch_bounds__(256, 4) void k_enum_tiles(const uint32_t* __restrict__ idx,
                                                     const uint32_t* __restrict__ H,
