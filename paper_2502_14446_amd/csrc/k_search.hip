@@ -209,6 +209,20 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ hist, int6
     }
 }
 
+// Work-groups are dealt to the 8 XCDs round-robin by linear id, so adjacent
+// tiles, which write adjacent pieces of every digit's output range, would sit
+// in different L2 caches. This bijection of the (segment, tile) grid gives
+// each XCD one contiguous range of tiles instead.
+__device__ inline void xcd_tile(int64_t tiles, int& seg, int64_t& tile)
+{
+    const int64_t total = tiles * gridDim.y;
+    const int64_t lin = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+    const int64_t q = total / 8, r = total % 8, k = lin % 8;
+    const int64_t m = k * q + (k < r ? k : r) + lin / 8;
+    seg = (int)(m / tiles);
+    tile = m - (int64_t)seg * tiles;
+}
+
 template <typename KT, bool FIRST>
 __global__ __launch_bounds__(256) void k_scatter(const KT* __restrict__ kin, const uint32_t* __restrict__ iin,
                                                  const uint32_t* __restrict__ H, StepGeom g, int pass,
@@ -223,8 +237,9 @@ __global__ __launch_bounds__(256) void k_scatter(const KT* __restrict__ kin, con
     __shared__ uint32_t gofs[256];
     __shared__ uint32_t scan_sh[4];
 
-    const int seg = blockIdx.y;
-    const int64_t tile = blockIdx.x;
+    int seg;
+    int64_t tile;
+    xcd_tile(tiles, seg, tile);
     const int64_t base = tile * kSortTile;
     const int count = (int)((g.ns - base) < kSortTile ? (g.ns - base) : kSortTile);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
