@@ -157,10 +157,34 @@ __global__ __launch_bounds__(256) void k_hist(const KT* __restrict__ kin, const 
     SegPtr sp;
     if (FIRST) sp = seg_words(H, g, seg);
     const KT* ks = kin + (int64_t)seg * g.ns;
-    for (int64_t e = base + threadIdx.x; e < end; e += 256) {
-        KT key = FIRST ? sort_key<KT>(sp.Lw[e], sp.Rw[e], g) : ks[e];
-        atomicAdd(&cnt[(uint32_t)(key >> (8 * pass)) & 255u], 1u);
+    // every load of the tile first, then the keys, then the counts: a loop
+    // that counted each element as it arrived would wait out one memory
+    // latency per element
+    constexpr int ITEMS = kSortTile / 256;
+    uint32_t dg[ITEMS];
+    if constexpr (FIRST) {
+        uint32_t lv[ITEMS], rv[ITEMS];
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            const int64_t e = base + q * 256 + threadIdx.x;
+            lv[q] = e < end ? sp.Lw[e] : 0u;
+            rv[q] = e < end ? sp.Rw[e] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) dg[q] = (uint32_t)(sort_key<KT>(lv[q], rv[q], g) >> (8 * pass)) & 255u;
+    } else {
+        KT kv[ITEMS];
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            const int64_t e = base + q * 256 + threadIdx.x;
+            kv[q] = e < end ? ks[e] : (KT)0;
+        }
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) dg[q] = (uint32_t)(kv[q] >> (8 * pass)) & 255u;
     }
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q)
+        if (base + q * 256 + threadIdx.x < end) atomicAdd(&cnt[dg[q]], 1u);
     __syncthreads();
     hist[((int64_t)seg * tiles + tile) * 256 + threadIdx.x] = cnt[threadIdx.x];
 }
@@ -253,22 +277,35 @@ __global__ __launch_bounds__(256) void k_scatter(const KT* __restrict__ kin, con
     const uint32_t* is = iin + (int64_t)seg * g.ns;
     KT k_[ITEMS];
     uint32_t i_[ITEMS], r_[ITEMS];
+    // wave-contiguous blocks of the tile keep the order; every load is issued
+    // before the first ranking step waits on one
+    if constexpr (FIRST) {
+        uint32_t lv[ITEMS], rv[ITEMS];
+#pragma unroll
+        for (int s = 0; s < ITEMS; ++s) {
+            const int e = wave * (kSortTile / 4) + s * 64 + lane;
+            lv[s] = e < count ? sp.Lw[base + e] : 0u;
+            rv[s] = e < count ? sp.Rw[base + e] : 0u;
+        }
+#pragma unroll
+        for (int s = 0; s < ITEMS; ++s) {
+            const int e = wave * (kSortTile / 4) + s * 64 + lane;
+            k_[s] = e < count ? sort_key<KT>(lv[s], rv[s], g) : (KT)0;
+            i_[s] = e < count ? (uint32_t)(base + e) : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < ITEMS; ++s) {
+            const int e = wave * (kSortTile / 4) + s * 64 + lane;
+            k_[s] = e < count ? ks[base + e] : (KT)0;
+            i_[s] = e < count ? is[base + e] : 0u;
+        }
+    }
 #pragma unroll
     for (int s = 0; s < ITEMS; ++s) {
-        const int e = wave * (kSortTile / 4) + s * 64 + lane;   // wave-contiguous blocks keep order
+        const int e = wave * (kSortTile / 4) + s * 64 + lane;
         const bool valid = e < count;
-        KT key = 0;
-        uint32_t id = 0;
-        if (valid) {
-            const int64_t ge = base + e;
-            if (FIRST) {
-                key = sort_key<KT>(sp.Lw[ge], sp.Rw[ge], g);
-                id = (uint32_t)ge;
-            } else {
-                key = ks[ge];
-                id = is[ge];
-            }
-        }
+        const KT key = k_[s];
         const uint32_t dg = (uint32_t)(key >> (8 * pass)) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -281,8 +318,6 @@ __global__ __launch_bounds__(256) void k_scatter(const KT* __restrict__ kin, con
         uint32_t before = 0;
         if (valid) before = wcnt[wave][dg];
         if (valid && rank == 0) wcnt[wave][dg] = before + (uint32_t)__popcll(peers);
-        k_[s] = key;
-        i_[s] = id;
         r_[s] = before + rank;
     }
     __syncthreads();
@@ -661,6 +696,10 @@ __global__ __launch_bounds__(256, NW >= 8 ? 4 : 5) void k_enum_runs(const KT* __
         const uint32_t* is = idx + (int64_t)seg * g.ns;
         const uint32_t* fbase = fps + (int64_t)jb * g.ns * nw;
         const uint32_t* qbase = fqs + (int64_t)jb * g.ns * nq;
+        // bit 2r: the lane's key in window r equals the one before it, bit
+        // 2r + 1: the one after it; xr: the window indices of run members
+        uint32_t sflags = 0;
+        uint32_t xr[4];
         {
             // fast skip: most groups of windows hold no run at the lowest round
             // of the first round group
@@ -673,15 +712,23 @@ __global__ __launch_bounds__(256, NW >= 8 ? 4 : 5) void k_enum_runs(const KT* __
                 const int64_t te = lane == 0 ? t - 1 : t + 1;
                 kedge[r] = ((lane == 0 || lane == 63) && te >= 0 && te < g.ns) ? ks[te] : (KT)0;
             }
-            bool any = false;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t t = qstart + 64 * r + lane;
-                const KT kp = lane == 0 ? kedge[r] : (KT)__shfl_up(kq[r], 1, 64);
-                const KT kn = lane == 63 ? kedge[r] : (KT)__shfl_down(kq[r], 1, 64);
-                any |= t < g.ns && ((t > 0 && kp == kq[r]) || (t + 1 < g.ns && kn == kq[r]));
+                // every lane takes part in both shuffles (a lane left out of one
+                // would hand its neighbour 0 instead of its key), then selects
+                const KT up = (KT)__shfl_up(kq[r], 1, 64);
+                const KT dn = (KT)__shfl_down(kq[r], 1, 64);
+                const KT kp = lane == 0 ? kedge[r] : up;
+                const KT kn = lane == 63 ? kedge[r] : dn;
+                const bool sp = t < g.ns && t > 0 && kp == kq[r];
+                const bool sn = t < g.ns && t + 1 < g.ns && kn == kq[r];
+                sflags |= ((sp ? 1u : 0u) | (sn ? 2u : 0u)) << (2 * r);
             }
-            if (!__ballot(any)) continue;
+            if (!__ballot(sflags != 0)) continue;
+            // the four windows' indices in one round of loads
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xr[r] = ((sflags >> (2 * r)) & 3u) ? is[qstart + 64 * r + lane] : 0u;
         }
 #pragma unroll 1
         for (int r = 0; r < 4; ++r) {
@@ -689,9 +736,8 @@ __global__ __launch_bounds__(256, NW >= 8 ? 4 : 5) void k_enum_runs(const KT* __
         if (base >= g.ns) break;
         const int64_t t = base + lane;
         const bool valid = t < g.ns;
-        const KT k = valid ? ks[t] : (KT)0;
-        const bool same_prev = valid && t > 0 && ks[t - 1] == k;
-        const bool same_next = valid && t + 1 < g.ns && ks[t + 1] == k;
+        const bool same_prev = ((sflags >> (2 * r)) & 1u) != 0;
+        const bool same_next = ((sflags >> (2 * r)) & 2u) != 0;
         const bool head = valid && !same_prev && same_next;
         const uint64_t heads = __ballot(head);
         if (!heads) continue;
@@ -708,7 +754,7 @@ __global__ __launch_bounds__(256, NW >= 8 ? 4 : 5) void k_enum_runs(const KT* __
         ncoll += (unsigned long long)npart;
         if (lane == 0) nmemb += (unsigned long long)__popcll(inner_bits);
         if (inner_bits) {
-            const uint32_t xu = valid ? is[t] : 0u;
+            const uint32_t xu = r == 0 ? xr[0] : r == 1 ? xr[1] : r == 2 ? xr[2] : xr[3];
             const uint32_t* ofw = fbase + (int64_t)xu * nw;
             uint32_t ofp[NW];
             load_row<NW>(ofp, ofw, inner);
@@ -742,7 +788,7 @@ __global__ __launch_bounds__(256, NW >= 8 ? 4 : 5) void k_enum_runs(const KT* __
         const uint64_t open = __ballot(head && !tb);
         if (!open) continue;
         const int hl = __ffsll((unsigned long long)open) - 1;
-        const KT hk = __shfl(k, hl, 64);
+        const KT hk = ks[base + hl];
         int64_t pos = base + 64, end = -1;
         while (end < 0) {
             const int64_t ee = pos + lane;
