@@ -657,7 +657,7 @@ __device__ inline void flush_runs(const uint32_t (*pend)[3], int npend, int TS, 
 //    same partner of Q at once: an LDS broadcast).
 // Pairs that pass the screen and are not trivial matches go to judge_pair.
 template <typename KT, int NW, bool TAIL>
-__global__ __launch_bounds__(256, NW >= 8 ? 4 : 5) void k_enum_runs(const KT* __restrict__ keys,
+__global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ keys,
                                                    const uint32_t* __restrict__ idx,
                                                    const uint32_t* __restrict__ H,
                                                    const uint32_t* __restrict__ fps,
