@@ -201,10 +201,16 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ hist, int6
     const int grp = threadIdx.x >> 8, dg = threadIdx.x & 255;
     const int64_t per = (tiles + 3) / 4;
     const int64_t t0 = grp * per, t1 = t0 + per < tiles ? t0 + per : tiles;
+    // eight rows in flight per thread in both passes over the tiles
     uint32_t s = 0;
     int64_t t = t0;
-    for (; t + 4 <= t1; t += 4)
-        s += h[t * 256 + dg] + h[(t + 1) * 256 + dg] + h[(t + 2) * 256 + dg] + h[(t + 3) * 256 + dg];
+    for (; t + 8 <= t1; t += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = h[(t + u) * 256 + dg];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
     for (; t < t1; ++t) s += h[t * 256 + dg];
     part[grp][dg] = s;
     __syncthreads();
@@ -226,7 +232,17 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ hist, int6
         base = part[0][dg];
     }
     uint32_t run = base + before;
-    for (t = t0; t < t1; ++t) {
+    for (t = t0; t + 8 <= t1; t += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = h[(t + u) * 256 + dg];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            h[(t + u) * 256 + dg] = run;
+            run += v[u];
+        }
+    }
+    for (; t < t1; ++t) {
         const uint32_t v = h[t * 256 + dg];
         h[t * 256 + dg] = run;
         run += v;
@@ -433,10 +449,17 @@ __device__ inline uint32_t prefix_digest16(uint64_t prefix, int i_lo)
 __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H, StepGeom g, int reps,
                                                  uint32_t* __restrict__ fps, uint32_t* __restrict__ fq)
 {
-    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (gid >= (int64_t)reps * g.ns) return;
-    const int jb = (int)(gid / g.ns);
-    const int64_t a = gid - (int64_t)jb * g.ns;
+    // work-group m = (tile of 256 windows) * reps + repetition, with each XCD
+    // taking one contiguous range of m: the batch's repetitions of a tile run
+    // back to back on one XCD, and the left half-function words they share
+    // (one left function serves g.m consecutive repetitions) come from its L2
+    const int64_t nb = (int64_t)gridDim.x;
+    const int64_t q = nb / 8, rr = nb % 8, x = blockIdx.x % 8;
+    const int64_t m = x * q + (x < rr ? x : rr) + blockIdx.x / 8;
+    const int jb = (int)(m % reps);
+    const int64_t a = (m / reps) * 256 + threadIdx.x;
+    if (a >= g.ns) return;
+    const int64_t gid = (int64_t)jb * g.ns + a;
     const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
     const int nw = fp_words(g.D), nq = fq_words(g.D);
     uint32_t* fw = fps + gid * nw;
@@ -475,9 +498,8 @@ __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H,
 hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, uint32_t* fq,
                           hipStream_t s)
 {
-    const int64_t total = (int64_t)reps * g.ns;
-    hipLaunchKernelGGL(k_fptable, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, H, g, reps, fps,
-                       fq);
+    const int64_t blocks = (g.ns + 255) / 256 * reps;   // (tile, repetition) pairs
+    hipLaunchKernelGGL(k_fptable, dim3((unsigned)blocks), dim3(256), 0, s, H, g, reps, fps, fq);
     return hipGetLastError();
 }
 
