@@ -227,7 +227,7 @@ def _oracle_sets(cand):
     return sets
 
 
-def _check_traversal(orc, s, p, seed, K, L, k, d, delta, rule, **kw):
+def _check_traversal(orc, s, p, seed, K, L, k, d, delta, rule, craft=None, **kw):
     plan, _ = _plan(s, p, "f64", seed, K=K, L=L, stop=rule, batch_reps=4, **kw)
     prm = plan.params()
     Lu = prm["L"]
@@ -235,6 +235,8 @@ def _check_traversal(orc, s, p, seed, K, L, k, d, delta, rule, **kw):
     r = prm["r"]
     assert r == orc.estimate_r(s.x, p["w"], seed) * kw.get("r_scale", 1.0)
     ref_sym, _, _ = _oracle_symbols(orc, s.x, p["w"], R, U, r)
+    if craft is not None:                        # an index made up by the test
+        ref_sym = craft(ref_sym, prm)
     words = orc.pack(ref_sym, prm["NF"], K)
     plan.set_hashes(words)                       # traverse the oracle's own index
     plan.set_trace(4_000_000, k)
@@ -329,6 +331,48 @@ def test_traversal_matches_oracle_rows_beyond_registers(orc):
     p = dict(w=30, mem_limit=1 << 30)
     rep, ref = _check_traversal(orc, s, p, 9, 8, 12, 2, 10, 1e-4, "lemma52", r_scale=8.0)
     assert ref["i_stop"] == 0 and rep["max_run"] > 64
+
+
+def test_traversal_runs_at_window_edges(orc):
+    # A made-up index whose sorted segments hold runs exactly where the
+    # enumeration's 64-element windows meet: the first two and last two lanes
+    # of a window, a pair straddling two windows, runs ending on the last
+    # lane, and one run crossing two window boundaries; every other window is
+    # alone. Position 0 of each left half-function carries the high byte of
+    # the window's group, of each right half-function the low byte, the rest
+    # 0, so the length-2 prefix is the group itself (plain sort keys, sorted
+    # position = group order) and both dimensions collide alike (d = 2).
+    # Sorted neighbours are windows far apart in time, so their pairs are not
+    # trivial matches.
+    s = synth.make_series(77, 2, 1400, 30, 1, 2, dtype="f64")
+    p = dict(w=30, mem_limit=1 << 30)
+    ns = s.n - p["w"] + 1
+    runs = [(0, 2), (62, 64), (127, 129), (191, 193), (254, 256), (317, 320), (383, 386), (500, 600), (700, 702)]
+    inner = {q for a0, a1 in runs for q in range(a0 + 1, a1)}
+    group = np.cumsum([0 if q in inner else 1 for q in range(ns)]) - 1
+    step = int(ns * 0.381966) | 1
+    while math.gcd(step, ns) != 1:
+        step += 2
+    win = (np.arange(ns) * step) % ns            # sorted position -> window
+    gw = np.empty(ns, dtype=np.int64)
+    gw[win] = group
+
+    def craft(sym, prm):
+        sym = np.zeros_like(sym)
+        for F in range(prm["NF"]):
+            sym[:, :, 4 * F] = (gw >> 8) & 255 if F < prm["n_left"] else gw & 255
+        return sym
+
+    rep, ref = _check_traversal(orc, s, p, 3, 8, 4, 1, 2, 0.1, "lemma52", craft=craft)
+    # the designed runs were there to be found: every non-trivial pair of them
+    # is a candidate of the first step on both sides
+    first = {(int(a), int(b)) for st, a, b in ref["cand"] if int(st) == 0}
+    want = set()
+    for a0, a1 in runs:
+        ws = sorted(int(win[q]) for q in range(a0, a1))
+        want |= {(x, y) for i, x in enumerate(ws) for y in ws[i + 1:] if 2 * (y - x) > p["w"]}
+    assert want and want <= first
+    assert rep["first_group_lo"] <= 4 and rep["max_run"] >= 100
 
 
 def test_example_4_1_on_device(orc):
