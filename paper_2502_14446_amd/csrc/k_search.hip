@@ -660,23 +660,18 @@ __device__ inline void flush_runs(const uint32_t (*pend)[3], int npend, int TS, 
     wave_sync_lds();
 }
 
-// Enumeration, fused with run detection. Segments are sorted by their
-// length-i_lo prefix (the group's lowest round), so every deeper round's runs
-// lie inside its runs. Each wavefront owns 64 consecutive elements of one
-// segment: ballots mark the heads of runs of length >= 2 that start there and
-// the tails where runs end.
+// Window scan: run detection and the runs that fit a window. Segments are
+// sorted by their length-i_lo prefix (the group's lowest round), so every
+// deeper round's runs lie inside its runs. Each wavefront owns 64 consecutive
+// elements of one segment (four such windows at a time): ballots mark the
+// heads of runs of length >= 2 that start there and the tails where runs end.
 //  * Runs that close inside the window are enumerated all at once, lane by
 //    lane: the member at position q of a run of n pairs with the members at
 //    q + s (mod n), 1 <= s <= (n - 1) / 2, plus, for even n and q < n / 2, the
 //    one at q + n / 2, which covers each unordered pair once; fingerprint
 //    words reach the partner by cross-lane permutes.
 //  * The one run that leaves the window has its end found 64 keys at a time
-//    and is cut into tiles of TS members, staged (window index, fingerprint
-//    row) in the wave's LDS region; tile P is stored twice in a row so that
-//    the circulant partners u + 1 + v of member u need no wrap (once, with an
-//    explicit wrap, when the rows are wider than the registers). Lane u owns
-//    member u of P and walks its partners in tile Q >= P (all lanes read the
-//    same partner of Q at once: an LDS broadcast).
+//    and is queued, as one unit per tile of TS members, for k_enum_tiles.
 // Pairs that pass the screen and are not trivial matches go to judge_pair.
 template <typename KT, int NW, bool TAIL>
 __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ keys,
