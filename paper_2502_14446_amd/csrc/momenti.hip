@@ -184,13 +184,15 @@ struct Profiler {
 struct BlockCache {
     std::vector<std::pair<size_t, void*>> idle;    // (capacity, block)
     std::vector<std::pair<void*, size_t>> owned;   // every block, with its capacity
+    bool exact = false;                            // reuse only blocks of the requested size
     void* take(size_t bytes)
     {
         int best = -1;
-        for (int q = 0; q < (int)idle.size(); ++q)
-            if (idle[q].first >= bytes && idle[q].first <= 2 * bytes + (1u << 20) &&
-                (best < 0 || idle[q].first < idle[best].first))
-                best = q;
+        for (int q = 0; q < (int)idle.size(); ++q) {
+            const size_t c = idle[q].first;
+            const bool fits = exact ? c == bytes : (c >= bytes && c <= 2 * bytes + (1u << 20));
+            if (fits && (best < 0 || c < idle[best].first)) best = q;
+        }
         if (best < 0) return nullptr;
         void* b = idle[best].second;
         idle.erase(idle.begin() + best);
@@ -204,6 +206,15 @@ struct BlockCache {
                 return;
             }
         (void)hipFree(b);   // not ours
+    }
+    void drop(void* b)   // return a block in use to the runtime
+    {
+        for (size_t q = 0; q < owned.size(); ++q)
+            if (owned[q].first == b) {
+                owned.erase(owned.begin() + q);
+                break;
+            }
+        (void)hipFree(b);
     }
     void trim()   // return idle blocks to the runtime
     {
@@ -224,7 +235,9 @@ struct BlockCache {
 };
 
 struct momenti_plan {
-    BlockCache* cache = nullptr;   // set for plans run by a batch worker
+    BlockCache* cache = nullptr;   // the batch worker's blocks, or own_cache
+    BlockCache own_cache;          // a plan of its own: blocks its next search reuses
+    bool recycle = false;          // own_cache: a search is releasing and re-taking its buffers
     int64_t n = 0, ns = 0;
     int D = 0, w = 0, dtype = 1;
     uint64_t mem_limit = 0;
@@ -323,10 +336,10 @@ static int dalloc_t(momenti_plan* p, T** ptr, size_t bytes)
 static void dfree(momenti_plan* p, void* ptr, size_t bytes)
 {
     if (!ptr) return;
-    if (p->cache)
-        p->cache->give(ptr);   // the worker's stream keeps later uses in order
+    if (p->cache != &p->own_cache || p->recycle)
+        p->cache->give(ptr);   // the plan's stream keeps later uses in order
     else
-        (void)hipFree(ptr);
+        p->cache->drop(ptr);
     if (bytes == 0) bytes = 16;
     p->bytes -= std::min<uint64_t>(p->bytes, bytes);
 }
@@ -553,7 +566,8 @@ static int prepare_impl(momenti_plan** out, int64_t n, int32_t D, int32_t w, int
 
     momenti_plan* p = new (std::nothrow) momenti_plan();
     if (!p) return fail(MOMENTI_E_NOMEM, "host allocation failed");
-    p->cache = cache;
+    p->cache = cache ? cache : &p->own_cache;
+    p->own_cache.exact = true;
     p->n = n; p->ns = n - w + 1; p->D = D; p->w = w; p->dtype = dtype; p->mem_limit = mem_limit;
     p->o = o; p->K = o.K; p->L = L;
     tensor_shape(L, &p->m, &p->NL, &p->NR);
@@ -1028,6 +1042,13 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     R.r = p->r;
     R.t_hash_ms = p->t_hash_ms;
 
+    // a plan of its own keeps the blocks of its previous search for this one
+    // (same sizes when the arguments repeat) until its allocations are done
+    struct Recycle {
+        momenti_plan* p;
+        ~Recycle() { p->recycle = false; }
+    } recycling{p};
+    p->recycle = true;
     release_search(p);
     const int max_steps = std::min(p->K, 7) * p->L;   // steps of the largest round group
     int P = p->o.pool_size ? p->o.pool_size : std::max(4096, 128 * k);
@@ -1062,6 +1083,13 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         if ((rc = dalloc_t(p, &p->coll_part, (size_t)p->coll_parts * 24))) return rc;
     }
     R.batch_reps = B;
+    // a plan of its own frees the blocks of its previous search that this one
+    // did not take back, so that it holds what it uses (a batch worker keeps
+    // them for its next series)
+    if (p->cache == &p->own_cache) {
+        p->own_cache.trim();
+        p->recycle = false;
+    }
 
     // Probe: repetition 0 of the first (up to 8) segment dimensions, sorted by
     // the full K-symbol prefix, gives the colliding pairs of every round;
