@@ -174,7 +174,9 @@ int momenti_hash(momenti_plan* p, const void* series);
  * Algorithm 2): writes up to k motifs to out (caller-owned, capacity >= k) in
  * increasing (dist_d, a, b) order and their count to *n_out (< k only when
  * fewer non-overlapping non-trivial pairs exist). rep may be NULL.
- * d in [1, D], k in [1, 4096], delta in (0, 1).
+ * d in [1, D], k in [1, 4096], delta in (0, 1). The traversal buffers stay
+ * with the plan after the call; the next search reuses those of the sizes it
+ * needs and frees the others (all within mem_limit).
  * Returns MOMENTI_OK, MOMENTI_OK_FALLBACK (exact answer, no step stopped),
  * MOMENTI_OK_PARTIAL (opts.max_pairs reached: TOP so far, possibly fewer than
  * k pairs), or E_ARG, E_STATE (momenti_hash not called), E_NOMEM, E_DEVICE,
