@@ -464,7 +464,9 @@ __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H,
     const int nw = fp_words(g.D), nq = fq_words(g.D);
     uint32_t* fw = fps + gid * nw;
     uint4* qw = reinterpret_cast<uint4*>(fq + gid * nq);
-    uint32_t word = 0;
+    // the fingerprint row leaves in 8- or 16-byte stores (w0..w3: the last
+    // four completed words), so that each store fills whole pieces of lines
+    uint32_t word = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
     uint32_t q4[4] = {0, 0, 0, 0};
     const int nf = 4 * nw > 2 * nq ? 4 * nw : 2 * nq;
     for (int f = 0; f < nf; ++f) {
@@ -479,8 +481,16 @@ __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H,
         if (f < 4 * nw) {
             word |= d8 << (8 * (f & 3));
             if ((f & 3) == 3) {
-                fw[f >> 2] = word;
+                w0 = w1; w1 = w2; w2 = w3; w3 = word;
                 word = 0;
+                const int wi = f >> 2;   // the word just completed
+                if (nw == 1)
+                    fw[0] = w3;
+                else if (nw == 2) {
+                    if (wi == 1) *reinterpret_cast<uint2*>(fw) = make_uint2(w2, w3);
+                } else if ((wi & 3) == 3) {
+                    reinterpret_cast<uint4*>(fw)[wi >> 2] = make_uint4(w0, w1, w2, w3);
+                }
             }
         }
         if (f < 2 * nq) {
