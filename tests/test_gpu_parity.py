@@ -375,6 +375,30 @@ def test_traversal_runs_at_window_edges(orc):
     assert rep["first_group_lo"] <= 4 and rep["max_run"] >= 100
 
 
+def test_repeated_searches_reuse_buffers(orc):
+    # a plan keeps its traversal buffers from one search to the next: a second
+    # identical search (same buffer sizes, stale contents) answers the same,
+    # and searches with other d (other sizes: some blocks freed, some made)
+    # answer as a fresh plan does
+    s = synth.make_series(61, 5, 3000, 40, 3, 3, dtype="f64")
+    p = dict(w=40, mem_limit=1 << 30)
+
+    def key(res):
+        got, rep, rc = res
+        return (rc, [(m["a"], m["b"], m["dist_d"], m["dims"]) for m in got],
+                rep["i_stop"], rep["j_stop"], rep["n_cand"], rep["n_collisions"])
+
+    plan, _ = _plan(s, p, "f64", 12)
+    first = key(plan.search(3, 3, 0.05))
+    assert key(plan.search(3, 3, 0.05)) == first
+    for d in (2, 4, 3):
+        fresh, _ = _plan(s, p, "f64", 12)
+        want = key(fresh.search(d, 3, 0.05))
+        fresh.close()
+        assert key(plan.search(d, 3, 0.05)) == want, f"d={d}"
+    plan.close()
+
+
 def test_example_4_1_on_device(orc):
     # the paper's worked example (section 4, Example 4.1) with its index
     # injected: the device stops at the same step with the same TOP; below
