@@ -8,16 +8,18 @@
  * code, header or table with it, and it never receives a value computed on
  * the GPU.
  *
- * Everything here is plain, sequential, double precision, written to be
- * checked against the paper by eye: no blocking, no fusion, no reordering.
- * It is compiled with -ffp-contract=off, so every expression is evaluated as
- * written (no fused multiply-add).
+ * Everything here is plain double precision, written to be checked against
+ * the paper by eye: no blocking, no fusion, no reordering. It is compiled
+ * with -ffp-contract=off, so every expression is evaluated as written (no
+ * fused multiply-add).
  *
  * Parts:
  *   O1  exact top-k motifs by the definitions of section 3.1 (brute force);
+ *       o1fast.c gives the same answer for long inputs (a diagonal sweep
+ *       used as a filter, every kept pair recomputed by these definitions);
  *   O2  the LSH search of Algorithm 1 with the stopping rule of Algorithm 2 /
  *       Lemma 6.1, the tensored index of section 6.1 and the r heuristic of
- *       section 6.1, run sequentially with an unbounded set of verified pairs.
+ *       section 6.1, step after step with an unbounded set of verified pairs.
  *
  * Indices are 0-based: window a covers x[a .. a+w-1], a in [0, n-w].
  */
@@ -25,6 +27,11 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* The library is built twice from this file: sequentially (the checker the
+ * tests use) and with OpenMP (the CPU baseline the benchmark times, all host
+ * cores). The parallel loops only split independent work (dimensions, the
+ * distances of distinct pairs); every result is the same in both builds. */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw,        */
@@ -417,6 +424,12 @@ double orc_round_fmt(double v, int32_t fmt)
     return v < 0 ? -r : r;
 }
 
+/* orc_round_fmt over an array (the form the tests call on many values). */
+void orc_round_fmt_array(const double* v, int64_t count, int32_t fmt, double* out)
+{
+    for (int64_t q = 0; q < count; ++q) out[q] = orc_round_fmt(v[q], fmt);
+}
+
 /* Spacing of the format's values around v. */
 static double fmt_gap(double v, int32_t fmt)
 {
@@ -431,12 +444,13 @@ static double fmt_gap(double v, int32_t fmt)
 }
 
 /* Eq. drp with both a and the normal form rounded to the format (the normal
- * form first to float32): h = floor((Q(a) . Q(x) + b) / r). abs_sum gets
- * sum |Q(a_t) Q(x_t)|; amb bounds the change from inputs that another valid
- * evaluation may round differently: sum |Q(a_t)| * gap over samples whose
- * float32 value lies within 1e-5 (1 + |x_t|) of a rounding midpoint, plus, for
- * E4M3, |Q(a_t) Q(x_t)| whenever either factor is subnormal (below 2^-6),
- * which hardware may flush to zero. */
+ * form first to float32): h = floor((Q(a) . Q(x) + b) / r). Subnormal values
+ * of the format are kept (rounded on the format's smallest quantum), never
+ * flushed. abs_sum gets sum |Q(a_t) Q(x_t)|; amb bounds the change from
+ * inputs that another valid evaluation may round differently: sum
+ * |Q(a_t)| * gap over samples whose float32 value lies within
+ * 1e-5 (1 + |x_t|) of a rounding midpoint (a normal form evaluated in float32
+ * may land on either side of it). */
 int32_t orc_hash_value_lowp(const double* z, int32_t w, const double* R_col, int64_t R_stride,
                             double U, double r, int32_t fmt, double* pre_floor, double* abs_sum,
                             double* amb)
@@ -452,8 +466,6 @@ int32_t orc_hash_value_lowp(const double* z, int32_t w, const double* R_col, int
         double g = fmt_gap(zf, fmt);
         double to_mid = fabs(g / 2.0 - fabs(zf - zq));
         if (to_mid <= 1e-5 * (1.0 + fabs(zf))) ambs = ambs + fabs(rq) * g;
-        if (fmt == ORC_FMT_E4M3 && (fabs(rq) < 0.015625 || fabs(zq) < 0.015625))
-            ambs = ambs + fabs(term) + fabs(rq) * g;
     }
     double b = r * U;
     double u = (dot + b) / r;
@@ -499,6 +511,20 @@ void orc_hash_dim(const double* xf, int64_t n, int32_t w, const double* Rf /* [w
         }
     }
     free(z);
+}
+
+/* Hash every window of every dimension: bytes [D][n_s][C], x [D][n],
+ * R [D][w][C], U [D][C]. */
+void orc_hash_all(const double* x, int64_t n, int32_t D, int32_t w, const double* R, const double* U,
+                  int32_t C, double r, uint8_t* bytes)
+{
+    int64_t ns = n - w + 1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int32_t f = 0; f < D; ++f)
+        orc_hash_dim(x + (int64_t)f * n, n, w, R + (int64_t)f * w * C, U + (int64_t)f * C, C, r,
+                     bytes + (int64_t)f * ns * C, NULL, NULL);
 }
 
 /* Hash one window (f, a) at every column: the "one by one" form used to
@@ -630,6 +656,18 @@ static int pair_cmp(const void* p, const void* q)
     return 0;
 }
 
+/* growable list of the pairs one dimension contributes to a step */
+typedef struct {
+    pair_t* p;
+    int64_t cnt, cap;
+} pair_list;
+
+static void free_dim_pairs(pair_list* pl, int32_t D)
+{
+    for (int32_t f = 0; f < D; ++f) free(pl[f].p);
+    free(pl);
+}
+
 typedef struct {
     uint64_t key;
     int64_t a;
@@ -721,7 +759,8 @@ int32_t orc_lsh_search(const double* x, int64_t n, int32_t D, int32_t w, int32_t
     orc_tensor_shape(L, &m, &n_left, &n_right);
     int32_t NF = n_left + n_right;
 
-    keyed_t* keyed = (keyed_t*)malloc(sizeof(keyed_t) * (size_t)ns);
+    keyed_t* keyed = (keyed_t*)malloc(sizeof(keyed_t) * (size_t)ns * (size_t)D);
+    pair_list* dim_pairs = (pair_list*)calloc((size_t)D, sizeof(pair_list));
     int64_t pcap = 1 << 16, pcnt = 0;
     pair_t* pairs = (pair_t*)malloc(sizeof(pair_t) * (size_t)pcap);
     int64_t vcap = 1024, vcnt = 0;
@@ -744,36 +783,53 @@ int32_t orc_lsh_search(const double* x, int64_t n, int32_t D, int32_t w, int32_t
             int32_t j = J - 1;
             int64_t step = (int64_t)(K - i) * L + j;
             /* step 1: one-dimensional collisions of every dimension */
-            pcnt = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
             for (int32_t f = 0; f < D; ++f) {
+                keyed_t* kf = keyed + (int64_t)f * ns;
+                pair_list* pl = &dim_pairs[f];
+                pl->cnt = 0;
                 for (int64_t a = 0; a < ns; ++a) {
-                    keyed[a].key = orc_prefix(words, ns, NF, n_left, m, f, j, a, i);
-                    keyed[a].a = a;
+                    kf[a].key = orc_prefix(words, ns, NF, n_left, m, f, j, a, i);
+                    kf[a].a = a;
                 }
-                qsort(keyed, (size_t)ns, sizeof(keyed_t), keyed_cmp);
+                qsort(kf, (size_t)ns, sizeof(keyed_t), keyed_cmp);
                 int64_t s0 = 0;
                 while (s0 < ns) {
                     int64_t e = s0 + 1;
-                    while (e < ns && keyed[e].key == keyed[s0].key) ++e;
+                    while (e < ns && kf[e].key == kf[s0].key) ++e;
                     for (int64_t p = s0; p < e; ++p)
                         for (int64_t q = p + 1; q < e; ++q) {
-                            int64_t a = keyed[p].a, b = keyed[q].a;   /* a < b (sorted by a within a run) */
+                            int64_t a = kf[p].a, b = kf[q].a;   /* a < b (sorted by a within a run) */
                             if (trivial(a, b, w)) continue;
-                            if (pcnt == pcap) {
-                                pcap *= 2;
-                                pairs = (pair_t*)realloc(pairs, sizeof(pair_t) * (size_t)pcap);
+                            if (pl->cnt == pl->cap) {
+                                pl->cap = pl->cap ? 2 * pl->cap : 1024;
+                                pl->p = (pair_t*)realloc(pl->p, sizeof(pair_t) * (size_t)pl->cap);
                             }
-                            pairs[pcnt].a = a;
-                            pairs[pcnt].b = b;
-                            ++pcnt;
+                            pl->p[pl->cnt].a = a;
+                            pl->p[pl->cnt].b = b;
+                            ++pl->cnt;
                         }
                     s0 = e;
                 }
+            }
+            pcnt = 0;
+            for (int32_t f = 0; f < D; ++f) pcnt += dim_pairs[f].cnt;
+            if (pcnt > pcap) {
+                pcap = pcnt;
+                pairs = (pair_t*)realloc(pairs, sizeof(pair_t) * (size_t)pcap);
+            }
+            pcnt = 0;
+            for (int32_t f = 0; f < D; ++f) {
+                memcpy(pairs + pcnt, dim_pairs[f].p, sizeof(pair_t) * (size_t)dim_pairs[f].cnt);
+                pcnt += dim_pairs[f].cnt;
             }
             ctl->n_collisions += pcnt;
             /* W(a, b): multiplicity of each pair over the dimensions */
             qsort(pairs, (size_t)pcnt, sizeof(pair_t), pair_cmp);
             int added = 0;
+            const int64_t v_before = vcnt;
             int64_t s0 = 0;
             while (s0 < pcnt) {
                 int64_t e = s0 + 1;
@@ -789,7 +845,7 @@ int32_t orc_lsh_search(const double* x, int64_t n, int32_t D, int32_t w, int32_t
                         }
                     }
                     ctl->cand_count++;
-                    /* step 2: distance of each new pair, kept in the verified set */
+                    /* step 2: each new pair joins the verified set */
                     if (pairset_insert(&seen, (uint64_t)a * (uint64_t)ns + (uint64_t)b)) {
                         if (vcnt == vcap) {
                             vcap *= 2;
@@ -798,12 +854,17 @@ int32_t orc_lsh_search(const double* x, int64_t n, int32_t D, int32_t w, int32_t
                         orc_motif* v = &ver[vcnt++];
                         v->a = a;
                         v->b = b;
-                        orc_distd(x, n, D, w, a, b, d, &v->dist_d, &v->dist_max, v->dims, NULL);
                         added = 1;
                     }
                 }
                 s0 = e;
             }
+            /* ... with its distance (definition "d-dimensional distance") */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+            for (int64_t q = v_before; q < vcnt; ++q)
+                orc_distd(x, n, D, w, ver[q].a, ver[q].b, d, &ver[q].dist_d, &ver[q].dist_max, ver[q].dims, NULL);
             ctl->n_verified = vcnt;
             if (added) {
                 if (sorted_cap < vcnt) {
@@ -828,11 +889,13 @@ int32_t orc_lsh_search(const double* x, int64_t n, int32_t D, int32_t w, int32_t
                 ctl->J_stop = J;
                 memcpy(out, top, sizeof(orc_motif) * (size_t)k);
                 free(keyed); free(pairs); free(ver); free(sorted); free(top); free(seen.slot);
+                free_dim_pairs(dim_pairs, D);
                 return k;
             }
         }
     }
     free(keyed); free(pairs); free(ver); free(sorted); free(top); free(seen.slot);
+    free_dim_pairs(dim_pairs, D);
     /* no step stopped: the exact answer over all pairs */
     return orc_topk_exact(x, n, D, w, d, k, out);
 }

@@ -15,14 +15,17 @@ import numpy as np
 
 __all__ = [
     "build", "lib", "philox", "gauss", "uniform", "window_stats", "stats", "dist", "distd",
-    "topk_exact", "tensor_shape", "L_used", "draw_projections", "estimate_r", "hash_dim",
-    "hash_one", "pack", "prefix", "collision_prob", "fail_bound", "stop", "lsh_search",
-    "lsh_pipeline", "STOP_TENSOR", "STOP_LEMMA52", "STOP_TENSOR_LITERAL", "FLAT_REL", "round_fmt", "hash_dim_lowp", "FMT",
+    "topk_exact", "topk_exact_sweep", "tensor_shape", "L_used", "draw_projections", "estimate_r", "hash_dim",
+    "hash_one", "hash_all", "pack", "prefix", "collision_prob", "fail_bound", "stop", "lsh_search",
+    "lsh_pipeline", "STOP_TENSOR", "STOP_LEMMA52", "STOP_TENSOR_LITERAL", "FLAT_REL", "round_fmt", "round_fmt_array", "hash_dim_lowp", "FMT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "momenti_oracle.c")
+_SRCS = [os.path.join(_HERE, "momenti_oracle.c"), os.path.join(_HERE, "o1fast.c")]
 _LIB = os.path.join(_HERE, "_build", "libmomenti_oracle.so")
+# the same sources with OpenMP: the CPU baseline (all host cores) and the
+# golden-file sweeps; identical results, the sequential build is the checker
+_LIB_OMP = os.path.join(_HERE, "_build", "libmomenti_oracle_omp.so")
 
 STOP_TENSOR = 0
 STOP_LEMMA52 = 1
@@ -30,14 +33,29 @@ STOP_TENSOR_LITERAL = 2
 FLAT_REL = 1e-8
 
 
+def _stale(path: str) -> bool:
+    return not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(s) for s in _SRCS)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no FMA contraction)."""
+    """Compile the oracle with gcc (plain -O2, no FMA contraction), once
+    sequential (the checker) and once with OpenMP."""
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off",
-                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    flags = ["-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-fPIC"]
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or _stale(out):
+            tmp = out + ".tmp"
+            objs = []
+            for src in _SRCS:
+                # the sweep's fixed-width loops over diagonals vectorise at -O3
+                opt = "-O3" if src.endswith("o1fast.c") else "-O2"
+                obj = tmp + "." + os.path.basename(src) + ".o"
+                subprocess.check_call(["gcc", opt, *flags, *extra, "-c", "-o", obj, src])
+                objs.append(obj)
+            subprocess.check_call(["gcc", "-shared", *extra, "-o", tmp, *objs, "-lm"])
+            for obj in objs:
+                os.remove(obj)
+            os.replace(tmp, out)
     return _LIB
 
 
@@ -55,15 +73,16 @@ class LshCtl(C.Structure):
                 ("n_verified", C.c_int64), ("n_collisions", C.c_int64)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+def lib(omp: bool = False):
+    """The sequential oracle (omp=False, the checker) or its OpenMP build."""
+    if omp not in _libs:
+        path = _LIB_OMP if omp else _LIB
+        if _stale(path):
             build(force=True)
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         P = C.POINTER
         d, i32, i64, u64 = C.c_double, C.c_int32, C.c_int64, C.c_uint64
         vp = C.c_void_p
@@ -83,8 +102,11 @@ def lib():
             "orc_hash_value": (i32, [vp, i32, vp, i64, d, d, P(d), P(d)]),
             "orc_hash_dim": (None, [vp, i64, i32, vp, vp, i32, d, vp, vp, vp]),
             "orc_hash_one": (None, [vp, i32, i64, vp, vp, i32, d, vp, vp, vp]),
+            "orc_hash_all": (None, [vp, i64, i32, i32, vp, vp, i32, d, vp]),
+            "orc_topk_exact_sweep": (i32, [vp, i64, i32, i32, i32, i32, i64, vp, vp]),
             "orc_pack": (None, [vp, i64, i32, i32, i32, vp]),
             "orc_round_fmt": (d, [d, i32]),
+            "orc_round_fmt_array": (None, [vp, i64, i32, vp]),
             "orc_hash_value_lowp": (i32, [vp, i32, vp, i64, d, d, i32, P(d), P(d), P(d)]),
             "orc_hash_dim_lowp": (None, [vp, i64, i32, vp, vp, i32, d, i32, vp, vp, vp, vp]),
             "orc_prefix": (u64, [vp, i64, i32, i32, i32, i32, i32, i64, i32]),
@@ -101,8 +123,8 @@ def lib():
             fn.argtypes = args
         assert L.orc_motif_size() == C.sizeof(Motif)
         assert L.orc_ctl_size() == C.sizeof(LshCtl)
-        _lib = L
-    return _lib
+        _libs[omp] = L
+    return _libs[omp]
 
 
 def _p(a: np.ndarray):
@@ -183,6 +205,23 @@ def topk_exact(x, w: int, d: int, k: int) -> List[dict]:
     return _motifs(arr, got)
 
 
+def topk_exact_sweep(x, w: int, d: int, k: int, pool: int = 1 << 16, omp: bool = True,
+                     info: Optional[dict] = None) -> List[dict]:
+    """The answer of topk_exact by a diagonal sweep (o1fast.c), for long inputs."""
+    x = _f64(x)
+    D, n = x.shape
+    arr = (Motif * max(k, 1))()
+    inf = np.zeros(5)
+    got = lib(omp).orc_topk_exact_sweep(_p(x), n, D, w, d, k, pool, C.cast(arr, C.c_void_p), _p(inf))
+    if got == -1:
+        raise MemoryError("oracle sweep could not allocate")
+    if got < 0:
+        raise RuntimeError("oracle sweep could not certify its answer")
+    if info is not None:
+        info.update(theta=inf[0], eps=inf[1], pool=int(inf[2]), passes=int(inf[3]), max_err=inf[4])
+    return _motifs(arr, got)
+
+
 # ----------------------------------------------------------------------------- sections 3.2, 6.1
 def tensor_shape(L: int):
     m, nl, nr = C.c_int32(), C.c_int32(), C.c_int32()
@@ -232,6 +271,13 @@ def round_fmt(v: float, fmt: str) -> float:
     return lib().orc_round_fmt(v, FMT[fmt])
 
 
+def round_fmt_array(v, fmt: str) -> np.ndarray:
+    v = _f64(v).ravel()
+    out = np.empty_like(v)
+    lib().orc_round_fmt_array(_p(v), v.size, FMT[fmt], _p(out))
+    return out
+
+
 def hash_dim_lowp(xf, w: int, Rf, Uf, r: float, fmt: str):
     """Symbols, pre-floor values, sum |.| and ambiguity bound of the rounded-input projection."""
     xf, Rf, Uf = _f64(xf), _f64(Rf), _f64(Uf)
@@ -275,7 +321,8 @@ def stop(dist_max: float, r: float, d: int, i: int, J: int, K: int, L: int, rule
 
 # ----------------------------------------------------------------------------- Algorithm 1
 def lsh_search(x, w: int, d: int, k: int, delta: float, words, K: int, L: int, r: float,
-               rule: int = STOP_TENSOR, trace: bool = False, cand_cap: int = 2_000_000) -> Dict:
+               rule: int = STOP_TENSOR, trace: bool = False, cand_cap: int = 2_000_000,
+               omp: bool = False) -> Dict:
     x = _f64(x)
     D, n = x.shape
     words = np.ascontiguousarray(words, dtype=np.uint32)
@@ -294,8 +341,8 @@ def lsh_search(x, w: int, d: int, k: int, delta: float, words, K: int, L: int, r
         ctl.top_pairs = tpairs.ctypes.data_as(C.POINTER(C.c_int64))
         ctl.top_distmax = tdm.ctypes.data_as(C.POINTER(C.c_double))
     arr = (Motif * max(k, 1))()
-    got = lib().orc_lsh_search(_p(x), n, D, w, d, k, delta, _p(words), C.byref(ctl),
-                               C.cast(arr, C.c_void_p))
+    got = lib(omp).orc_lsh_search(_p(x), n, D, w, d, k, delta, _p(words), C.byref(ctl),
+                                  C.cast(arr, C.c_void_p))
     out = dict(motifs=_motifs(arr, got), i_stop=ctl.i_stop, J_stop=ctl.J_stop,
                n_verified=ctl.n_verified, n_collisions=ctl.n_collisions,
                fallback=(ctl.i_stop == 0))
@@ -308,15 +355,25 @@ def lsh_search(x, w: int, d: int, k: int, delta: float, words, K: int, L: int, r
     return out
 
 
+def hash_all(x, w: int, R, U, r: float, omp: bool = False) -> np.ndarray:
+    """Symbols [D][n_s][C] of every window of every dimension (Eq. drp)."""
+    x, R, U = _f64(x), _f64(R), _f64(U)
+    D, n = x.shape
+    Cc = R.shape[2]
+    by = np.zeros((D, n - w + 1, Cc), dtype=np.uint8)
+    lib(omp).orc_hash_all(_p(x), n, D, w, _p(R), _p(U), Cc, r, _p(by))
+    return by
+
+
 def lsh_pipeline(x, w: int, d: int, k: int, delta: float, seed: int, K: int = 8,
                  L_max: int = 200, mem_limit: Optional[int] = None, elem_bytes: int = 8,
                  r: Optional[float] = None, rule: int = STOP_TENSOR, trace: bool = False,
-                 r_scale: float = 1.0) -> Dict:
+                 r_scale: float = 1.0, omp: bool = False) -> Dict:
     """The whole method: L under the memory cap, draws, r, hashes, packing, search.
-    Without an explicit r, r is r_scale times the section 6.1 estimate."""
+    Without an explicit r, r is r_scale times the section 6.1 estimate. omp
+    runs the OpenMP build of the oracle (same results)."""
     x = _f64(x)
     D, n = x.shape
-    ns = n - w + 1
     L = L_max if mem_limit is None else L_used(n, D, w, L_max, elem_bytes, mem_limit)
     if L < 1:
         raise MemoryError("memory limit below the smallest index")
@@ -325,10 +382,8 @@ def lsh_pipeline(x, w: int, d: int, k: int, delta: float, seed: int, K: int = 8,
     Ccols = 4 * NF
     R, U = draw_projections(seed, D, w, Ccols)
     rr = estimate_r(x, w, seed) * (r_scale if r_scale > 0 else 1.0) if r is None else float(r)
-    by = np.zeros((D, ns, Ccols), dtype=np.uint8)
-    for f in range(D):
-        by[f], _, _ = hash_dim(x[f], w, R[f], U[f], rr, want_pre=False)
+    by = hash_all(x, w, R, U, rr, omp=omp)
     words = pack(by, NF, K)
-    res = lsh_search(x, w, d, k, delta, words, K, L, rr, rule=rule, trace=trace)
+    res = lsh_search(x, w, d, k, delta, words, K, L, rr, rule=rule, trace=trace, omp=omp)
     res.update(L=L, r=rr, words=words, R=R, U=U, NF=NF, m=m, n_left=nl)
     return res
