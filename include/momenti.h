@@ -88,7 +88,7 @@ typedef struct {
     int32_t proj;             /* MOMENTI_PROJ_* (default F32) */
     int32_t stop_rule;        /* MOMENTI_STOP_* (default TENSOR) */
     int32_t series_on_device; /* 1: the series pointer passed to momenti_hash is device memory */
-    int32_t pool_size;        /* verified pairs kept on the device; 0 = max(4096, 64 k) */
+    int32_t pool_size;        /* verified pairs kept on the device; 0 = max(4096, 128 k) */
     int32_t batch_reps;       /* repetitions traversed per launch; 0 = chosen from mem_limit */
     int32_t profile;          /* 1: time every kernel launch with HIP events (momenti_get_profile);
                                  2: time only the pair enumeration (the dominant kernel, least
@@ -141,6 +141,10 @@ typedef struct {
     int32_t budget_round;     /* MOMENTI_OK_PARTIAL: the highest round not traversed; else 0 */
     int32_t max_run;          /* most windows sharing a prefix in one segment, among the runs
                                  that crossed a 64-window boundary (enumerated in tiles) */
+    int32_t group_splits;     /* round groups whose verified records would have exceeded
+                                 mem_limit, traversed again one round at a time */
+    int32_t step_parts;       /* most parts one repetition was enumerated in (its candidates did
+                                 not fit in mem_limit at once); 0 when none was */
 } momenti_report;
 
 /* Fill *o with the defaults (K = 8, L = 200, r estimated, F32 projection,

@@ -728,6 +728,7 @@ static int pairset_insert(pairset* s, uint64_t code)   /* returns 1 when newly i
 typedef struct {
     /* inputs */
     int32_t K, L, rule;
+    int32_t no_fallback;     /* 1: when no step stops, return 0 motifs instead of the exact answer */
     double r;
     /* optional trace of every step (step s = (K - i) * L + (J - 1)) */
     int64_t* cand;           /* triples (s, a, b): the pairs with W >= d at step s */
@@ -897,6 +898,7 @@ int32_t orc_lsh_search(const double* x, int64_t n, int32_t D, int32_t w, int32_t
     free(keyed); free(pairs); free(ver); free(sorted); free(top); free(seen.slot);
     free_dim_pairs(dim_pairs, D);
     /* no step stopped: the exact answer over all pairs */
+    if (ctl->no_fallback) return 0;
     return orc_topk_exact(x, n, D, w, d, k, out);
 }
 

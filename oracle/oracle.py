@@ -65,7 +65,8 @@ class Motif(C.Structure):
 
 
 class LshCtl(C.Structure):
-    _fields_ = [("K", C.c_int32), ("L", C.c_int32), ("rule", C.c_int32), ("r", C.c_double),
+    _fields_ = [("K", C.c_int32), ("L", C.c_int32), ("rule", C.c_int32), ("no_fallback", C.c_int32),
+                ("r", C.c_double),
                 ("cand", C.POINTER(C.c_int64)), ("cand_cap", C.c_int64), ("cand_count", C.c_int64),
                 ("top_size", C.POINTER(C.c_int32)), ("top_pairs", C.POINTER(C.c_int64)),
                 ("top_distmax", C.POINTER(C.c_double)),
@@ -322,12 +323,15 @@ def stop(dist_max: float, r: float, d: int, i: int, J: int, K: int, L: int, rule
 # ----------------------------------------------------------------------------- Algorithm 1
 def lsh_search(x, w: int, d: int, k: int, delta: float, words, K: int, L: int, r: float,
                rule: int = STOP_TENSOR, trace: bool = False, cand_cap: int = 2_000_000,
-               omp: bool = False) -> Dict:
+               omp: bool = False, fallback: bool = True) -> Dict:
+    """Algorithm 1 over a given index. fallback=False skips the exact answer
+    when no step stops (motifs is then empty; the steps are still traced)."""
     x = _f64(x)
     D, n = x.shape
     words = np.ascontiguousarray(words, dtype=np.uint32)
     ctl = LshCtl()
     ctl.K, ctl.L, ctl.rule, ctl.r = K, L, rule, r
+    ctl.no_fallback = 0 if fallback else 1
     keep = []
     if trace:
         cand = np.zeros((cand_cap, 3), dtype=np.int64)

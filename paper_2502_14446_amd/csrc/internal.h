@@ -66,7 +66,8 @@ constexpr int kMaxSteps = 8 * 1024;
 struct ReplayCtl {
     uint32_t n_keep;
     int32_t K, L, s0, nsteps;
-    int32_t pad[3];
+    int32_t dropped;     // set by the filter when it left out a record (the pool was full)
+    int32_t pad[2];
     uint32_t step_count[kMaxSteps];
     uint32_t step_off[kMaxSteps + 1];
 };
@@ -104,7 +105,17 @@ struct StepGeom {
     int hashed;          // 1: sorted by a 24-bit hash of that prefix instead (equal prefixes
                          // stay adjacent; the rare equal hashes of different prefixes only
                          // add members to a run, and the exact test rejects them)
+    int part, nparts;    // emit only the candidates (a, b) with pair_part(a, b, nparts) == part
+                         // (nparts a power of two; 1 = all): a step whose candidates do not fit
+                         // in memory at once is enumerated in parts
 };
+// Part of a candidate pair when a step is enumerated in parts.
+__host__ __device__ inline uint32_t pair_part(uint32_t a, uint32_t b, int nparts)
+{
+    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15;
+    return h & (uint32_t)(nparts - 1);
+}
 // Sort keys of a segment element: the length-i_lo prefix, or its 24-bit hash.
 inline bool sort_keys_32(const StepGeom& g) { return g.hashed || g.i_lo <= 4; }
 inline int sort_passes(const StepGeom& g) { return g.hashed ? 3 : g.i_lo; }

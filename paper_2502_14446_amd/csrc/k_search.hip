@@ -610,6 +610,7 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
                                   int f, int j, int kt, int d, Cand* __restrict__ cand, uint32_t cap,
                                   Counters* __restrict__ cnt)
 {
+    if (g.nparts > 1 && pair_part(a, b, g.nparts) != (uint32_t)g.part) return;   // another part's pair
     const int l = j / g.m, r = j - l * g.m;
     const int nlev = g.i - g.i_lo + 2;
     // per level lv (round i_lo + lv), byte lv counts the dimensions colliding
@@ -1334,6 +1335,7 @@ __global__ __launch_bounds__(256) void k_filter(const VRec* __restrict__ rec, ui
     const bool full = ps->n_pool >= P;
     VRec thr;
     if (full) thr = pools[(int64_t)ps->cur * P + P - 1];
+    bool dropped = false;
     for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c < count; c += gridDim.x * 256) {
         const VRec& r = rec[c];
         const int st = rec_step(r, rc->K, rc->L, rc->s0);
@@ -1342,8 +1344,13 @@ __global__ __launch_bounds__(256) void k_filter(const VRec* __restrict__ rec, ui
             const uint32_t pos = atomicAdd(&rc->n_keep, 1u);
             keep[pos] = c;
             atomicAdd(&rc->step_count[st], 1u);
+        } else {
+            dropped = true;
         }
     }
+    // a record left out makes the pool a truncated one (what TOP may need
+    // could be missing while |TOP| < k): one atomic per wavefront
+    if (__ballot(dropped) && (threadIdx.x & 63) == 0) atomicOr(&rc->dropped, 1);
 }
 
 // Exclusive scan of the per-step counts (one block): offsets and cursors.
@@ -1410,7 +1417,7 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool(const VRec* __restrict__ 
     if (tid == 0) {
         s_np = ps->n_pool;
         s_cur = ps->cur;
-        s_trunc = ps->truncated;
+        s_trunc = ps->truncated | (rc->dropped ? 1 : 0);
         s_topn = ps->top_n;
     }
     __syncthreads();

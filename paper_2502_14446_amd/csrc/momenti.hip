@@ -180,29 +180,42 @@ struct Profiler {
 // Device blocks kept for reuse by the plans of one batch worker: a freed
 // block goes back here and is handed to the next request it fits (at most
 // twice the size asked for), so consecutive series stop paying for hipMalloc
-// and hipFree. Blocks are released when the worker ends.
+// and hipFree. Blocks are released when the worker ends. A plan is charged a
+// block's whole capacity, and the idle blocks count against its mem_limit
+// too: they are returned to the runtime before an allocation that would put
+// the plan's blocks plus the idle ones over the limit.
 struct BlockCache {
     std::vector<std::pair<size_t, void*>> idle;    // (capacity, block)
     std::vector<std::pair<void*, size_t>> owned;   // every block, with its capacity
+    size_t idle_bytes = 0;
     bool exact = false;                            // reuse only blocks of the requested size
-    void* take(size_t bytes)
+    void* take(size_t bytes, size_t room, size_t* cap_out)
     {
         int best = -1;
         for (int q = 0; q < (int)idle.size(); ++q) {
             const size_t c = idle[q].first;
             const bool fits = exact ? c == bytes : (c >= bytes && c <= 2 * bytes + (1u << 20));
-            if (fits && (best < 0 || c < idle[best].first)) best = q;
+            if (fits && c <= room && (best < 0 || c < idle[best].first)) best = q;
         }
         if (best < 0) return nullptr;
         void* b = idle[best].second;
+        *cap_out = idle[best].first;
+        idle_bytes -= idle[best].first;
         idle.erase(idle.begin() + best);
         return b;
+    }
+    size_t capacity(void* b) const
+    {
+        for (auto& o : owned)
+            if (o.first == b) return o.second;
+        return 0;
     }
     void give(void* b)
     {
         for (auto& o : owned)
             if (o.first == b) {
                 idle.push_back({o.second, b});
+                idle_bytes += o.second;
                 return;
             }
         (void)hipFree(b);   // not ours
@@ -227,6 +240,7 @@ struct BlockCache {
             (void)hipFree(b.second);
         }
         idle.clear();
+        idle_bytes = 0;
     }
     ~BlockCache()
     {
@@ -295,6 +309,14 @@ struct momenti_plan {
     int32_t tr_k = 0;
 };
 
+// Device block of at least `bytes` for the plan, within its mem_limit: the
+// plan is charged the block's capacity, and its blocks plus the cache's idle
+// ones stay within the limit.
+static void note_peak(momenti_plan* p)
+{
+    p->peak = std::max<uint64_t>(p->peak, p->bytes + (p->cache ? p->cache->idle_bytes : 0));
+}
+
 static int dalloc(momenti_plan* p, void** ptr, size_t bytes)
 {
     *ptr = nullptr;
@@ -302,11 +324,15 @@ static int dalloc(momenti_plan* p, void** ptr, size_t bytes)
     if (p->bytes + bytes > p->mem_limit)
         return fail(MOMENTI_E_NOMEM, "device budget exceeded: %llu + %zu > %llu bytes",
                     (unsigned long long)p->bytes, bytes, (unsigned long long)p->mem_limit);
-    if (p->cache && (*ptr = p->cache->take(bytes)) != nullptr) {
-        p->bytes += bytes;
-        p->peak = std::max(p->peak, p->bytes);
+    size_t capb = 0;
+    if (p->cache && (*ptr = p->cache->take(bytes, p->mem_limit - p->bytes, &capb)) != nullptr) {
+        p->bytes += capb;
+        note_peak(p);
         return MOMENTI_OK;
     }
+    // a fresh block: the idle ones go back to the runtime first if, with
+    // them, the plan would hold more than its limit
+    if (p->cache && p->bytes + p->cache->idle_bytes + bytes > p->mem_limit) p->cache->trim();
     hipError_t e = hipMalloc(ptr, bytes);
     if (e != hipSuccess && p->cache) {
         (void)hipGetLastError();
@@ -320,7 +346,7 @@ static int dalloc(momenti_plan* p, void** ptr, size_t bytes)
     }
     if (p->cache) p->cache->owned.push_back({*ptr, bytes});
     p->bytes += bytes;
-    p->peak = std::max(p->peak, p->bytes);
+    note_peak(p);
     return MOMENTI_OK;
 }
 
@@ -336,6 +362,8 @@ static int dalloc_t(momenti_plan* p, T** ptr, size_t bytes)
 static void dfree(momenti_plan* p, void* ptr, size_t bytes)
 {
     if (!ptr) return;
+    const size_t capb = p->cache->capacity(ptr);
+    if (capb) bytes = capb;
     if (p->cache != &p->own_cache || p->recycle)
         p->cache->give(ptr);   // the plan's stream keeps later uses in order
     else
@@ -971,6 +999,27 @@ static int alloc_pool(momenti_plan* p, int P, int k, int steps)
     return MOMENTI_OK;
 }
 
+// A pool of P pairs for a restart. When the budget is taken by the candidate
+// buffer and the store, they are halved to make room (a repetition whose
+// candidates then overflow them is enumerated in parts). Called only when
+// nothing is stored (at a restart or before the exact answer), so the store's
+// contents may go.
+static int grow_pool(momenti_plan* p, int P, int k, int steps)
+{
+    int rc;
+    while ((rc = alloc_pool(p, P, k, steps)) == MOMENTI_E_NOMEM && p->cap > (1u << 14)) {
+        const uint32_t half = p->cap / 2;
+        if ((rc = alloc_cand(p, half))) return rc;
+        dfree(p, p->store, (size_t)p->store_cap * sizeof(VRec));
+        dfree(p, p->keep, (size_t)p->store_cap * 8);
+        p->store = nullptr;
+        p->keep = nullptr;
+        p->store_cap = 0;
+        if ((rc = grow_store(p, half, 0))) return rc;
+    }
+    return rc;
+}
+
 // Replay `count` verified records at `rec` (tagged with round and repetition)
 // through the pool for steps [s0, s0 + nsteps); snapshots land in p->snaps.
 static int replay(momenti_plan* p, const VRec* rec, uint32_t count, uint32_t* keep, int k, int s0,
@@ -1170,7 +1219,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
                 ++R.pool_overflow;
                 P *= 2;
                 int e;
-                if ((e = alloc_pool(p, P, k, max_steps))) return e;
+                if ((e = grow_pool(p, P, k, max_steps))) return e;
                 return 2;
             }
             if (sn.top_n == k &&
@@ -1194,12 +1243,16 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         return 0;
     };
 
+    // Round groups still to traverse. A multi-round group keeps its verified
+    // records until its replay; when they would exceed the memory budget the
+    // group is split into single-round groups (each replayed batch by batch).
+    std::vector<std::pair<int, int>> todo(groups.begin(), groups.end());
 restart:
     HIP_OK(launch_pool_reset(st_pool(p), p->st));
     R.n_steps = 0;
     if (tracing && p->tr_count) *p->tr_count = 0;
-    for (const auto& gr : groups) {
-        const int i_hi = gr.first, i_lo = gr.second;
+    for (size_t gi = 0; gi < todo.size(); ++gi) {
+        const int i_hi = todo[gi].first, i_lo = todo[gi].second;
         const int s0 = (p->K - i_hi) * p->L;
         const int nsteps = (i_hi - i_lo + 1) * p->L;
         if (p->o.max_pairs > 0.0 && pairs_est[i_lo] > p->o.max_pairs) {
@@ -1237,13 +1290,14 @@ restart:
         // a single-round group replays each batch as soon as it is verified,
         // so that it stops at the first repetition where the rule holds
         const bool incremental = i_hi == i_lo;
-        for (int j0 = 0; j0 < p->L;) {
+        bool split = false;
+        for (int j0 = 0; j0 < p->L && !split;) {
             const int Bc = std::min(B, p->L - j0);
             StepGeom g;
             g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
             g.j0 = j0; g.Ds = Ds; g.nseg = Bc * Ds; g.i = i_hi; g.K = p->K; g.i_lo = i_lo;
             g.hashed = i_lo > 4;   // longer prefixes are grouped by a 24-bit hash (3 passes)
-            HIP_OK(launch_zero(p->status, 64, p->st));
+            g.part = 0; g.nparts = 1;
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
             const double kb = sort_keys_32(g) ? 4.0 : 8.0;
@@ -1261,80 +1315,139 @@ restart:
             HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + nq)), 0.0, [&] {
                 return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->st);
             }));
-            int enum_slot = -1, verify_slot = -1;
-            HIP_OK(timed(p, KI_ENUM, 0.0, 0.0, [&] {
-                return launch_enum(g, p->sb, buf, p->H, p->fps, p->fq, kt, d, p->w, p->cand, p->cap,
-                                   st_counters(p), p->coll_part, p->st);
-            }, &enum_slot));
-            HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
-                return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
-                                     p->D, p->w, d, p->mu, p->isig, p->vrec, p->st);
-            }, &verify_slot));
-            Counters cnt;
-            HIP_OK(hipMemcpyAsync(p->host_status, p->status, sizeof(Counters), hipMemcpyDeviceToHost, p->st));
-            HIP_OK(hipStreamSynchronize(p->st));
-            std::memcpy(&cnt, p->host_status, sizeof cnt);
-            {
-                // sizes known only now: the enumeration read every key once and
-                // every run member's index and fingerprint row once (pairs that
-                // pass the screen re-read 4 D index words: negligible);
-                // verification read 2 D w samples per candidate
-                const uint32_t nc = std::min(cnt.n_cand, p->cap);
-                prof_set(p, enum_slot, elems * kb + (double)cnt.n_memb * (4.0 + 4.0 * nw),
-                         (double)cnt.n_coll * (5.0 * nw + 1.0));
-                prof_set(p, verify_slot, (double)nc * (2.0 * p->D * p->w * elem_x + 32.0 * p->D + sizeof(VRec)),
-                         (double)nc * 6.0 * p->D * p->w);
-                prof_flush(p);
-            }
-            if (cnt.n_units > p->sb.ucap)   // cannot happen: ucap bounds the tile rows of a batch
-                return fail(MOMENTI_E_DEVICE, "%u tile rows queued, room for %u", cnt.n_units, p->sb.ucap);
-            if (cnt.n_cand > p->cap) {
-                // more candidates than room: fewer repetitions per launch, then a larger buffer
-                if (Bc > 1) {
-                    B = std::max(1, Bc / 2);
+            // Enumeration, verification and (single-round groups) replay, in
+            // g.nparts parts when one repetition's candidates do not fit in
+            // memory at once: merging a step's records into the pool part by
+            // part leaves the same pool (the best P of their union) and TOP.
+            bool redo = false;   // fewer repetitions per launch, or a larger buffer
+            for (g.part = 0; g.part < g.nparts && !redo && !split; ++g.part) {
+                HIP_OK(launch_zero(p->status, 64, p->st));
+                int enum_slot = -1, verify_slot = -1;
+                HIP_OK(timed(p, KI_ENUM, 0.0, 0.0, [&] {
+                    return launch_enum(g, p->sb, buf, p->H, p->fps, p->fq, kt, d, p->w, p->cand, p->cap,
+                                       st_counters(p), p->coll_part, p->st);
+                }, &enum_slot));
+                HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
+                    return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
+                                         p->D, p->w, d, p->mu, p->isig, p->vrec, p->st);
+                }, &verify_slot));
+                Counters cnt;
+                HIP_OK(hipMemcpyAsync(p->host_status, p->status, sizeof(Counters), hipMemcpyDeviceToHost, p->st));
+                HIP_OK(hipStreamSynchronize(p->st));
+                std::memcpy(&cnt, p->host_status, sizeof cnt);
+                {
+                    // sizes known only now: the enumeration read every key once and
+                    // every run member's index and fingerprint row once (pairs that
+                    // pass the screen re-read 4 D index words: negligible);
+                    // verification read 2 D w samples per candidate
+                    const uint32_t nc = std::min(cnt.n_cand, p->cap);
+                    prof_set(p, enum_slot, elems * kb + (double)cnt.n_memb * (4.0 + 4.0 * nw),
+                             (double)cnt.n_coll * (5.0 * nw + 1.0));
+                    prof_set(p, verify_slot, (double)nc * (2.0 * p->D * p->w * elem_x + 32.0 * p->D + sizeof(VRec)),
+                             (double)nc * 6.0 * p->D * p->w);
+                    prof_flush(p);
+                }
+                if (cnt.n_units > p->sb.ucap)   // cannot happen: ucap bounds the tile rows of a batch
+                    return fail(MOMENTI_E_DEVICE, "%u tile rows queued, room for %u", cnt.n_units, p->sb.ucap);
+                if (cnt.n_cand > p->cap) {
+                    // more candidates than room: fewer repetitions per launch, then a
+                    // larger buffer, then (a single-round group) parts of the step;
+                    // a multi-round group is split into single rounds
+                    if (Bc > 1) {
+                        B = std::max(1, Bc / 2);
+                        redo = true;
+                        break;
+                    }
+                    uint32_t need = p->cap;
+                    while (need < cnt.n_cand && need < (1u << 30)) need <<= 1;
+                    // a single-round group replays each batch from the store, whose
+                    // capacity must stay >= the candidate buffer's
+                    const bool grow_st = incremental && need > p->store_cap;
+                    const uint64_t extra = cand_bytes(need) - cand_bytes(p->cap) + (grow_st ? store_bytes(need) : 0);
+                    if (need >= cnt.n_cand && extra <= p->mem_limit - p->bytes) {
+                        const uint32_t old_cap = p->cap;
+                        rc = alloc_cand(p, need);
+                        if (rc == MOMENTI_OK && grow_st) rc = grow_store(p, need, 0);
+                        if (rc == MOMENTI_OK) {
+                            redo = true;
+                            break;
+                        }
+                        if (rc != MOMENTI_E_NOMEM) return rc;
+                        // could not allocate after all: back to a buffer the store covers
+                        if ((rc = alloc_cand(p, std::min(old_cap, std::max(p->store_cap, 1u << 14))))) return rc;
+                    }
+                    if (!incremental) {
+                        split = true;
+                        break;
+                    }
+                    int np = g.nparts;
+                    while ((uint64_t)np * p->cap < 2ull * cnt.n_cand * (uint64_t)g.nparts && np < (1 << 16)) np <<= 1;
+                    if (np == g.nparts)
+                        return fail(MOMENTI_E_NOMEM, "%u candidates in one step exceed mem_limit", cnt.n_cand);
+                    if (verbose)
+                        std::fprintf(stderr, "[momenti] step (%d, %d): %u candidates, enumerated in %d parts\n",
+                                     i_hi, j0 + 1, cnt.n_cand, np);
+                    g.nparts = np;
+                    R.step_parts = std::max(R.step_parts, np);
+                    g.part = -1;   // parts already merged into the pool merge again as no-ops
                     continue;
                 }
-                uint32_t need = p->cap;
-                while (need < cnt.n_cand && need < (1u << 30)) need <<= 1;
-                if (cand_bytes(need) > p->mem_limit - p->bytes + cand_bytes(p->cap))
-                    return fail(MOMENTI_E_NOMEM, "%u candidates in one step exceed mem_limit", cnt.n_cand);
-                if ((rc = alloc_cand(p, need))) return rc;
-                continue;
-            }
-            if (cnt.n_cand) {
-                if ((rc = grow_store(p, stored + cnt.n_cand, stored))) return rc;
-                HIP_OK(hipMemcpyAsync(p->store + stored, p->vrec, (size_t)cnt.n_cand * sizeof(VRec),
-                                      hipMemcpyDeviceToDevice, p->st));
-                stored += cnt.n_cand;
-            }
-            R.n_collisions += (int64_t)cnt.n_coll;
-            n_screened += cnt.n_screen;
-            max_run = std::max(max_run, cnt.max_run);
-            R.max_run = (int32_t)max_run;
-            R.n_cand += cnt.n_cand;
-            R.n_verified += cnt.n_cand;
-            if (tracing && p->tr_cand && cnt.n_cand) {
-                hcand.resize(cnt.n_cand);
-                HIP_OK(copy_sync(p, hcand.data(), p->cand, cnt.n_cand * sizeof(Cand), hipMemcpyDeviceToHost));
-                for (const Cand& c : hcand) {
-                    const int64_t s = (int64_t)(p->K - (int)c.pad) * p->L + c.j;
-                    if (*p->tr_count < p->tr_cap) {
-                        p->tr_cand[3 * *p->tr_count + 0] = s;
-                        p->tr_cand[3 * *p->tr_count + 1] = c.a;
-                        p->tr_cand[3 * *p->tr_count + 2] = c.b;
+                if (cnt.n_cand) {
+                    if (!incremental && (rc = grow_store(p, stored + cnt.n_cand, stored))) {
+                        if (rc != MOMENTI_E_NOMEM) return rc;
+                        split = true;   // the group's records would exceed the budget
+                        break;
                     }
-                    ++*p->tr_count;
+                    HIP_OK(hipMemcpyAsync(p->store + stored, p->vrec, (size_t)cnt.n_cand * sizeof(VRec),
+                                          hipMemcpyDeviceToDevice, p->st));
+                    stored += cnt.n_cand;
+                }
+                if (g.part == 0) {
+                    R.n_collisions += (int64_t)cnt.n_coll;
+                    n_screened += cnt.n_screen;
+                }
+                max_run = std::max(max_run, cnt.max_run);
+                R.max_run = (int32_t)max_run;
+                R.n_cand += cnt.n_cand;
+                R.n_verified += cnt.n_cand;
+                if (tracing && p->tr_cand && cnt.n_cand) {
+                    hcand.resize(cnt.n_cand);
+                    HIP_OK(copy_sync(p, hcand.data(), p->cand, cnt.n_cand * sizeof(Cand), hipMemcpyDeviceToHost));
+                    for (const Cand& c : hcand) {
+                        const int64_t s = (int64_t)(p->K - (int)c.pad) * p->L + c.j;
+                        if (*p->tr_count < p->tr_cap) {
+                            p->tr_cand[3 * *p->tr_count + 0] = s;
+                            p->tr_cand[3 * *p->tr_count + 1] = c.a;
+                            p->tr_cand[3 * *p->tr_count + 2] = c.b;
+                        }
+                        ++*p->tr_count;
+                    }
+                }
+                if (incremental) {
+                    if ((rc = replay(p, p->store, stored, p->keep, k, s0 + j0, Bc))) return rc;
+                    stored = 0;   // the pool holds what the next steps need
                 }
             }
+            if (redo || split) continue;
             if (incremental) {
-                if ((rc = replay(p, p->store, stored, p->keep, k, s0 + j0, Bc))) return rc;
-                stored = 0;   // the pool holds what the next steps need
+                // the snapshots of the last part's replay are those of the whole batch
                 const int cs = check_steps(s0 + j0, Bc);
                 if (cs < 0) return cs;
                 if (cs == 1) return MOMENTI_OK;
                 if (cs == 2) goto restart;
             }
             j0 += Bc;
+        }
+        if (split) {
+            // traverse the group's rounds one by one (the pool is unchanged:
+            // none of this group's records has been replayed yet)
+            if (verbose)
+                std::fprintf(stderr, "[momenti] rounds %d..%d split into single rounds (memory budget)\n", i_hi, i_lo);
+            todo.erase(todo.begin() + (std::ptrdiff_t)gi);
+            for (int i = i_lo; i <= i_hi; ++i) todo.insert(todo.begin() + (std::ptrdiff_t)gi, {i, i});
+            ++R.group_splits;
+            --gi;
+            continue;
         }
         // multi-round group: replay its verified records in step order now
         if (!incremental) {
@@ -1404,7 +1517,7 @@ static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int
             return MOMENTI_OK;
         }
         ++rep->pool_overflow;
-        if ((rc = alloc_pool(p, p->P * 2, k, p->snap_steps))) return rc;
+        if ((rc = grow_pool(p, p->P * 2, k, p->snap_steps))) return rc;
     }
 }
 

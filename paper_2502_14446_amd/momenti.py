@@ -61,7 +61,8 @@ class Report(C.Structure):
                 ("n_collisions", C.c_int64), ("n_cand", C.c_int64), ("n_verified", C.c_int64),
                 ("peak_bytes", C.c_uint64), ("fallback", C.c_int32), ("pool_overflow", C.c_int32),
                 ("batch_reps", C.c_int32), ("first_group_lo", C.c_int32),
-                ("budget_round", C.c_int32), ("max_run", C.c_int32)]
+                ("budget_round", C.c_int32), ("max_run", C.c_int32),
+                ("group_splits", C.c_int32), ("step_parts", C.c_int32)]
 
 
 class MomentiError(RuntimeError):

@@ -598,11 +598,18 @@ def test_memory_cap_reduces_repetitions(orc):
 
 
 # --------------------------------------------------------------------------- low precision
-def _lowp_band(w, pre, sab, amb, r):
+def _lowp_band(w, pre, sab, amb, r, proj="bf16"):
     # FP32 accumulation of exact products, the FP32 epilogue (1/r, U, fma), and
-    # inputs whose float32 value sits at a rounding midpoint of the format
+    # inputs whose float32 value sits at a rounding midpoint of the format.
+    # The FP8 matrix instruction sums its 64 products less precisely than FP32
+    # additions would: measured on gfx950 up to 536 2^-24 of the sum of their
+    # magnitudes (512 x 1024 random N(0,1) dot products, e4m3 inputs); the band
+    # takes 1024 2^-24 of sum |Q(a) Q(x)| for it.
     u = 2.0 ** -24
-    return 2.0 * u * ((w + 4) * sab / r + 3.0 * (np.abs(pre) + 1.0)) + amb / r
+    band = 2.0 * u * ((w + 4) * sab / r + 3.0 * (np.abs(pre) + 1.0)) + amb / r
+    if proj == "fp8":
+        band = band + 1024.0 * u * sab / r
+    return band
 
 
 @pytest.mark.parametrize("proj", ["bf16", "fp8"])
@@ -621,7 +628,7 @@ def test_lowp_hash_matches_rounded_input_emulation(orc, proj):
         by.append(b_); pre.append(p_); sab.append(s_); amb.append(a_)
     by, pre, sab, amb = map(np.array, (by, pre, sab, amb))
     gsym = _unpack(plan.hashes(), 8)
-    bad_out, bad_in, near, diff = _check_symbols(gsym, by, pre, _lowp_band(50, pre, sab, amb, r), 8)
+    bad_out, bad_in, near, diff = _check_symbols(gsym, by, pre, _lowp_band(50, pre, sab, amb, r, proj), 8)
     print(f"{proj}: symbols={by.size} band={near} differing={diff}")
     assert bad_out == 0 and bad_in == 0
     # against the FP64 hash: the flip rate the narrow format costs, as the
