@@ -48,7 +48,7 @@ extern "C" {
 #define MOMENTI_E_NOMEM (-2)     /* mem_limit too small for the smallest index, or a device allocation failed */
 #define MOMENTI_E_DEVICE (-3)    /* a HIP runtime call failed */
 #define MOMENTI_E_STATE (-4)     /* call out of order (e.g. search before hash) */
-#define MOMENTI_E_UNSUPPORTED (-5) /* exact fallback needed but the input is too large for it */
+#define MOMENTI_E_UNSUPPORTED (-5) /* an input size beyond what the index layout can address */
 
 /* Series element type. */
 #define MOMENTI_F64 0
@@ -184,7 +184,9 @@ int momenti_hash(momenti_plan* p, const void* series);
  * Returns MOMENTI_OK, MOMENTI_OK_FALLBACK (exact answer, no step stopped),
  * MOMENTI_OK_PARTIAL (opts.max_pairs reached: TOP so far, possibly fewer than
  * k pairs), or E_ARG, E_STATE (momenti_hash not called), E_NOMEM, E_DEVICE,
- * E_UNSUPPORTED (the exact fallback is limited to n - w + 1 <= 65536 windows). */
+ * E_UNSUPPORTED (more windows per batch of segments than 32-bit positions hold). The exact
+ * answer of the fallback covers every window count: short series stream every pair through
+ * the verifier, longer ones sweep the diagonals of the pair matrix. */
 int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
                    int32_t* n_out, momenti_report* rep);
 

@@ -170,5 +170,27 @@ hipError_t launch_pool_reset(PoolState* ps, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_allpairs(int64_t ns, int w, int64_t row_lo, int64_t row_hi, int64_t base,
                            Cand* cand, Counters* cnt, hipStream_t s);
+// Set the candidate count (e.g. to the buffer's capacity after an overflow,
+// so that the buffered candidates can be verified).
+hipError_t launch_set_count(Counters* cnt, uint32_t v, hipStream_t s);
+
+// ---- exact answer over every pair (k_exact.hip) ----
+// One launch of the diagonal sweep: work items [item_lo, item_hi) of a grid
+// of groups of G adjacent diagonals (the first at s_lo, group gr at
+// s_lo + gr G) times chunks of Lc pairs along them (item = gr chunks + c).
+// Pairs whose d smallest per-dimension distances sum below theta are
+// appended to the candidates (a, b, 0, 0) for verification.
+struct SweepArgs {
+    int64_t n, ns;
+    int64_t s_lo;          // first diagonal offset of group 0
+    int64_t item_lo, item_hi;
+    int64_t chunks;        // chunks per group
+    int D, Dp, G, DL;      // dimensions, lanes per diagonal, diagonals per wave, dimensions per lane
+    int w, d, Lc;
+    int part, nparts;      // emit only pair_part(a, b, nparts) == part (nparts 1: all)
+    double theta, th2, low2;   // theta, theta^2, (theta / d)^2
+};
+hipError_t launch_sweep(const void* x, int dtype, const double* mu, const double* isig, const SweepArgs& g,
+                        Cand* cand, uint32_t cap, Counters* cnt, hipStream_t s);
 
 }  // namespace mm

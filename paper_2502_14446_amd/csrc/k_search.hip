@@ -1655,6 +1655,12 @@ __global__ void k_set_count(Counters* cnt, uint32_t v)
     cnt->n_cand = v;
 }
 
+hipError_t launch_set_count(Counters* cnt, uint32_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, cnt, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_allpairs(int64_t ns, int w, int64_t row_lo, int64_t row_hi, int64_t base,
                            Cand* cand, Counters* cnt, hipStream_t s)
 {

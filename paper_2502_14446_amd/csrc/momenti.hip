@@ -153,10 +153,10 @@ static uint8_t to_e4m3_bits(double v)
 // Optional per-kernel timing with HIP events recorded on the plan's stream
 // around each launch; folded into totals whenever the host synchronises.
 enum KernelId { KI_STATS, KI_RSAMPLE, KI_PROJ, KI_HIST, KI_SCAN, KI_SCATTER, KI_PROBE, KI_FPTABLE, KI_ENUM,
-                KI_VERIFY, KI_FILTER, KI_POOL, KI_ALLPAIRS, KI_COUNT };
+                KI_VERIFY, KI_FILTER, KI_POOL, KI_ALLPAIRS, KI_SWEEP, KI_COUNT };
 static const char* const kKernelNames[KI_COUNT] = {
     "stats", "rsample", "proj", "sort_hist", "sort_scan", "sort_scatter", "probe", "fptable", "enum",
-    "verify", "pool_filter", "pool", "allpairs"};
+    "verify", "pool_filter", "pool", "allpairs", "sweep"};
 
 struct KTotal {
     int64_t launches = 0;
@@ -1467,14 +1467,17 @@ restart:
 }
 
 // Algorithm 1, last line: no step stopped, so answer with the exact top-k
-// over every non-trivial pair (same verifier and pool, all pairs streamed as
-// one step).
+// over every non-trivial pair. Short series stream every pair through the
+// verifier and the pool as one step; longer ones sweep the diagonals of the
+// pair matrix (exact_sweep).
+constexpr int64_t kAllPairsMax = 4096;
+
+static int exact_sweep(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out, momenti_report* rep);
+
 static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out,
                           momenti_report* rep)
 {
-    if (p->ns > 65536)
-        return fail(MOMENTI_E_UNSUPPORTED, "exact fallback limited to 65536 windows (n_s=%lld)",
-                    (long long)p->ns);
+    if (p->ns > kAllPairsMax) return exact_sweep(p, d, k, out, n_out, rep);
     const int64_t h = p->w / 2;
     const int64_t M = p->ns - h - 1;
     auto off = [M](int64_t a) { int64_t aa = std::min(a, std::max<int64_t>(M, 0)); return aa * M - aa * (aa - 1) / 2; };
@@ -1519,6 +1522,165 @@ static int exact_fallback(momenti_plan* p, int d, int k, momenti_motif* out, int
         ++rep->pool_overflow;
         if ((rc = grow_pool(p, p->P * 2, k, p->snap_steps))) return rc;
     }
+}
+
+// The exact answer by the diagonal sweep of k_exact.hip. The pool keeps the
+// pairs the traversal verified; the sweep adds every pair whose d smallest
+// per-dimension distances, as the sweep evaluates them, sum below the cut
+// theta (each verified by k_verify). A pair left out has a sweep value >=
+// theta, hence an exact dist_d >= theta - eps (eps bounds the sweep's
+// rounding). Greedy over all pairs decides each pick from earlier pairs only,
+// so when TOP holds k picks and the k-th is below theta - eps, TOP is the
+// greedy choice over every pair; otherwise the cut widens and the sweep
+// repeats. The cut starts at TOP's k-th distance (plus margin) and follows it
+// down as TOP improves.
+static int exact_sweep(momenti_plan* p, int d, int k, momenti_motif* out, int32_t* n_out, momenti_report* rep)
+{
+    int rc;
+    if ((rc = grow_store(p, p->cap, 0))) return rc;   // room to replay a whole candidate buffer
+    const int DL = p->D > 64 ? 2 : 1;
+    int Dp = 1;
+    while (Dp < std::min(p->D, 64)) Dp <<= 1;
+    if (DL == 2) Dp = 64;
+    const int G = 64 / Dp;
+    const int Lc = std::max(2048, 8 * p->w);
+    const int64_t first = p->w / 2 + 1;   // smallest diagonal offset with 2 s > w
+    if (first >= p->ns) {
+        *n_out = 0;
+        return MOMENTI_OK;
+    }
+    const int64_t groups = (p->ns - first + G - 1) / G;
+    const int64_t chunks = (p->ns - first + Lc - 1) / Lc;
+    const int64_t items = groups * chunks;
+    const double eps = (double)d * std::sqrt(1e-6 * (double)p->w);
+    const double elem_x = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
+
+    auto read_top = [&](int* topn, double* kth) -> int {
+        PoolState ps;
+        HIP_OK(hipMemcpyAsync(p->host_status + 64, st_pool(p), sizeof ps, hipMemcpyDeviceToHost, p->st));
+        HIP_OK(hipStreamSynchronize(p->st));
+        std::memcpy(&ps, p->host_status + 64, sizeof ps);
+        *topn = ps.top_n;
+        *kth = INFINITY;
+        if (ps.top_n >= k) {
+            VRec v;
+            HIP_OK(copy_sync(p, &v, p->top + (k - 1), sizeof v, hipMemcpyDeviceToHost));
+            *kth = v.dist_d;
+        }
+        return MOMENTI_OK;
+    };
+    int topn = 0;
+    double kth = INFINITY;
+    if ((rc = read_top(&topn, &kth))) return rc;
+    double theta = topn >= k ? kth + 2.0 * eps : INFINITY;
+    std::vector<double> buf;
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        double theta_min = INFINITY;
+        bool restart = false;
+        std::vector<std::pair<int64_t, int64_t>> work;   // item ranges still to sweep (taken from the back)
+        const int64_t per = std::max<int64_t>(1, (items + 31) / 32);
+        for (int64_t lo = ((items + per - 1) / per - 1) * per; lo >= 0; lo -= per)
+            work.push_back({lo, std::min(items, lo + per)});
+        while (!work.empty() && !restart) {
+            const auto range = work.back();
+            work.pop_back();
+            int nparts = 1;
+            for (int part = 0; part < nparts; ++part) {
+                SweepArgs g;
+                g.n = p->n; g.ns = p->ns; g.s_lo = first; g.item_lo = range.first; g.item_hi = range.second;
+                g.chunks = chunks; g.D = p->D; g.Dp = Dp; g.G = G; g.DL = DL; g.w = p->w; g.d = d; g.Lc = Lc;
+                g.part = part; g.nparts = nparts;
+                g.theta = theta;
+                g.th2 = std::isinf(theta) ? INFINITY : theta * theta;
+                g.low2 = std::isinf(theta) ? INFINITY : (theta / d) * (theta / d);
+                HIP_OK(launch_zero(p->status, 64, p->st));
+                const double pairs = (double)(range.second - range.first) * G * Lc;
+                HIP_OK(timed(p, KI_SWEEP, pairs * p->D * 4.0 * elem_x, pairs * p->D * 12.0, [&] {
+                    return launch_sweep(p->series, p->dtype, p->mu, p->isig, g, p->cand, p->cap, st_counters(p), p->st);
+                }));
+                HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
+                    return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
+                                         p->D, p->w, d, p->mu, p->isig, p->vrec, p->st);
+                }));
+                Counters cnt;
+                HIP_OK(hipMemcpyAsync(p->host_status, p->status, sizeof(Counters), hipMemcpyDeviceToHost, p->st));
+                HIP_OK(hipStreamSynchronize(p->st));
+                std::memcpy(&cnt, p->host_status, sizeof cnt);
+                prof_flush(p);
+                if (cnt.n_cand > p->cap) {
+                    // too many pairs below the cut in this range: while there is no
+                    // cut yet (TOP short of k picks), take the distance that about
+                    // cap / 8 of the buffered pairs reach; else sweep halves of the
+                    // range; a single item is split into parts of its pairs
+                    if (std::isinf(theta)) {
+                        // verify the candidates the buffer holds (the verifier skips
+                        // an overflowed buffer), then read their distances
+                        HIP_OK(launch_set_count(st_counters(p), p->cap, p->st));
+                        HIP_OK(launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns,
+                                             p->D, p->w, d, p->mu, p->isig, p->vrec, p->st));
+                        buf.resize(p->cap);
+                        std::vector<VRec> vr(p->cap);
+                        HIP_OK(copy_sync(p, vr.data(), p->vrec, (size_t)p->cap * sizeof(VRec), hipMemcpyDeviceToHost));
+                        for (uint32_t q = 0; q < p->cap; ++q) buf[q] = vr[q].dist_d;
+                        std::nth_element(buf.begin(), buf.begin() + p->cap / 8, buf.end());
+                        const double th = buf[p->cap / 8] + 2.0 * eps;
+                        if (th < theta) {
+                            theta = th;
+                            nparts = 0;   // ends the part loop; the range is swept again
+                            work.push_back(range);
+                            break;
+                        }
+                    }
+                    if (range.second - range.first > 1) {
+                        const int64_t mid = range.first + (range.second - range.first) / 2;
+                        work.push_back({mid, range.second});
+                        work.push_back({range.first, mid});
+                        nparts = 0;
+                        break;
+                    }
+                    int np = nparts;
+                    while ((uint64_t)np * p->cap < 2ull * cnt.n_cand * (uint64_t)nparts && np < (1 << 20)) np <<= 1;
+                    if (np == nparts)
+                        return fail(MOMENTI_E_NOMEM, "exact answer: %u pairs below the cut in one part", cnt.n_cand);
+                    nparts = np;
+                    part = -1;   // parts already merged into the pool merge again as no-ops
+                    continue;
+                }
+                theta_min = std::min(theta_min, theta);
+                rep->n_verified += cnt.n_cand;
+                if (cnt.n_cand == 0) continue;
+                if ((rc = replay(p, p->vrec, cnt.n_cand, p->keep, k, p->K * p->L, 1))) return rc;
+                const Snap sn = p->host_snaps[0];
+                if (sn.top_n < k && sn.truncated) {
+                    // the pool dropped pairs TOP may need: larger pool, sweep again
+                    ++rep->pool_overflow;
+                    if ((rc = grow_pool(p, p->P * 2, k, p->snap_steps))) return rc;
+                    HIP_OK(launch_pool_reset(st_pool(p), p->st));
+                    restart = true;
+                    break;
+                }
+                if ((rc = read_top(&topn, &kth))) return rc;
+                if (topn >= k) theta = std::min(theta, kth + 2.0 * eps);
+            }
+        }
+        if (restart) {   // the pool was emptied: the same cut, every range again
+            topn = 0;
+            kth = INFINITY;
+            continue;
+        }
+        if ((rc = read_top(&topn, &kth))) return rc;
+        if (std::isinf(theta_min) || (topn >= k && kth < theta_min - eps)) {
+            const int got = std::min(topn, k);
+            std::vector<VRec> tv(std::max(got, 1));
+            if (got) HIP_OK(copy_sync(p, tv.data(), p->top, (size_t)got * sizeof(VRec), hipMemcpyDeviceToHost));
+            to_motifs(tv, got, out);
+            *n_out = got;
+            return MOMENTI_OK;
+        }
+        // not certified: widen the cut past TOP's k-th pick (or double it)
+        theta = topn >= k ? kth + 4.0 * eps : 2.0 * theta_min;
+    }
+    return fail(MOMENTI_E_DEVICE, "exact answer: the sweep did not certify its result");
 }
 
 extern "C" int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_t w,

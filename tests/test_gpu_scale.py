@@ -344,3 +344,40 @@ def test_bench_workload_answer_against_the_exact_golden(orc):
             W = sum(orc.prefix(words, prm["L"], f, J - 1, a, i) == orc.prefix(words, prm["L"], f, J - 1, b, i)
                     for f in range(s.D))
             assert W < p["d"], f"device index: ({a}, {b}) collides in {W} dimensions at ({i}, {J})"
+
+
+# --------------------------------------------------------------------------- exact answer on the device
+@pytest.mark.parametrize("case", ["no_top", "partial_top", "flat", "dims96"])
+def test_exact_fallback_sweep_equals_the_oracle(orc, case):
+    # no step stops (LEMMA52 with a vanishing delta), so the answer is the
+    # exact top-k over every pair, which the device computes by sweeping the
+    # diagonals of the pair matrix past 4096 windows; the oracle's own sweep
+    # (itself pinned to the brute force) gives the reference
+    if case == "no_top":
+        # 70 000 windows and a tiny r: nothing collides, TOP is empty, the cut
+        # starts from the first candidates the sweep buffers
+        s = synth.make_series(95, 4, 70_050, 50, 3, 2, dtype="f32")
+        w, d, k, K, L, rs = 50, 2, 3, 8, 2, 0.02
+    elif case == "partial_top":
+        # the traversal's TOP (rounds 2 and 1 of two repetitions) sets the cut
+        s = synth.make_series(96, 4, 70_050, 50, 3, 2, dtype="f32")
+        w, d, k, K, L, rs = 50, 2, 3, 2, 2, 1.0
+    elif case == "flat":
+        # flat stretches (normal forms of zeros), each in one dimension only, so
+        # that no pair is at distance 0 in d = 2 dimensions (which would stop)
+        s = synth.make_series(97, 3, 20_000, 40, 2, 2, dtype="f32")
+        s.x[0, 5000:5400] = 1.25
+        s.x[1, 12000:12300] = 7.0
+        s.x[2, 15000:15200] = -3.0
+        w, d, k, K, L, rs = 40, 2, 4, 8, 2, 0.02
+    else:
+        # D = 96: two dimensions per lane in the sweep
+        s = synth.make_series(98, 96, 6000, 40, 2, 10, noise=0.02, dtype="f32")
+        w, d, k, K, L, rs = 40, 8, 2, 8, 2, 0.02
+    p = dict(w=w, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, "f32", 5, K=K, L=L, stop="lemma52", r_scale=rs)
+    got, rep, rc = plan.search(d, k, 1e-300)
+    plan.close()
+    assert rc == mm.OK_FALLBACK and rep["fallback"] == 1
+    want = orc.topk_exact_sweep(s.x, w, d, k)
+    _compare_motifs(got, want)
