@@ -4,7 +4,13 @@ One step = index construction (window statistics, r estimate, MFMA projection
 and packing) plus the full traversal (prefix sorts, enumeration, verification,
 pool, stopping rule) over the resident synthetic series. Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload rw8_1m]
+The default workload is rwsin32_4m (D = 32, n = 4 194 304, w = 1000, d = 8,
+k = 10): `value` is its time to solution with the BF16 projection, next to
+the FP32 projection timed in the same process, the hash-flip rate and the
+distance error against the FP64 oracle, and the oracle's own search on the
+host cores.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload rwsin32_4m|rw8_1m|...]
 """
 from __future__ import annotations
 
@@ -15,6 +21,8 @@ import os
 import re
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -86,19 +94,56 @@ def calibrate_copy(nbytes: int, reps: int) -> int:
     return 0
 
 
-def cpu_baseline(series, p, seed: int, n_cpu: int, r_scale: float) -> dict:
+def cpu_baseline(series, p, seed: int, r: float) -> dict:
+    """The oracle's LSH search (O2, OpenMP build on every host core) on a
+    bounded sample of the workload: the stretches of 3 w points around each
+    planted window, joined in time order (every planted motif is in it, so
+    the search stops on the rule as the device's does), with the device run's
+    d, k, delta, K, L, seed and r."""
     import oracle
-    x = series.x[:, :n_cpu]
+    w = p["w"]
+    segs = sorted(q for m in series.motifs for q in (m.p1, m.p2))
+    lo = [max(0, q - w) for q in segs]
+    x = np.concatenate([series.x[:, a: min(series.n, a + 3 * w)] for a in lo], axis=1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or (os.cpu_count() or 1)
     t0 = time.perf_counter()
-    res = oracle.lsh_pipeline(x, p["w"], p["d"], p["k"], p["delta"], seed,
-                              mem_limit=p["mem_limit"], elem_bytes=4, r_scale=r_scale)
+    res = oracle.lsh_pipeline(x, w, p["d"], p["k"], p["delta"], seed, mem_limit=p["mem_limit"],
+                              elem_bytes=4 if series.dtype == "f32" else 8, r=r, omp=True)
     dt = time.perf_counter() - t0
-    ns = n_cpu - p["w"] + 1
-    return {"value": ns * p["D"] / dt, "unit": "subseq·dims/s", "cores": 1, "kind": "oracle",
-            "sample": (f"first {n_cpu} points of the same series, same d/k/delta/K/L/seed/r; the "
-                       f"oracle's complete search (hash + traversal"
-                       f"{' + exact fallback' if res.get('fallback') else ''}) took {dt:.2f} s, "
-                       f"stop ({res['i_stop']},{res['J_stop']}), single-threaded C")}
+    ns = x.shape[1] - w + 1
+    return {"value": ns * series.D / dt, "unit": "subseq·dims/s", "cores": threads, "kind": "oracle",
+            "sample": (f"the oracle's whole search (index + traversal, OpenMP over dimensions) on "
+                       f"{x.shape[1]} points: the {3 * w}-point stretches around the {len(segs)} planted "
+                       f"windows joined in time order, same d/k/delta/K/L/seed/r; took {dt:.1f} s, "
+                       f"stop ({res['i_stop']},{res['J_stop']})"
+                       f"{', exact fallback' if res.get('fallback') else ''}"),
+            "seconds": dt, "stop": [res["i_stop"], res["J_stop"]]}
+
+
+def flip_rate(plan, series, p, seed: int, r: float, cells: int = 4096) -> dict:
+    """Hash symbols of sampled windows against the FP64 oracle's (Eq. drp):
+    the fraction that differ, on runs of 16 consecutive windows at random
+    places of every dimension."""
+    import oracle
+    rng = np.random.default_rng(0xF11B)
+    w, D = p["w"], series.D
+    ns = series.n - w + 1
+    prm = plan.params()
+    NF, K = prm["NF"], 8
+    R, U = oracle.draw_projections(seed, D, w, 4 * NF)
+    runs = max(1, cells // (16 * D))
+    diff = total = 0
+    for f in range(D):
+        for a0 in rng.integers(0, ns - 16, runs):
+            words = plan.hash_words(f, int(a0), 16)
+            for q in range(16):
+                by, _, _ = oracle.hash_one(series.x[f], w, int(a0) + q, R[f], U[f], r)
+                for F in range(NF):
+                    for pos in range(K // 2):
+                        g = (int(words[F, q]) >> (24 - 8 * pos)) & 255
+                        diff += g != int(by[4 * F + pos])
+                        total += 1
+    return {"rate": diff / total, "symbols": total}
 
 
 def bench_batch(args, torch, mm, synth) -> int:
@@ -150,17 +195,94 @@ def bench_batch(args, torch, mm, synth) -> int:
     return 0
 
 
+def run_leg(args, torch, mm, s, p, x, proj: str, seed: int, r_scale: float, steps: int, warmup: int,
+            profile: bool):
+    """Time `steps` whole searches (index + traversal) of one projection
+    precision on a resident series; one more untimed step, profiled per kernel."""
+    plan = mm.Plan(s.n, s.D, p["w"], "f32" if s.dtype == "f32" else "f64", p["mem_limit"],
+                   device_series=True, seed=seed, proj=proj, profile=2 if profile else 0,
+                   r_scale=r_scale, max_pairs=args.max_pairs)
+
+    def step():
+        plan.hash(x)
+        return plan.search(p["d"], p["k"], p["delta"])
+
+    for wi in range(warmup):
+        got, rep, rc = step()
+        log(f"[bench] {proj} warmup {wi}: tts {rep['t_hash_ms'] + rep['t_search_ms']:.1f} ms, "
+            f"stop ({rep['i_stop']},{rep['j_stop']})")
+    plan.profile(clear=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for si in range(steps):
+        got, rep, rc = step()
+        reps.append(rep)
+        log(f"[bench] {proj} step {si}: hash {rep['t_hash_ms']:.2f} ms, search {rep['t_search_ms']:.1f} ms, "
+            f"stop ({rep['i_stop']},{rep['j_stop']}), cand {rep['n_cand']}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    prof_t, prof = {}, {}
+    if profile:
+        # the timed steps carry HIP events around the pair enumeration only
+        # (the dominant kernel); one more step, untimed, times every kernel
+        prof_t = plan.profile(clear=True)
+        plan.set_profile(1)
+        step()
+        prof = plan.profile(clear=True)
+    return dict(plan=plan, ms=ms, got=got, rep=rep, rc=rc, reps=reps, prof_t=prof_t, prof=prof)
+
+
+def roofline(leg, proj: str, workload: str, steps: int) -> dict:
+    prof, prof_t = leg["prof"], leg["prof_t"]
+    ranked = sorted(((v["ms"], k) for k, v in prof.items() if v["launches"]), reverse=True)
+    dom = ranked[0][1]
+    # the dominant kernel's figures over the timed region when it was timed
+    # there (the enumeration), else from the extra step
+    live = dom in prof_t and prof_t[dom]["launches"] > 0
+    v = prof_t[dom] if live else prof[dom]
+    nsteps = steps if live else 1
+    sec = v["ms"] / 1000.0
+    if dom == "proj":
+        bound, unit, peak = "mfma", "TFLOP/s", PEAKS["mfma_TFLOPs"][proj]
+        ach = v["flops"] / sec / 1e12
+    elif dom == "enum":
+        # the pair screen is 32-bit integer VALU work
+        bound, unit, peak = "alu", "TOP/s", PEAKS["alu_TOPs"]
+        ach = v["flops"] / sec / 1e12
+    else:
+        bound, unit, peak = "hbm", "GB/s", PEAKS["hbm_GBps"]
+        ach = v["bytes"] / sec / 1e9
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": measured_traffic(dom, workload), "kernel": dom,
+            "avg_launch_ms": v["ms"] / v["launches"], "launches_per_step": v["launches"] / nsteps,
+            "timed_region": live,
+            "algorithmic_bytes_per_launch": v["bytes"] / v["launches"],
+            "algorithmic_ops_per_launch": v["flops"] / v["launches"]}
+
+
+def proj_mfma(leg, proj: str) -> dict | None:
+    pj = leg["prof"].get("proj")
+    if not pj or not pj["launches"]:
+        return None
+    ach = pj["flops"] / (pj["ms"] / 1000.0) / 1e12
+    return {"achieved_TFLOPs": ach, "peak": PEAKS["mfma_TFLOPs"][proj],
+            "frac": ach / PEAKS["mfma_TFLOPs"][proj], "ms": pj["ms"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rw8_1m")
+    ap.add_argument("--workload", default="rwsin32_4m")
     ap.add_argument("--proj", default=None, help="projection precision (default: the workload's)")
-    ap.add_argument("--cpu-n", type=int, default=2000,
-                    help="points of the series the CPU oracle is timed on (about 25 s on one core)")
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="timed steps of the comparison precision (FP32 against BF16)")
+    ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-checks", action="store_true", help="skip the flip-rate and distance checks")
     ap.add_argument("--r-scale", type=float, default=0.0,
                     help="r as a multiple of the section 6.1 estimate (default: the workload's)")
     ap.add_argument("--max-pairs", type=float, default=5e13,
@@ -184,103 +306,85 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload in synth.BATCHES:
         return bench_batch(args, torch, mm, synth)
+    t_gen = time.perf_counter()
     s, p = synth.workload(args.workload)
     proj = args.proj or p["proj"]
+    cmp_proj = None if (args.no_compare or args.proj) else p.get("compare_proj")
     seed = synth.LSH_SEED[args.workload]
     log(f"[bench] workload {args.workload}: D={s.D} n={s.n} w={p['w']} d={p['d']} k={p['k']} "
-        f"delta={p['delta']} proj={proj}")
+        f"delta={p['delta']} proj={proj}{' vs ' + cmp_proj if cmp_proj else ''} "
+        f"(series drawn in {time.perf_counter() - t_gen:.1f} s)")
     x = torch.from_numpy(s.as_dtype()).to("cuda:0")
     torch.cuda.synchronize()
     r_scale = args.r_scale if args.r_scale > 0 else p.get("r_scale", 1.0)
-    plan = mm.Plan(s.n, s.D, p["w"], "f32" if s.dtype == "f32" else "f64", p["mem_limit"],
-                   device_series=True, seed=seed, proj=proj, profile=0 if args.no_profile else 2,
-                   r_scale=r_scale, max_pairs=args.max_pairs)
-
-    def step():
-        plan.hash(x)
-        return plan.search(p["d"], p["k"], p["delta"])
-
-    for wi in range(args.warmup):
-        got, rep, rc = step()
-        log(f"[bench] warmup {wi}: tts {rep['t_hash_ms'] + rep['t_search_ms']:.1f} ms, "
-            f"stop ({rep['i_stop']},{rep['j_stop']})")
-    plan.profile(clear=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = []
-    for si in range(args.steps):
-        got, rep, rc = step()
-        reps.append(rep)
-        log(f"[bench] step {si}: hash {rep['t_hash_ms']:.2f} ms, search {rep['t_search_ms']:.1f} ms, "
-            f"stop ({rep['i_stop']},{rep['j_stop']}), cand {rep['n_cand']}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1000.0 / args.steps
+    prof_on = not args.no_profile
+    lead = run_leg(args, torch, mm, s, p, x, proj, seed, r_scale, args.steps, args.warmup, prof_on)
     ns = s.n - p["w"] + 1
     units = ns * s.D
-    prm = plan.params()
-    prof_t, prof = {}, {}
-    if not args.no_profile:
-        # the timed steps carry HIP events around the pair enumeration only
-        # (the dominant kernel); one more step, untimed, times every kernel
-        prof_t = plan.profile(clear=True)
-        plan.set_profile(1)
-        step()
-        prof = plan.profile(clear=True)
-    plan.close()
-
+    prm = lead["plan"].params()
+    got, rep, rc = lead["got"], lead["rep"], lead["rc"]
     planted = {(m.p1, m.p2) for m in s.motifs}
-    found = {(m["a"], m["b"]) for m in got}
+    found = [(m["a"], m["b"]) for m in got]
+    hash_ms = sum(r["t_hash_ms"] for r in lead["reps"]) / len(lead["reps"])
     out = {
-        "metric": METRIC, "value": units / (ms / 1000.0), "unit": "subseq·dims/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "metric": METRIC, "value": lead["ms"] / 1000.0, "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": lead["ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": proj, "data": "synthetic",
         "config": {"workload": args.workload, "D": s.D, "n": s.n, "w": p["w"], "d": p["d"],
                    "k": p["k"], "delta": p["delta"], "mem_limit": p["mem_limit"],
                    "series": s.dtype, "proj": proj, "K": 8, "L_used": prm["L"], "r_scale": r_scale},
-        "tts_s": ms / 1000.0,
-        "hash_subseq_dims_per_s": units / (sum(r["t_hash_ms"] for r in reps) / len(reps) / 1000.0),
-        "hash_ms": sum(r["t_hash_ms"] for r in reps) / len(reps),
-        "stop": [rep["i_stop"], rep["j_stop"]], "r": prm["r"], "status": rc,
+        "tts_s": {proj: lead["ms"] / 1000.0},
+        "hash_subseq_dims_per_s": {proj: units / (hash_ms / 1000.0)},
+        "hash_ms": {proj: hash_ms},
+        "search_subseq_dims_per_s": {proj: units / (lead["ms"] / 1000.0)},
+        "stop": {proj: [rep["i_stop"], rep["j_stop"]]}, "r": prm["r"], "status": {proj: rc},
         "n_cand": rep["n_cand"], "n_collisions": rep["n_collisions"],
-        "planted_recovered": f"{len(planted & found)}/{len(planted)}",
+        "planted_recovered": {proj: f"{len(planted & set(found))}/{len(planted)}"},
     }
-    if prof:
-        ranked = sorted(((v["ms"], k) for k, v in prof.items() if v["launches"]), reverse=True)
-        out["kernel_ms_per_step"] = {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}
-        dom = ranked[0][1]
-        # the dominant kernel's figures over the timed region when it was timed
-        # there (the enumeration), else from the extra step
-        live = dom in prof_t and prof_t[dom]["launches"] > 0
-        v = prof_t[dom] if live else prof[dom]
-        nsteps = args.steps if live else 1
-        avg_ms = v["ms"] / v["launches"]
-        sec = v["ms"] / 1000.0
-        if dom == "proj":
-            bound, unit, peak = "mfma", "TFLOP/s", PEAKS["mfma_TFLOPs"][proj]
-            ach = v["flops"] / sec / 1e12
-        elif dom == "enum":
-            # the pair screen is 32-bit integer VALU work
-            bound, unit, peak = "alu", "TOP/s", PEAKS["alu_TOPs"]
-            ach = v["flops"] / sec / 1e12
-        else:
-            bound, unit, peak = "hbm", "GB/s", PEAKS["hbm_GBps"]
-            ach = v["bytes"] / sec / 1e9
-        out["roofline"] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-                           "traffic": measured_traffic(dom, args.workload), "kernel": dom,
-                           "avg_launch_ms": avg_ms, "launches_per_step": v["launches"] / nsteps,
-                           "timed_region": live,
-                           "algorithmic_bytes_per_launch": v["bytes"] / v["launches"],
-                           "algorithmic_ops_per_launch": v["flops"] / v["launches"]}
-        pj = prof.get("proj")
-        if pj and pj["launches"]:
-            ach = pj["flops"] / (pj["ms"] / 1000.0) / 1e12
-            out["proj_mfma"] = {"achieved_TFLOPs": ach, "peak": PEAKS["mfma_TFLOPs"][proj],
-                                "frac": ach / PEAKS["mfma_TFLOPs"][proj]}
+    if prof_on and lead["prof"]:
+        out["kernel_ms_per_step"] = {proj: {k: round(v["ms"], 3) for k, v in lead["prof"].items() if v["launches"]}}
+        out["roofline"] = roofline(lead, proj, args.workload, args.steps)
+        out["proj_mfma"] = {proj: proj_mfma(lead, proj)}
+    checks = not args.no_checks
+    if checks:
+        import oracle
+        # r of the oracle (section 6.1 estimate, same draws) equals the device's
+        r_orc = oracle.estimate_r(s.x, p["w"], seed) * r_scale
+        out["r_oracle_equal"] = r_orc == prm["r"]
+        out["flip_rate_vs_fp64"] = {proj: flip_rate(lead["plan"], s, p, seed, prm["r"])}
+        err = 0.0
+        for m in got:
+            dd, dm, dims, _ = oracle.distd(s.x, p["w"], m["a"], m["b"], p["d"])
+            err = max(err, abs(m["dist_d"] - dd) / dd, abs(m["dist_max"] - dm) / dm)
+        out["dist_rel_err_vs_fp64"] = {proj: err}
+    lead["plan"].close()
+    if cmp_proj:
+        leg = run_leg(args, torch, mm, s, p, x, cmp_proj, seed, r_scale, args.compare_steps, 1, prof_on)
+        hms = sum(r["t_hash_ms"] for r in leg["reps"]) / len(leg["reps"])
+        out["tts_s"][cmp_proj] = leg["ms"] / 1000.0
+        out["hash_subseq_dims_per_s"][cmp_proj] = units / (hms / 1000.0)
+        out["hash_ms"][cmp_proj] = hms
+        out["search_subseq_dims_per_s"][cmp_proj] = units / (leg["ms"] / 1000.0)
+        out["stop"][cmp_proj] = [leg["rep"]["i_stop"], leg["rep"]["j_stop"]]
+        out["status"][cmp_proj] = leg["rc"]
+        found_c = [(m["a"], m["b"]) for m in leg["got"]]
+        out["planted_recovered"][cmp_proj] = f"{len(planted & set(found_c))}/{len(planted)}"
+        out[f"tts_ratio_{cmp_proj}_over_{proj}"] = leg["ms"] / lead["ms"]
+        out[f"topk_{proj}_equals_{cmp_proj}"] = found == found_c
+        if prof_on and leg["prof"]:
+            out["kernel_ms_per_step"][cmp_proj] = {k: round(v["ms"], 3) for k, v in leg["prof"].items()
+                                                   if v["launches"]}
+            out["proj_mfma"][cmp_proj] = proj_mfma(leg, cmp_proj)
+        if checks:
+            out["flip_rate_vs_fp64"][cmp_proj] = flip_rate(leg["plan"], s, p, seed, prm["r"])
+        leg["plan"].close()
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: oracle on the first {args.cpu_n} points")
-        out["cpu_baseline"] = cpu_baseline(s, p, seed, args.cpu_n, r_scale)
+        log("[bench] cpu baseline: the oracle's search on the stretches around the planted windows")
+        import oracle
+        r_cpu = oracle.estimate_r(s.x, p["w"], seed) * r_scale
+        out["cpu_baseline"] = cpu_baseline(s, p, seed, r_cpu)
+        out["cpu_baseline"]["gpu_same_unit"] = units / (lead["ms"] / 1000.0)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -242,6 +242,12 @@ int momenti_get_stats(momenti_plan* p, double* mu, double* inv_sigma, size_t cou
  * (symbol = (floor((a.x + b)/r) + 128) mod 256, Eq. drp). Host buffer. */
 int momenti_get_hashes(momenti_plan* p, uint32_t* dst, size_t count);
 
+/* The index words of `count` consecutive windows a0 .. a0 + count - 1 of
+ * dimension f: dst is [n_left + n_right][count] (uint32, host). For sampling
+ * a large index without copying it whole. Errors: E_ARG (range outside the
+ * index), E_STATE (no index yet). */
+int momenti_get_hash_words(momenti_plan* p, int32_t f, int64_t a0, int64_t count, uint32_t* dst);
+
 /* Replace the index by words computed elsewhere (same layout), e.g. to
  * traverse a reference index. Host buffer. Marks the plan hashed; the
  * statistics must already exist (momenti_hash called once). */

@@ -803,6 +803,22 @@ int momenti_get_hashes(momenti_plan* p, uint32_t* dst, size_t count)
     return MOMENTI_OK;
 }
 
+int momenti_get_hash_words(momenti_plan* p, int32_t f, int64_t a0, int64_t count, uint32_t* dst)
+{
+    if (!p || !dst) return fail(MOMENTI_E_ARG, "NULL argument");
+    if (!p->hashed) return fail(MOMENTI_E_STATE, "no index yet");
+    if (f < 0 || f >= p->D || a0 < 0 || count < 0 || a0 + count > p->ns)
+        return fail(MOMENTI_E_ARG, "dimension %d, windows [%lld, %lld) outside the index", f, (long long)a0,
+                    (long long)(a0 + count));
+    if (count == 0) return MOMENTI_OK;
+    HIP_OK(hipStreamSynchronize(p->st));
+    // rows of the dimension's half-functions, count words each
+    HIP_OK(hipMemcpy2DAsync(dst, (size_t)count * 4, p->H + ((int64_t)f * p->NF) * p->ns + a0, (size_t)p->ns * 4,
+                            (size_t)count * 4, (size_t)p->NF, hipMemcpyDeviceToHost, p->st));
+    HIP_OK(hipStreamSynchronize(p->st));
+    return MOMENTI_OK;
+}
+
 int momenti_set_hashes(momenti_plan* p, const uint32_t* src, size_t count)
 {
     if (!p || !src) return fail(MOMENTI_E_ARG, "NULL argument");

@@ -27,7 +27,7 @@ EXPORTS = [
     "momenti_destroy", "momenti_last_error", "momenti_get_params", "momenti_get_stats",
     "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace", "momenti_get_profile",
     "momenti_set_profile",
-    "momenti_topk_batch",
+    "momenti_topk_batch", "momenti_get_hash_words",
 ]
 
 
@@ -96,6 +96,7 @@ def lib():
             "momenti_get_stats": (i32, [vp, vp, vp, C.c_size_t]),
             "momenti_get_hashes": (i32, [vp, vp, C.c_size_t]),
             "momenti_set_hashes": (i32, [vp, vp, C.c_size_t]),
+            "momenti_get_hash_words": (i32, [vp, i32, i64, i64, vp]),
             "momenti_set_trace": (i32, [vp, vp, i64, vp, vp, vp, i64, i32]),
             "momenti_get_profile": (i32, [vp, P(KProf), i32, P(i32), i32]),
             "momenti_set_profile": (i32, [vp, i32]),
@@ -228,6 +229,12 @@ class Plan:
         NF = self.params()["NF"]
         out = np.zeros((self.D, NF, ns), dtype=np.uint32)
         _check(lib().momenti_get_hashes(self.h, out.ctypes.data_as(C.c_void_p), out.size))
+        return out
+
+    def hash_words(self, f: int, a0: int, count: int) -> np.ndarray:
+        """Index words [n_left + n_right][count] of windows a0 .. a0+count-1 of dimension f."""
+        out = np.zeros((self.params()["NF"], count), dtype=np.uint32)
+        _check(lib().momenti_get_hash_words(self.h, f, a0, count, out.ctypes.data_as(C.c_void_p)))
         return out
 
     def set_hashes(self, words: np.ndarray) -> None:

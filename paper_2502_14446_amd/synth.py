@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import List, Sequence, Tuple
 
 import numpy as np
@@ -144,7 +145,7 @@ WORKLOADS = {
     # r at r_scale times the estimate (with the estimate itself no step stops
     # above round 1 for these distances and d)
     "rwsin32_4m": dict(D=32, n=4_194_304, w=1000, d=8, k=10, delta=0.05, n_motifs=10,
-                       motif_dims=8, dtype="f32", proj="bf16", sinusoids=True,
+                       motif_dims=8, dtype="f32", proj="bf16", compare_proj="f32", sinusoids=True,
                        mem_limit=64_000_000_000, r_scale=4.0),
     # large fp8: D=128, n=1e6, w=500, d=16, k=50, delta=0.01, 64 GB cap
     "rw128_1m": dict(D=128, n=1_000_000, w=500, d=16, k=50, delta=0.01, n_motifs=50,
@@ -156,12 +157,30 @@ LSH_SEED = {"tiny": 0x15A001, "rw8_1m": 0x15A002, "rwsin32_4m": 0x15A003, "rw128
 
 
 def workload(name: str, n: int | None = None, seed: int | None = None) -> Tuple[Series, dict]:
-    """Series and parameters of a named workload (optionally at a reduced length n)."""
+    """Series and parameters of a named workload (optionally at a reduced length n).
+    With MOMENTI_SERIES_CACHE set to a directory, the drawn series is kept
+    there (.npy) and loaded on later calls: the same values, drawn once."""
     p = dict(WORKLOADS[name])
     nn = p["n"] if n is None else n
-    s = make_series(DATA_SEED[name] if seed is None else seed, p["D"], nn, p["w"],
-                    p["n_motifs"], p["motif_dims"], dtype=p["dtype"],
-                    sinusoids=p.get("sinusoids", False), min_gap=p.get("min_gap", 0))
+    sd = DATA_SEED[name] if seed is None else seed
+    cache = os.environ.get("MOMENTI_SERIES_CACHE")
+    path = os.path.join(cache, f"{name}_{nn}_{sd:x}.npz") if cache else None
+    if path and os.path.exists(path):
+        z = np.load(path)
+        motifs = [Motif(tuple(int(v) for v in row[2:] if v >= 0), int(row[0]), int(row[1]))
+                  for row in z["motifs"]]
+        s = Series(z["x"], p["w"], motifs, p["dtype"])
+    else:
+        s = make_series(sd, p["D"], nn, p["w"], p["n_motifs"], p["motif_dims"], dtype=p["dtype"],
+                        sinusoids=p.get("sinusoids", False), min_gap=p.get("min_gap", 0))
+        if path:
+            os.makedirs(cache, exist_ok=True)
+            width = 2 + max((len(m.dims) for m in s.motifs), default=0)
+            rows = np.full((len(s.motifs), width), -1, dtype=np.int64)
+            for q, m in enumerate(s.motifs):
+                rows[q, :2 + len(m.dims)] = [m.p1, m.p2, *m.dims]
+            np.savez(path + ".tmp.npz", x=s.x, motifs=rows)
+            os.replace(path + ".tmp.npz", path)
     p["n"] = nn
     return s, p
 
