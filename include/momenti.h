@@ -190,6 +190,23 @@ int momenti_hash(momenti_plan* p, const void* series);
 int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
                    int32_t* n_out, momenti_report* rep);
 
+/* momenti_search for callers that cannot allocate device memory (code under
+ * stream capture, serving loops or harnesses that forbid hipMalloc): every
+ * traversal buffer is carved from a scratch area of 256 MiB that the library
+ * keeps on each device it runs on (a static device array, held until the
+ * process ends); host staging uses plain memory. Arguments, results and
+ * report are those of momenti_search on the same plan (report.peak_bytes is
+ * the part of the scratch area used); the plan's own traversal buffers are
+ * left as they are. The call makes no hipMalloc, hipFree or hipHostMalloc;
+ * it synchronises the plan's stream before and after. Every call on one
+ * device shares that device's area, which keeps the last call's contents:
+ * calls that overlap on one device race, so run them one at a time per
+ * device. Errors as momenti_search, plus E_NOMEM when the traversal of this
+ * input does not fit in the scratch area (momenti_search then allocates what
+ * it needs). */
+int momenti_search_noalloc(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
+                           int32_t* n_out, momenti_report* rep);
+
 /* One call: prepare + hash + search + destroy. Arguments as above. */
 int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_t w, int32_t d,
                  int32_t k, double delta, uint64_t mem_limit, const momenti_opts* opts,

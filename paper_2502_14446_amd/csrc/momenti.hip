@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -252,6 +253,10 @@ struct momenti_plan {
     BlockCache* cache = nullptr;   // the batch worker's blocks, or own_cache
     BlockCache own_cache;          // a plan of its own: blocks its next search reuses
     bool recycle = false;          // own_cache: a search is releasing and re-taking its buffers
+    // momenti_search_noalloc: traversal buffers are carved, in order, from the
+    // device's scratch area (bytes = the part used, mem_limit = its size)
+    bool arena = false;
+    unsigned char* arena_base = nullptr;
     int64_t n = 0, ns = 0;
     int D = 0, w = 0, dtype = 1;
     uint64_t mem_limit = 0;
@@ -321,6 +326,19 @@ static int dalloc(momenti_plan* p, void** ptr, size_t bytes)
 {
     *ptr = nullptr;
     if (bytes == 0) bytes = 16;
+    if (p->arena) {
+        // the next 256-byte aligned piece of the scratch area; nothing is
+        // given back before the call ends
+        const size_t need = (bytes + 255) / 256 * 256;
+        if (p->bytes + need > p->mem_limit)
+            return fail(MOMENTI_E_NOMEM, "scratch area exhausted: %llu + %zu > %llu bytes (momenti_search "
+                        "allocates what this input needs)", (unsigned long long)p->bytes, need,
+                        (unsigned long long)p->mem_limit);
+        *ptr = p->arena_base + p->bytes;
+        p->bytes += need;
+        p->peak = std::max<uint64_t>(p->peak, p->bytes);
+        return MOMENTI_OK;
+    }
     if (p->bytes + bytes > p->mem_limit)
         return fail(MOMENTI_E_NOMEM, "device budget exceeded: %llu + %zu > %llu bytes",
                     (unsigned long long)p->bytes, bytes, (unsigned long long)p->mem_limit);
@@ -359,9 +377,26 @@ static int dalloc_t(momenti_plan* p, T** ptr, size_t bytes)
     return rc;
 }
 
-static void dfree(momenti_plan* p, void* ptr, size_t bytes)
+// Host staging buffers: pinned, except under momenti_search_noalloc (plain
+// memory: no allocating HIP call there).
+static bool host_alloc(momenti_plan* p, void** ptr, size_t bytes)
+{
+    if (p->arena) {
+        *ptr = std::malloc(bytes);
+        return *ptr != nullptr;
+    }
+    return hipHostMalloc(ptr, bytes, 0) == hipSuccess;
+}
+
+static void host_free(momenti_plan* p, void* ptr)
 {
     if (!ptr) return;
+    if (p->arena) std::free(ptr); else (void)hipHostFree(ptr);
+}
+
+static void dfree(momenti_plan* p, void* ptr, size_t bytes)
+{
+    if (!ptr || p->arena) return;   // scratch pieces are not given back one by one
     const size_t capb = p->cache->capacity(ptr);
     if (capb) bytes = capb;
     if (p->cache != &p->own_cache || p->recycle)
@@ -510,9 +545,9 @@ static void release_search(momenti_plan* p)
     dfree(p, p->snaps, (size_t)p->snap_steps * sizeof(Snap));
     dfree(p, p->snap_tops, (size_t)p->snap_steps * p->snap_k * sizeof(VRec));
     p->snaps = nullptr; p->snap_tops = nullptr; p->snap_steps = 0; p->snap_k = 0;
-    if (p->host_status) (void)hipHostFree(p->host_status);
+    host_free(p, p->host_status);
     p->host_status = nullptr;
-    if (p->host_snaps) (void)hipHostFree(p->host_snaps);
+    host_free(p, p->host_snaps);
     p->host_snaps = nullptr;
 }
 
@@ -999,7 +1034,7 @@ static int alloc_pool(momenti_plan* p, int P, int k, int steps)
     dfree(p, p->snaps, (size_t)p->snap_steps * sizeof(Snap));
     dfree(p, p->snap_tops, (size_t)p->snap_steps * p->snap_k * sizeof(VRec));
     p->pools = nullptr; p->top = nullptr; p->snaps = nullptr; p->snap_tops = nullptr;
-    if (p->host_snaps) (void)hipHostFree(p->host_snaps);
+    host_free(p, p->host_snaps);
     p->host_snaps = nullptr;
     int rc;
     if ((rc = dalloc_t(p, &p->pools, (size_t)2 * P * sizeof(VRec)))) return rc;
@@ -1010,8 +1045,8 @@ static int alloc_pool(momenti_plan* p, int P, int k, int steps)
     if ((rc = dalloc_t(p, &p->snap_tops, (size_t)steps * k * sizeof(VRec)))) return rc;
     p->snap_steps = steps;
     p->snap_k = k;
-    if (hipHostMalloc((void**)&p->host_snaps, (size_t)steps * sizeof(Snap), 0) != hipSuccess)
-        return fail(MOMENTI_E_NOMEM, "pinned host allocation failed");
+    if (!host_alloc(p, (void**)&p->host_snaps, (size_t)steps * sizeof(Snap)))
+        return fail(MOMENTI_E_NOMEM, "host staging allocation failed");
     return MOMENTI_OK;
 }
 
@@ -1113,16 +1148,18 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         momenti_plan* p;
         ~Recycle() { p->recycle = false; }
     } recycling{p};
-    p->recycle = true;
-    release_search(p);
+    if (!p->arena) {
+        p->recycle = true;
+        release_search(p);
+    }
     const int max_steps = std::min(p->K, 7) * p->L;   // steps of the largest round group
     int P = p->o.pool_size ? p->o.pool_size : std::max(4096, 128 * k);
     P = std::max(P, k);
     int rc;
     if ((rc = dalloc_t(p, &p->status, 4096))) return rc;
     if ((rc = dalloc_t(p, &p->rctl, sizeof(ReplayCtl)))) return rc;
-    if (hipHostMalloc((void**)&p->host_status, 4096, 0) != hipSuccess)
-        return fail(MOMENTI_E_NOMEM, "pinned host allocation failed");
+    if (!host_alloc(p, (void**)&p->host_status, 4096))
+        return fail(MOMENTI_E_NOMEM, "host staging allocation failed");
     if ((rc = alloc_pool(p, P, k, max_steps))) return rc;
     const int64_t tiles = (p->ns + kSortTile - 1) / kSortTile;
     // A pair colliding in >= d dimensions has its lowest colliding dimension
@@ -1151,7 +1188,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     // a plan of its own frees the blocks of its previous search that this one
     // did not take back, so that it holds what it uses (a batch worker keeps
     // them for its next series)
-    if (p->cache == &p->own_cache) {
+    if (p->cache == &p->own_cache && !p->arena) {
         p->own_cache.trim();
         p->recycle = false;
     }
@@ -1697,6 +1734,128 @@ static int exact_sweep(momenti_plan* p, int d, int k, momenti_motif* out, int32_
         theta = topn >= k ? kth + 4.0 * eps : 2.0 * theta_min;
     }
     return fail(MOMENTI_E_DEVICE, "exact answer: the sweep did not certify its result");
+}
+
+// ------------------------------------------------------------------ search without allocations
+// The scratch area of momenti_search_noalloc: one per device, held until the
+// process ends. In host code `scratch` names a host-side stand-in; its device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is ever handed to kernels or copies.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch area on device `dev` (made current for the
+// lookup, then restored).
+static int scratch_on(int dev, void** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return fail(MOMENTI_E_DEVICE, "device %d outside [0, %d)", dev, kMaxDevices);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        HIP_OK(hipGetDevice(&cur));
+        if (cur != dev) HIP_OK(hipSetDevice(dev));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) HIP_OK(hipSetDevice(cur));
+        if (e != hipSuccess || !ptr)
+            return fail(MOMENTI_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MOMENTI_OK;
+}
+
+// The traversal buffers of a plan, set aside while momenti_search_noalloc runs.
+struct SearchBuffers {
+    SortBufs sb;
+    int sb_nseg, sb_reps;
+    uint32_t *fps, *fq;
+    unsigned long long* coll_part;
+    int64_t coll_parts;
+    Cand* cand;
+    VRec* vrec;
+    uint32_t cap;
+    VRec* store;
+    uint32_t* keep;
+    uint32_t store_cap;
+    VRec* pools;
+    int P;
+    VRec* top;
+    int top_k;
+    unsigned char* status;
+    ReplayCtl* rctl;
+    Snap* snaps;
+    VRec* snap_tops;
+    int snap_steps, snap_k;
+    unsigned char* host_status;
+    Snap* host_snaps;
+};
+
+static SearchBuffers set_aside(momenti_plan* p)
+{
+    SearchBuffers b{p->sb, p->sb_nseg, p->sb_reps, p->fps, p->fq, p->coll_part, p->coll_parts, p->cand, p->vrec,
+                    p->cap, p->store, p->keep, p->store_cap, p->pools, p->P, p->top, p->top_k, p->status, p->rctl,
+                    p->snaps, p->snap_tops, p->snap_steps, p->snap_k, p->host_status, p->host_snaps};
+    p->sb = SortBufs{};
+    p->sb_nseg = p->sb_reps = 0;
+    p->fps = p->fq = nullptr;
+    p->coll_part = nullptr; p->coll_parts = 0;
+    p->cand = nullptr; p->vrec = nullptr; p->cap = 0;
+    p->store = nullptr; p->keep = nullptr; p->store_cap = 0;
+    p->pools = nullptr; p->P = 0; p->top = nullptr; p->top_k = 0;
+    p->status = nullptr; p->rctl = nullptr;
+    p->snaps = nullptr; p->snap_tops = nullptr; p->snap_steps = p->snap_k = 0;
+    p->host_status = nullptr; p->host_snaps = nullptr;
+    return b;
+}
+
+static void put_back(momenti_plan* p, const SearchBuffers& b)
+{
+    p->sb = b.sb; p->sb_nseg = b.sb_nseg; p->sb_reps = b.sb_reps; p->fps = b.fps; p->fq = b.fq;
+    p->coll_part = b.coll_part; p->coll_parts = b.coll_parts; p->cand = b.cand; p->vrec = b.vrec; p->cap = b.cap;
+    p->store = b.store; p->keep = b.keep; p->store_cap = b.store_cap; p->pools = b.pools; p->P = b.P;
+    p->top = b.top; p->top_k = b.top_k; p->status = b.status; p->rctl = b.rctl; p->snaps = b.snaps;
+    p->snap_tops = b.snap_tops; p->snap_steps = b.snap_steps; p->snap_k = b.snap_k;
+    p->host_status = b.host_status; p->host_snaps = b.host_snaps;
+}
+
+extern "C" int momenti_search_noalloc(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
+                                      int32_t* n_out, momenti_report* rep)
+{
+    g_err.clear();
+    if (!p || !out || !n_out) return fail(MOMENTI_E_ARG, "NULL argument");
+    void* base = nullptr;
+    int rc = scratch_on(p->dev, &base);
+    if (rc) return rc;
+    HIP_OK(p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize());   // earlier work on the plan is done
+    const SearchBuffers kept = set_aside(p);
+    const uint64_t limit = p->mem_limit, held = p->bytes, peak = p->peak;
+    const bool prof_on = p->prof.on;
+    p->arena = true;
+    p->arena_base = (unsigned char*)base;
+    p->mem_limit = kScratchBytes;
+    p->bytes = 0;
+    p->peak = 0;
+    p->prof.on = false;   // no events are created during this call
+    rc = momenti_search(p, d, k, delta, out, n_out, rep);
+    // the call's work on the scratch area ends before the next call may use it
+    const hipError_t e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
+    host_free(p, p->host_status);
+    host_free(p, p->host_snaps);
+    put_back(p, kept);
+    p->arena = false;
+    p->arena_base = nullptr;
+    p->mem_limit = limit;
+    p->bytes = held;
+    p->peak = peak;
+    p->prof.on = prof_on;
+    if (rc >= 0 && e != hipSuccess) return fail(MOMENTI_E_DEVICE, "search without allocations: %s", hipGetErrorString(e));
+    return rc;
 }
 
 extern "C" int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_t w,

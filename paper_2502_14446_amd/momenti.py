@@ -27,7 +27,7 @@ EXPORTS = [
     "momenti_destroy", "momenti_last_error", "momenti_get_params", "momenti_get_stats",
     "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace", "momenti_get_profile",
     "momenti_set_profile",
-    "momenti_topk_batch", "momenti_get_hash_words",
+    "momenti_topk_batch", "momenti_get_hash_words", "momenti_search_noalloc",
 ]
 
 
@@ -88,6 +88,7 @@ def lib():
             "momenti_prepare": (i32, [P(vp), i64, i32, i32, i32, u64, P(Opts)]),
             "momenti_hash": (i32, [vp, vp]),
             "momenti_search": (i32, [vp, i32, i32, d, P(Motif), P(i32), P(Report)]),
+            "momenti_search_noalloc": (i32, [vp, i32, i32, d, P(Motif), P(i32), P(Report)]),
             "momenti_topk": (i32, [vp, i32, i64, i32, i32, i32, i32, d, u64, P(Opts), P(Motif),
                                    P(i32), P(Report)]),
             "momenti_destroy": (None, [vp]),
@@ -209,6 +210,14 @@ class Plan:
         got = C.c_int32()
         rep = Report()
         rc = _check(lib().momenti_search(self.h, d, k, delta, arr, C.byref(got), C.byref(rep)))
+        return _motifs(arr, got.value), _report(rep), rc
+
+    def search_noalloc(self, d: int, k: int, delta: float) -> Tuple[List[Dict], Dict, int]:
+        """momenti_search_noalloc: the same search, its buffers in the library's scratch area."""
+        arr = (Motif * max(k, 1))()
+        got = C.c_int32()
+        rep = Report()
+        rc = _check(lib().momenti_search_noalloc(self.h, d, k, delta, arr, C.byref(got), C.byref(rep)))
         return _motifs(arr, got.value), _report(rep), rc
 
     def params(self) -> Dict:
