@@ -72,6 +72,22 @@ extern "C" {
 #define MOMENTI_STOP_TENSOR 0
 #define MOMENTI_STOP_LEMMA52 1
 #define MOMENTI_STOP_TENSOR_LITERAL 2
+/* RIGOROUS: a bound that follows from the tensored index itself. Repetitions
+ * that share a half-function are not independent, so Lemma 6.1's product is
+ * not obviously an upper bound. Each symbol of a half-function collides with
+ * probability >= p = P(dist_max)^d (Eq. eucl-collision-probability over the d
+ * dimensions), independently, so each half-function collides at least to a
+ * geometric depth (P(depth >= s) = p^s); the probability that no visited
+ * repetition (left j div m, right j mod m) reached the prefix length of its
+ * round, with those depths, is computed exactly (a finite sum over which
+ * right functions reach the two depths involved). */
+#define MOMENTI_STOP_RIGOROUS 3
+
+/* Meaning of delta (opts.delta_mode). PER_MOTIF: each returned motif is the
+ * true one with probability >= 1 - delta (Lemma 5.3). JOINT: all k at once
+ * (Lemma 5.4: the rule runs with delta / k). */
+#define MOMENTI_DELTA_PER_MOTIF 0
+#define MOMENTI_DELTA_JOINT 1
 
 typedef struct momenti_plan momenti_plan;   /* opaque, owned by the library */
 
@@ -100,6 +116,12 @@ typedef struct {
                                  (from one probed repetition) above this is not traversed and
                                  the search returns MOMENTI_OK_PARTIAL; <= 0: no budget */
     void* stream;             /* hipStream_t, NULL = default stream */
+    int32_t delta_mode;       /* MOMENTI_DELTA_PER_MOTIF (default) or MOMENTI_DELTA_JOINT */
+    int32_t max_steps;        /* anytime budget: after this many (round, repetition) steps the
+                                 search returns TOP as it stands (MOMENTI_OK_PARTIAL, each motif
+                                 with its failure bound); <= 0: none */
+    double max_ms;            /* the same budget in wall-clock milliseconds of the traversal,
+                                 checked after every replayed batch of repetitions; <= 0: none */
 } momenti_opts;
 
 /* Per-kernel totals collected when opts.profile is set: launches, summed
@@ -120,6 +142,10 @@ typedef struct {
     double dist_d;            /* definition "d-dimensional distance" */
     double dist_max;          /* Eq. distdmax: largest distance among the chosen dimensions */
     uint64_t dims[2];         /* bit f set for each chosen dimension (D <= 128) */
+    double fail_prob;         /* the stopping rule's bound, at the step where the search ended,
+                                 on the probability that a pair at this motif's dist_max was
+                                 never a candidate (Lemma 5.2 / 6.1 with p = P(dist_max)^d; the
+                                 anytime error probability); 0 for an exact answer */
 } momenti_motif;
 
 typedef struct {
@@ -145,6 +171,9 @@ typedef struct {
                                  mem_limit, traversed again one round at a time */
     int32_t step_parts;       /* most parts one repetition was enumerated in (its candidates did
                                  not fit in mem_limit at once); 0 when none was */
+    double fail_bound;        /* the rule's bound for TOP's k-th motif at the last step traversed
+                                 (<= delta, or delta / k, when the rule held; 1 when TOP held
+                                 fewer than k motifs; 0 for an exact answer) */
 } momenti_report;
 
 /* Fill *o with the defaults (K = 8, L = 200, r estimated, F32 projection,
@@ -206,6 +235,22 @@ int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_
  * it needs). */
 int momenti_search_noalloc(momenti_plan* p, int32_t d, int32_t k, double delta, momenti_motif* out,
                            int32_t* n_out, momenti_report* rep);
+
+/* Several dimensionalities in one traversal (section 6.3): the top-k motifs
+ * of every d in [d_lo, d_hi] (1 <= d_lo <= d_hi <= D). Each d has its own
+ * pool; one verification of a candidate gives its distance for every d, and
+ * the index is enumerated for the smallest d not yet answered, so a d stops
+ * at the same step, with the same answer, as momenti_search(p, d, ...) with
+ * the same plan (single-round traversal; the pairs counted are the same).
+ * out (caller-owned, (d_hi - d_lo + 1) * k motifs) receives d's motifs at
+ * offset (d - d_lo) * k; n_out[d - d_lo] their count; status[d - d_lo] what
+ * momenti_search would return for d (MOMENTI_OK, _OK_FALLBACK or
+ * _OK_PARTIAL); reps (NULL or one report per d) the report of d. Options
+ * as momenti_search (max_steps and max_ms end every open d at once;
+ * max_pairs and tracing are not applied). Returns MOMENTI_OK or an error
+ * (E_STATE also for a plan in scratch mode). */
+int momenti_search_multi(momenti_plan* p, int32_t d_lo, int32_t d_hi, int32_t k, double delta,
+                         momenti_motif* out, int32_t* n_out, int32_t* status, momenti_report* reps);
 
 /* One call: prepare + hash + search + destroy. Arguments as above. */
 int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_t w, int32_t d,

@@ -589,7 +589,9 @@ double orc_collision_prob(double R, double r)
     return 1.0 - 2.0 * Phi - 2.0 / (sqrt(2.0 * M_PI) * t) * (1.0 - exp(-(t * t) / 2.0));
 }
 
-enum { ORC_STOP_TENSOR = 0, ORC_STOP_LEMMA52 = 1, ORC_STOP_TENSOR_LITERAL = 2 };
+enum { ORC_STOP_TENSOR = 0, ORC_STOP_LEMMA52 = 1, ORC_STOP_TENSOR_LITERAL = 2, ORC_STOP_RIGOROUS = 3 };
+
+
 
 /* Failure bound after J repetitions of round i.
  * rule TENSOR: Lemma 6.1 with P_t(i', J') = (1 - p^ceil(i'))^(J' div m) *
@@ -612,8 +614,100 @@ static double tfactor(double p, int32_t c, int64_t e, int32_t rule)
     return powi_(1.0 - powi_(p, c), e);
 }
 
+/* A bound on the failure probability under tensoring that follows from the
+ * index's structure itself (rule RIGOROUS; the printed Lemma 6.1 multiplies
+ * over repetitions that share half-functions, which are not independent).
+ * Repetition j uses left function l = j div m and right function r = j mod m;
+ * at prefix length i it collides on the pair (in the d dimensions of its
+ * dist_max) when the left function's first ceil(i/2) symbols and the right
+ * function's first floor(i/2) symbols all collide. Each symbol collides with
+ * probability >= p = P(dist_max)^d, independently of every other symbol, so
+ * the collision depth of each half-function is at least a geometric depth G
+ * with P(G >= s) = p^s; failure only becomes likelier when depths shrink, so
+ * the probability of failure with exactly these depths bounds it. Failure
+ * after J repetitions of round i (below round K, after every repetition of
+ * round i+1 too): no repetition j < J collides at prefix i and no repetition
+ * j >= J at prefix i+1 (a collision at i+1 is one at i). Conditioned on
+ * which right functions reach the two depths, the left functions are
+ * independent, which gives the sum below over the states of a few column
+ * ranges. */
+static double seg_state_prob(int st, int64_t len, double qx, double qy)
+{
+    /* st 0: no right function of the range reaches depth b (prob of each: qx);
+     * 1: some reach b, none b' (qy); 2: some reach b' (b' >= b) */
+    double none_x = powi_(1.0 - qx, len), none_y = powi_(1.0 - qy, len);
+    if (st == 0) return none_x;
+    if (st == 1) return none_y - none_x;
+    return 1.0 - none_y;
+}
+
+static double rigorous_bound(double p, int32_t i, int32_t J, int32_t K, int32_t L)
+{
+    int32_t m = (int32_t)ceil_sqrt(L);
+    int32_t nl = (L + m - 1) / m;
+    int32_t a = (i + 1) / 2, b = i / 2;            /* left / right symbols at prefix i */
+    int32_t a2 = (i + 2) / 2, b2 = (i + 1) / 2;    /* at prefix i + 1 */
+    int deeper = i < K;
+    double qx = powi_(p, b), qy = deeper ? powi_(p, b2) : 0.0;
+    double keep_a = 1.0 - powi_(p, a), keep_a2 = 1.0 - powi_(p, a2);
+    /* column ranges cut at c = J mod m and at the lengths of the rows */
+    int32_t lstar = J / m, c = J % m;
+    int32_t len_last = L - (nl - 1) * m;
+    int32_t cuts[6] = {0, c, m, len_last, 0, 0};
+    int32_t ncut = 4;
+    /* the partial row's length */
+    int32_t len_star = lstar < nl ? (lstar == nl - 1 ? len_last : m) : 0;
+    cuts[ncut++] = len_star;
+    /* sort and dedupe */
+    for (int32_t u = 1; u < ncut; ++u)
+        for (int32_t v = u; v > 0 && cuts[v - 1] > cuts[v]; --v) {
+            int32_t t = cuts[v]; cuts[v] = cuts[v - 1]; cuts[v - 1] = t;
+        }
+    int32_t seg_lo[5], seg_hi[5], nseg = 0;
+    for (int32_t u = 0; u + 1 < ncut; ++u)
+        if (cuts[u + 1] > cuts[u]) {
+            seg_lo[nseg] = cuts[u];
+            seg_hi[nseg] = cuts[u + 1];
+            ++nseg;
+        }
+    int64_t nstates = 1;
+    for (int32_t u = 0; u < nseg; ++u) nstates *= 3;
+    double total = 0.0;
+    for (int64_t code = 0; code < nstates; ++code) {
+        int32_t st[5];
+        int64_t cc = code;
+        double pr = 1.0;
+        for (int32_t u = 0; u < nseg; ++u) {
+            st[u] = (int32_t)(cc % 3);
+            cc /= 3;
+            pr *= seg_state_prob(st[u], seg_hi[u] - seg_lo[u], qx, qy);
+        }
+        if (pr == 0.0) continue;
+        /* for every row: does some right function of its prefix-i columns reach
+         * depth b (fx), of its prefix-(i+1) columns depth b' (fy)? */
+        double rows = 1.0;
+        for (int32_t l = 0; l < nl; ++l) {
+            int32_t len = l == nl - 1 ? len_last : m;
+            int32_t xi_hi = l < lstar ? len : (l == lstar ? c : 0);   /* columns [0, xi_hi) at prefix i */
+            int32_t yi_lo = xi_hi, yi_hi = deeper ? len : xi_hi;       /* columns [yi_lo, yi_hi) at i + 1 */
+            int fx = 0, fy = 0;
+            for (int32_t u = 0; u < nseg; ++u) {
+                if (seg_lo[u] < xi_hi && st[u] >= 1) fx = 1;            /* ranges never straddle a cut */
+                if (seg_lo[u] >= yi_lo && seg_lo[u] < yi_hi && st[u] == 2) fy = 1;
+            }
+            double ok = 1.0;
+            if (fx) ok = keep_a;                 /* the left function must stay below depth a */
+            else if (fy) ok = keep_a2;           /* ... below depth a' only */
+            rows *= ok;
+        }
+        total += pr * rows;
+    }
+    return total;
+}
+
 double orc_fail_bound(double p, int32_t i, int32_t J, int32_t K, int32_t L, int32_t rule)
 {
+    if (rule == ORC_STOP_RIGOROUS) return rigorous_bound(p, i, J, K, L);
     if (rule == ORC_STOP_LEMMA52) {
         double v = powi_(1.0 - powi_(p, i), J);
         if (i < K) v = v * powi_(1.0 - powi_(p, i + 1), L - J);

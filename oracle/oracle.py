@@ -17,7 +17,7 @@ __all__ = [
     "build", "lib", "philox", "gauss", "uniform", "window_stats", "stats", "dist", "distd",
     "topk_exact", "topk_exact_sweep", "tensor_shape", "L_used", "draw_projections", "estimate_r", "hash_dim",
     "hash_one", "hash_all", "pack", "prefix", "collision_prob", "fail_bound", "stop", "lsh_search",
-    "lsh_pipeline", "STOP_TENSOR", "STOP_LEMMA52", "STOP_TENSOR_LITERAL", "FLAT_REL", "round_fmt", "round_fmt_array", "hash_dim_lowp", "FMT",
+    "lsh_pipeline", "STOP_TENSOR", "STOP_LEMMA52", "STOP_TENSOR_LITERAL", "STOP_RIGOROUS", "FLAT_REL", "round_fmt", "round_fmt_array", "hash_dim_lowp", "FMT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,6 +30,7 @@ _LIB_OMP = os.path.join(_HERE, "_build", "libmomenti_oracle_omp.so")
 STOP_TENSOR = 0
 STOP_LEMMA52 = 1
 STOP_TENSOR_LITERAL = 2
+STOP_RIGOROUS = 3
 FLAT_REL = 1e-8
 
 

@@ -9,16 +9,19 @@
 namespace mm {
 
 // A candidate pair (a < b) emitted by the traversal, tagged with the
-// repetition j and the round (prefix length) i that produced it.
+// repetition j, the round (prefix length) i that produced it and the number
+// W of dimensions it collided in there.
 struct Cand {
-    uint32_t a, b, j, pad;   // pad: round i
+    uint32_t a, b, j, pad;   // pad: round i | W << 8
 };
+__host__ __device__ inline int tag_round(uint32_t pad) { return (int)(pad & 0xFFu); }
+__host__ __device__ inline int tag_weight(uint32_t pad) { return (int)(pad >> 8); }
 
 // A verified pair: dist_d (definition "d-dimensional distance"), dist_max
 // (Eq. distdmax), the chosen dimensions and the repetition that produced it.
 struct VRec {
     double dist_d, dist_max;
-    uint32_t a, b, j, pad;   // pad: round i
+    uint32_t a, b, j, pad;   // pad: round i | W << 8 (as in Cand)
     uint64_t dims[2];
 };
 static_assert(sizeof(VRec) == 48, "VRec layout");
@@ -67,7 +70,8 @@ struct ReplayCtl {
     uint32_t n_keep;
     int32_t K, L, s0, nsteps;
     int32_t dropped;     // set by the filter when it left out a record (the pool was full)
-    int32_t pad[2];
+    int32_t wmin;        // records with a weight W below this are not for this pool
+    int32_t pad;
     uint32_t step_count[kMaxSteps];
     uint32_t step_off[kMaxSteps + 1];
 };
@@ -105,6 +109,9 @@ struct StepGeom {
     int hashed;          // 1: sorted by a 24-bit hash of that prefix instead (equal prefixes
                          // stay adjacent; the rare equal hashes of different prefixes only
                          // add members to a run, and the exact test rejects them)
+    int dhi;             // highest dimensionality searched (several at once, section 6.3): a pair
+                         // is emitted at round i < K while some d in (W_{i+1}, W_i] is at most
+                         // dhi (d itself for one dimensionality); its W_i rides in Cand.pad
     int part, nparts;    // emit only the candidates (a, b) with pair_part(a, b, nparts) == part
                          // (nparts a power of two; 1 = all): a step whose candidates do not fit
                          // in memory at once is enumerated in parts
@@ -156,9 +163,11 @@ hipError_t launch_enum(const StepGeom& g, const SortBufs& b, int buf, const uint
 // segments) that share their length-i prefix, i = 1 .. g.i_lo, for segments
 // sorted by their length-g.i_lo prefix (8 counters, device memory).
 hipError_t launch_probe(const StepGeom& g, const SortBufs& b, int buf, unsigned long long* out, hipStream_t s);
+// Verification of the candidates: for every d in [d, d + nd), record
+// c's dist_d, dist_max and dimensions at out[(d - d0) * cap + c].
 hipError_t launch_verify(const Cand* cand, uint32_t cap, const Counters* cnt, const void* x,
                          int dtype, int64_t n, int64_t ns, int D, int w, int d, const double* mu,
-                         const double* isig, VRec* out, hipStream_t s);
+                         const double* isig, VRec* out, hipStream_t s, int nd = 1);
 // Replay `count` verified records (tagged with round and repetition) in step
 // order through the pool: filter, bucket by step, then one work-group walks
 // the steps of rc->[s0, s0 + nsteps) and writes a snapshot per step. rc must

@@ -634,10 +634,13 @@ __device__ inline void judge_pair(uint32_t a, uint32_t b, const uint32_t* __rest
     for (int lv = nlev - 2; lv >= 0; --lv) {
         const int i = g.i_lo + lv;
         if (i > top) continue;   // rounds i_lo .. min(top, i_hi)
-        if ((int)((atl >> (8 * lv)) & 0xFF) < d || ((blw >> (8 * lv)) & 0xFF) != 0) continue;
-        if (i < g.K && (int)((atl >> (8 * (lv + 1))) & 0xFF) >= d) continue;
+        const int Wi = (int)((atl >> (8 * lv)) & 0xFF);
+        if (Wi < d || ((blw >> (8 * lv)) & 0xFF) != 0) continue;
+        // below round K: skip a pair every dimensionality of (d .. dhi] it counts
+        // for had already at prefix i + 1 (section 6.2)
+        if (i < g.K && (int)((atl >> (8 * (lv + 1))) & 0xFF) >= (Wi < g.dhi ? Wi : g.dhi)) continue;
         const uint32_t pos = atomicAdd(&cnt->n_cand, 1u);
-        if (pos < cap) cand[pos] = Cand{a, b, (uint32_t)j, (uint32_t)i};
+        if (pos < cap) cand[pos] = Cand{a, b, (uint32_t)j, (uint32_t)i | ((uint32_t)Wi << 8)};
     }
 }
 
@@ -1239,7 +1242,7 @@ __global__ __launch_bounds__(256) void k_verify(const Cand* __restrict__ cand, u
                                                 const T* __restrict__ x, int64_t n, int64_t ns,
                                                 int D, int w, int d, const double* __restrict__ mu,
                                                 const double* __restrict__ isig,
-                                                VRec* __restrict__ out)
+                                                VRec* __restrict__ out, int nd)
 {
     __shared__ double sorted[4][kMaxD];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1272,25 +1275,32 @@ __global__ __launch_bounds__(256) void k_verify(const Cand* __restrict__ cand, u
             rank0 += (v < my0) || (v == my0 && fp < lane);
             rank1 += (v < my1) || (v == my1 && fp < lane + 64);
         }
-        const bool sel0 = lane < D && rank0 < d;
-        const bool sel1 = lane + 64 < D && rank1 < d;
-        if (sel0) sorted[wave][rank0] = my0;
-        if (sel1) sorted[wave][rank1] = my1;
-        const uint64_t m0 = __ballot(sel0), m1 = __ballot(sel1);
+        // distances in rank order; for each dimensionality d' in [d, d + nd):
+        // the d' smallest (ties to the lower dimension), their sum in rank
+        // order and the largest of them
+        const int dtop = d + nd - 1;
+        if (lane < D && rank0 < dtop) sorted[wave][rank0] = my0;
+        if (lane + 64 < D && rank1 < dtop) sorted[wave][rank1] = my1;
         wave_sync_lds();
-        if (lane == 0) {
-            double s = 0.0;
-            for (int q = 0; q < d; ++q) s = s + sorted[wave][q];
-            VRec v;
-            v.dist_d = s;
-            v.dist_max = sorted[wave][d - 1];
-            v.a = cd.a;
-            v.b = cd.b;
-            v.j = cd.j;
-            v.pad = cd.pad;
-            v.dims[0] = m0;
-            v.dims[1] = m1;
-            out[c] = v;
+        double s = 0.0;
+        if (lane == 0)
+            for (int q = 0; q < d - 1; ++q) s = s + sorted[wave][q];
+        for (int dd = 0; dd < nd; ++dd) {
+            const int dq = d + dd;
+            const uint64_t m0 = __ballot(lane < D && rank0 < dq), m1 = __ballot(lane + 64 < D && rank1 < dq);
+            if (lane == 0) {
+                s = s + sorted[wave][dq - 1];
+                VRec v;
+                v.dist_d = s;
+                v.dist_max = sorted[wave][dq - 1];
+                v.a = cd.a;
+                v.b = cd.b;
+                v.j = cd.j;
+                v.pad = cd.pad;
+                v.dims[0] = m0;
+                v.dims[1] = m1;
+                out[(size_t)dd * cap + c] = v;
+            }
         }
         wave_sync_lds();
     }
@@ -1298,15 +1308,16 @@ __global__ __launch_bounds__(256) void k_verify(const Cand* __restrict__ cand, u
 
 hipError_t launch_verify(const Cand* cand, uint32_t cap, const Counters* cnt, const void* x,
                          int dtype, int64_t n, int64_t ns, int D, int w, int d, const double* mu,
-                         const double* isig, VRec* out, hipStream_t s)
+                         const double* isig, VRec* out, hipStream_t s, int nd)
 {
+    if (nd < 1 || d + nd - 1 > D) return hipErrorInvalidValue;
     dim3 grid(2048);
     if (dtype == 0)
         hipLaunchKernelGGL(k_verify<double>, grid, dim3(256), 0, s, cand, cap, cnt, (const double*)x,
-                           n, ns, D, w, d, mu, isig, out);
+                           n, ns, D, w, d, mu, isig, out, nd);
     else
         hipLaunchKernelGGL(k_verify<float>, grid, dim3(256), 0, s, cand, cap, cnt, (const float*)x,
-                           n, ns, D, w, d, mu, isig, out);
+                           n, ns, D, w, d, mu, isig, out, nd);
     return hipGetLastError();
 }
 
@@ -1322,7 +1333,7 @@ __device__ inline bool key_less(double da, uint32_t aa, uint32_t ab, double db, 
 // step = (K - i) L + j (rounds descending, repetitions ascending).
 __device__ inline int rec_step(const VRec& r, int K, int L, int s0)
 {
-    return (K - (int)r.pad) * L + (int)r.j - s0;
+    return (K - tag_round(r.pad)) * L + (int)r.j - s0;
 }
 
 // Keep the records that can still enter the pool: all of them while it is
@@ -1340,6 +1351,7 @@ __global__ __launch_bounds__(256) void k_filter(const VRec* __restrict__ rec, ui
         const VRec& r = rec[c];
         const int st = rec_step(r, rc->K, rc->L, rc->s0);
         if (st < 0 || st >= rc->nsteps) continue;   // not a step of this window
+        if (tag_weight(r.pad) < rc->wmin) continue;   // a pair this dimensionality does not count
         if (!full || key_less(r.dist_d, r.a, r.b, thr.dist_d, thr.a, thr.b)) {
             const uint32_t pos = atomicAdd(&rc->n_keep, 1u);
             keep[pos] = c;

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -257,6 +258,10 @@ struct momenti_plan {
     // device's scratch area (bytes = the part used, mem_limit = its size)
     bool arena = false;
     unsigned char* arena_base = nullptr;
+    // several dimensionalities at once: records per candidate (one per d) and
+    // the pool state in use (NULL: the one in the status block)
+    int vsets = 1;
+    PoolState* ps_cur = nullptr;
     int64_t n = 0, ns = 0;
     int D = 0, w = 0, dtype = 1;
     uint64_t mem_limit = 0;
@@ -614,9 +619,11 @@ static int prepare_impl(momenti_plan** out, int64_t n, int32_t D, int32_t w, int
     if (o.L < 1 || o.L > 1024) return fail(MOMENTI_E_ARG, "L=%d outside [1, 1024]", o.L);
     if (o.proj < MOMENTI_PROJ_F64 || o.proj > MOMENTI_PROJ_FP8)
         return fail(MOMENTI_E_ARG, "projection precision %d not available", o.proj);
-    if (o.stop_rule != MOMENTI_STOP_TENSOR && o.stop_rule != MOMENTI_STOP_LEMMA52 &&
-        o.stop_rule != MOMENTI_STOP_TENSOR_LITERAL)
+    if (o.stop_rule < MOMENTI_STOP_TENSOR || o.stop_rule > MOMENTI_STOP_RIGOROUS)
         return fail(MOMENTI_E_ARG, "bad stop rule %d", o.stop_rule);
+    if (o.delta_mode != MOMENTI_DELTA_PER_MOTIF && o.delta_mode != MOMENTI_DELTA_JOINT)
+        return fail(MOMENTI_E_ARG, "bad delta mode %d", o.delta_mode);
+    if (!std::isfinite(o.max_ms)) return fail(MOMENTI_E_ARG, "max_ms must be finite");
     if (!std::isfinite(o.r_scale) || !std::isfinite(o.max_pairs) || !std::isfinite(o.r) ||
         !std::isfinite(o.merge_pairs))
         return fail(MOMENTI_E_ARG, "r, r_scale, merge_pairs and max_pairs must be finite");
@@ -931,14 +938,69 @@ static double log_term(double logp, int c, int64_t e, bool empty_half_is_one = f
     return (double)e * std::log1p(-pc);
 }
 
-// Algorithm 2: stop when the bound on never having seen a pair at the k-th
-// motif's dist_max is at most delta. TENSOR: Lemma 6.1; LEMMA52: Lemma 5.2.
-static bool stop_holds(double dist_max, double r, int d, int i, int J, int K, int L, int m, int rule,
-                       double delta)
+// RIGOROUS rule: the failure probability of the tensored index with every
+// half-function collapsed to a geometric collision depth (P(depth >= s) =
+// p^s, each symbol colliding independently with probability p). Repetition
+// j pairs left function j div m with right function j mod m; at prefix length
+// i' it collides when the left depth reaches ceil(i'/2) and the right depth
+// floor(i'/2). Failure after J repetitions of round i: none of repetitions
+// 0 .. J-1 collides at i and (below round K) none of J .. L-1 at i + 1. Given
+// which right functions reach depth floor(i/2) (and floor((i+1)/2)), the left
+// functions decide independently, row by row; the right functions are
+// summarised per column range between the row boundaries.
+static double rigorous_fail(double p, int i, int J, int K, int L, int m)
+{
+    const int nl = (L + m - 1) / m, tail = L - (nl - 1) * m;   // rows; length of the last row
+    const bool next = i < K;
+    const double reach_b = std::pow(p, i / 2), reach_b1 = next ? std::pow(p, (i + 1) / 2) : 0.0;
+    const double below_a = 1.0 - std::pow(p, (i + 1) / 2), below_a1 = 1.0 - std::pow(p, (i + 2) / 2);
+    const int rows_i = J / m, cols_i = J % m;   // rows wholly at prefix i; prefix-i columns of the next row
+    auto row_len = [&](int l) { return l == nl - 1 ? tail : m; };
+    int edge[5] = {0, cols_i, tail, m, rows_i < nl ? row_len(rows_i) : 0};
+    std::sort(edge, edge + 5);
+    int lo[4], len[4], ns = 0;
+    for (int u = 0; u + 1 < 5; ++u)
+        if (edge[u + 1] > edge[u]) { lo[ns] = edge[u]; len[ns] = edge[u + 1] - edge[u]; ++ns; }
+    double total = 0.0;
+    int state[4] = {0, 0, 0, 0};   // per range: 0 none reaches b; 1 some reach b, none b'; 2 some reach b'
+    for (;;) {
+        double pr = 1.0;
+        for (int u = 0; u < ns && pr > 0.0; ++u) {
+            const double none_b = std::pow(1.0 - reach_b, len[u]), none_b1 = std::pow(1.0 - reach_b1, len[u]);
+            pr *= state[u] == 0 ? none_b : state[u] == 1 ? none_b1 - none_b : 1.0 - none_b1;
+        }
+        if (pr > 0.0) {
+            for (int l = 0; l < nl; ++l) {
+                const int n = row_len(l);
+                const int xi = l < rows_i ? n : (l == rows_i ? std::min(cols_i, n) : 0);   // [0, xi) at prefix i
+                bool hit_i = false, hit_i1 = false;
+                for (int u = 0; u < ns; ++u) {
+                    if (lo[u] < xi && state[u] >= 1) hit_i = true;
+                    if (next && lo[u] >= xi && lo[u] < n && state[u] == 2) hit_i1 = true;
+                }
+                pr *= hit_i ? below_a : hit_i1 ? below_a1 : 1.0;
+            }
+            total += pr;
+        }
+        int u = 0;
+        while (u < ns && ++state[u] == 3) state[u++] = 0;
+        if (u == ns) break;
+    }
+    return total;
+}
+
+// The stopping rule's bound on having never seen, in >= d dimensions, a pair
+// at distance dist_max after J repetitions of round i (natural log; -inf when
+// 0). TENSOR: Lemma 6.1; LEMMA52: Lemma 5.2; RIGOROUS: rigorous_fail.
+static double log_fail(double dist_max, double r, int d, int i, int J, int K, int L, int m, int rule)
 {
     const double P = collision_probability(dist_max, r);
-    if (!(P > 0.0)) return false;
+    if (!(P > 0.0)) return 0.0;
     const double logp = (double)d * std::log(P);   // p = P^d
+    if (rule == MOMENTI_STOP_RIGOROUS) {
+        const double v = rigorous_fail(std::exp(logp), i, J, K, L, m);
+        return v > 0.0 ? std::log(v) : -INFINITY;
+    }
     double lf;
     if (rule == MOMENTI_STOP_LEMMA52) {
         lf = log_term(logp, i, J);
@@ -951,12 +1013,20 @@ static bool stop_holds(double dist_max, double r, int d, int i, int J, int K, in
             lf += log_term(logp, (i + 2) / 2, J2 / m, e1) + log_term(logp, (i + 1) / 2, J2 % m, e1);
         }
     }
-    return lf <= std::log(delta);
+    return lf;
+}
+
+// Algorithm 2: stop when the bound on never having seen a pair at the k-th
+// motif's dist_max is at most delta.
+static bool stop_holds(double dist_max, double r, int d, int i, int J, int K, int L, int m, int rule,
+                       double delta)
+{
+    return log_fail(dist_max, r, d, i, J, K, L, m, rule) <= std::log(delta);
 }
 
 // ------------------------------------------------------------------ search
 static Counters* st_counters(momenti_plan* p) { return (Counters*)p->status; }
-static PoolState* st_pool(momenti_plan* p) { return (PoolState*)(p->status + 64); }
+static PoolState* st_pool(momenti_plan* p) { return p->ps_cur ? p->ps_cur : (PoolState*)(p->status + 64); }
 
 // double-buffered keys and indices and digit histograms of reps * Ds
 // segments, and the two fingerprint rows of reps repetitions
@@ -966,7 +1036,7 @@ static size_t sort_bytes(int64_t reps, int64_t Ds, int64_t D, int64_t ns, int64_
            (size_t)reps * ns * 4 * (fp_words((int)D) + fq_words((int)D)) +
            (size_t)units_bound(reps * Ds, ns) * sizeof(RunRec);
 }
-static size_t cand_bytes(uint32_t cap) { return (size_t)cap * (sizeof(Cand) + sizeof(VRec)); }
+static size_t cand_bytes(uint32_t cap, int vsets = 1) { return (size_t)cap * (sizeof(Cand) + vsets * sizeof(VRec)); }
 static size_t store_bytes(uint32_t cap) { return (size_t)cap * (sizeof(VRec) + 8); }
 
 static int alloc_sort(momenti_plan* p, int reps, int Ds)
@@ -994,11 +1064,11 @@ static int alloc_sort(momenti_plan* p, int reps, int Ds)
 static int alloc_cand(momenti_plan* p, uint32_t cap)
 {
     dfree(p, p->cand, (size_t)p->cap * sizeof(Cand));
-    dfree(p, p->vrec, (size_t)p->cap * sizeof(VRec));
+    dfree(p, p->vrec, (size_t)p->cap * p->vsets * sizeof(VRec));
     p->cand = nullptr; p->vrec = nullptr; p->cap = 0;
     int rc;
     if ((rc = dalloc_t(p, &p->cand, (size_t)cap * sizeof(Cand)))) return rc;
-    if ((rc = dalloc_t(p, &p->vrec, (size_t)cap * sizeof(VRec)))) return rc;
+    if ((rc = dalloc_t(p, &p->vrec, (size_t)cap * p->vsets * sizeof(VRec)))) return rc;
     p->cap = cap;
     return MOMENTI_OK;
 }
@@ -1074,13 +1144,13 @@ static int grow_pool(momenti_plan* p, int P, int k, int steps)
 // Replay `count` verified records at `rec` (tagged with round and repetition)
 // through the pool for steps [s0, s0 + nsteps); snapshots land in p->snaps.
 static int replay(momenti_plan* p, const VRec* rec, uint32_t count, uint32_t* keep, int k, int s0,
-                  int nsteps)
+                  int nsteps, int wmin = 0)
 {
     HIP_OK(launch_zero(p->rctl, offsetof(ReplayCtl, step_count) + (size_t)nsteps * 4, p->st));
     struct {
         uint32_t n_keep;
-        int32_t K, L, s0, nsteps;
-    } hdr = {0u, p->K, p->L, s0, nsteps};
+        int32_t K, L, s0, nsteps, dropped, wmin;
+    } hdr = {0u, p->K, p->L, s0, nsteps, 0, wmin};
     HIP_OK(hipMemcpyAsync(p->rctl, &hdr, sizeof hdr, hipMemcpyHostToDevice, p->st));
     HIP_OK(timed(p, KI_POOL, 0.0, 0.0, [&] {
         return launch_replay(rec, count, keep, keep + std::max<uint32_t>(count, 1u), p->rctl, st_pool(p),
@@ -1101,6 +1171,7 @@ static void to_motifs(const std::vector<VRec>& v, int count, momenti_motif* out)
         out[s].dist_max = v[s].dist_max;
         out[s].dims[0] = v[s].dims[0];
         out[s].dims[1] = v[s].dims[1];
+        out[s].fail_prob = 0.0;   // exact unless the search sets its bound
     }
 }
 
@@ -1134,6 +1205,8 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     if (d < 1 || d > p->D) return fail(MOMENTI_E_ARG, "d=%d outside [1, D=%d]", d, p->D);
     if (k < 1 || k > 4096) return fail(MOMENTI_E_ARG, "k=%d outside [1, 4096]", k);
     if (!(delta > 0.0 && delta < 1.0)) return fail(MOMENTI_E_ARG, "delta=%g outside (0, 1)", delta);
+    // Lemma 5.4: all k motifs at once with probability >= 1 - delta
+    const double delta_rule = p->o.delta_mode == MOMENTI_DELTA_JOINT ? delta / k : delta;
     *n_out = 0;
     const auto t0 = std::chrono::steady_clock::now();
     momenti_report R{};
@@ -1168,7 +1241,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     const int Ds = std::max(1, p->D - d + 1);
     const uint64_t left0 = p->mem_limit - p->bytes;
     uint32_t cap = 1u << 20;
-    while (cap > (1u << 14) && cand_bytes(cap) + store_bytes(cap) + sort_bytes(1, Ds, p->D, p->ns, tiles) > left0)
+    while (cap > (1u << 14) && cand_bytes(cap, p->vsets) + store_bytes(cap) + sort_bytes(1, Ds, p->D, p->ns, tiles) > left0)
         cap >>= 1;
     if ((rc = alloc_cand(p, cap))) return rc;
     if ((rc = grow_store(p, cap, 0))) return rc;
@@ -1202,6 +1275,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         StepGeom g;
         g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
         g.j0 = 0; g.Ds = Ds; g.nseg = Dp; g.i = p->K; g.K = p->K; g.i_lo = p->K; g.hashed = 0;
+        g.dhi = d; g.part = 0; g.nparts = 1;
         int buf = 0;
         const double elems = (double)Dp * p->ns, kb = p->K <= 4 ? 4.0 : 8.0;
         for (int pass = 0; pass < p->K; ++pass) {
@@ -1233,6 +1307,15 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         std::fprintf(stderr, "\n");
     }
 
+    // The failure bound of each returned motif at step (i, J) of the traversal
+    // (1 before any step), and the k-th's in the report.
+    auto annotate = [&](int count, int i, int J) {
+        for (int q = 0; q < count; ++q)
+            out[q].fail_prob = i > 0 ? std::exp(log_fail(out[q].dist_max, p->r, d, i, J, p->K, p->L, p->m,
+                                                         p->o.stop_rule)) : 1.0;
+        R.fail_bound = count >= k ? out[k - 1].fail_prob : 1.0;
+    };
+    int last_i = 0, last_J = 0;   // the last step whose TOP is known
     const bool tracing = p->tr_cand || p->tr_top_size;
     if (p->tr_count) *p->tr_count = 0;
     if (p->tr_top_size)
@@ -1246,7 +1329,8 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
     // Steps [s0, s0 + nsteps) have just been replayed: record the trace, then
     // test the stopping rule after each step in order. Returns 1 when it
     // held (out and rep filled), 2 when the pool must grow and the search
-    // restart, 0 to go on, or an error code.
+    // restart, 3 when a step or time budget ended the search (out and rep
+    // filled with TOP at that step), 0 to go on, or an error code.
     auto check_steps = [&](int s0, int nsteps) -> int {
         if (tracing && p->tr_top_size) {
             hsnap.resize((size_t)nsteps * k);
@@ -1275,13 +1359,16 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
                 if ((e = grow_pool(p, P, k, max_steps))) return e;
                 return 2;
             }
+            last_i = i;
+            last_J = J;
             if (sn.top_n == k &&
-                stop_holds(sn.dist_max, p->r, d, i, J, p->K, p->L, p->m, p->o.stop_rule, delta)) {
+                stop_holds(sn.dist_max, p->r, d, i, J, p->K, p->L, p->m, p->o.stop_rule, delta_rule)) {
                 std::vector<VRec> tv(k);
                 HIP_OK(copy_sync(p, tv.data(), p->snap_tops + (size_t)st * k, (size_t)k * sizeof(VRec),
                                  hipMemcpyDeviceToHost));
                 to_motifs(tv, k, out);
                 *n_out = k;
+                annotate(k, i, J);
                 R.i_stop = i;
                 R.j_stop = J;
                 if (verbose)
@@ -1291,6 +1378,23 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
                 R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                 if (rep) *rep = R;
                 return 1;
+            }
+            // anytime budgets: TOP as it stands after this step, with its bounds
+            const double elapsed = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if ((p->o.max_steps > 0 && R.n_steps >= p->o.max_steps) || (p->o.max_ms > 0.0 && elapsed >= p->o.max_ms)) {
+                const int nt = std::min(sn.top_n, k);
+                std::vector<VRec> tv(std::max(nt, 1));
+                if (nt)
+                    HIP_OK(copy_sync(p, tv.data(), p->snap_tops + (size_t)st * k, (size_t)nt * sizeof(VRec),
+                                     hipMemcpyDeviceToHost));
+                to_motifs(tv, nt, out);
+                *n_out = nt;
+                annotate(nt, i, J);
+                R.budget_round = i;
+                R.peak_bytes = p->peak;
+                R.t_search_ms = elapsed;
+                if (rep) *rep = R;
+                return 3;
             }
         }
         return 0;
@@ -1321,6 +1425,7 @@ restart:
                 to_motifs(tv, nt, out);
             }
             *n_out = nt;
+            annotate(nt, last_i, last_J);
             if (verbose)
                 std::fprintf(stderr, "[momenti] budget: rounds %d..%d estimated at %.3g pairs > %.3g; %d motifs so far\n",
                              i_hi, i_lo, pairs_est[i_lo], p->o.max_pairs, nt);
@@ -1350,6 +1455,7 @@ restart:
             g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
             g.j0 = j0; g.Ds = Ds; g.nseg = Bc * Ds; g.i = i_hi; g.K = p->K; g.i_lo = i_lo;
             g.hashed = i_lo > 4;   // longer prefixes are grouped by a 24-bit hash (3 passes)
+            g.dhi = d;
             g.part = 0; g.nparts = 1;
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
@@ -1416,7 +1522,7 @@ restart:
                     // a single-round group replays each batch from the store, whose
                     // capacity must stay >= the candidate buffer's
                     const bool grow_st = incremental && need > p->store_cap;
-                    const uint64_t extra = cand_bytes(need) - cand_bytes(p->cap) + (grow_st ? store_bytes(need) : 0);
+                    const uint64_t extra = cand_bytes(need, p->vsets) - cand_bytes(p->cap, p->vsets) + (grow_st ? store_bytes(need) : 0);
                     if (need >= cnt.n_cand && extra <= p->mem_limit - p->bytes) {
                         const uint32_t old_cap = p->cap;
                         rc = alloc_cand(p, need);
@@ -1467,7 +1573,7 @@ restart:
                     hcand.resize(cnt.n_cand);
                     HIP_OK(copy_sync(p, hcand.data(), p->cand, cnt.n_cand * sizeof(Cand), hipMemcpyDeviceToHost));
                     for (const Cand& c : hcand) {
-                        const int64_t s = (int64_t)(p->K - (int)c.pad) * p->L + c.j;
+                        const int64_t s = (int64_t)(p->K - tag_round(c.pad)) * p->L + c.j;
                         if (*p->tr_count < p->tr_cap) {
                             p->tr_cand[3 * *p->tr_count + 0] = s;
                             p->tr_cand[3 * *p->tr_count + 1] = c.a;
@@ -1487,6 +1593,7 @@ restart:
                 const int cs = check_steps(s0 + j0, Bc);
                 if (cs < 0) return cs;
                 if (cs == 1) return MOMENTI_OK;
+                if (cs == 3) return MOMENTI_OK_PARTIAL;
                 if (cs == 2) goto restart;
             }
             j0 += Bc;
@@ -1508,11 +1615,13 @@ restart:
             const int cs = check_steps(s0, nsteps);
             if (cs < 0) return cs;
             if (cs == 1) return MOMENTI_OK;
+            if (cs == 3) return MOMENTI_OK_PARTIAL;
             if (cs == 2) goto restart;
         }
     }
     rc = exact_fallback(p, d, k, out, n_out, &R);
     R.fallback = 1;
+    R.fail_bound = 0.0;   // the exact answer
     R.peak_bytes = p->peak;
     R.t_search_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (rep) *rep = R;
@@ -1734,6 +1843,292 @@ static int exact_sweep(momenti_plan* p, int d, int k, momenti_motif* out, int32_
         theta = topn >= k ? kth + 4.0 * eps : 2.0 * theta_min;
     }
     return fail(MOMENTI_E_DEVICE, "exact answer: the sweep did not certify its result");
+}
+
+// ------------------------------------------------------------------ several dimensionalities
+// Section 6.3: one traversal answers every dimensionality d in [d_lo, d_hi].
+// Each d has its own pool of verified pairs; one verification of a candidate
+// gives its dist_d for every d (the d smallest per-dimension distances are a
+// prefix of the same ranking). Pool d takes the candidates that collided in
+// >= d dimensions, so after every step it holds the pairs a search for d
+// alone holds, and d stops at that search's step with its answer. The
+// enumeration follows the smallest d not yet answered (d_cur): fewer
+// dimensions then count for nothing. Rounds are traversed one at a time,
+// each batch of repetitions replayed into every open pool as it is verified.
+struct PoolSet {
+    VRec *pools = nullptr, *top = nullptr, *snap_tops = nullptr;
+    Snap *snaps = nullptr, *host_snaps = nullptr;
+    int P = 0, top_k = 0, steps = 0, snap_k = 0;
+    PoolState* ps = nullptr;
+};
+
+static void pool_in(momenti_plan* p, const PoolSet& q)
+{
+    p->pools = q.pools; p->P = q.P; p->top = q.top; p->top_k = q.top_k; p->snaps = q.snaps;
+    p->snap_tops = q.snap_tops; p->snap_steps = q.steps; p->snap_k = q.snap_k; p->host_snaps = q.host_snaps;
+    p->ps_cur = q.ps;
+}
+
+static void pool_out(momenti_plan* p, PoolSet& q)
+{
+    q.pools = p->pools; q.P = p->P; q.top = p->top; q.top_k = p->top_k; q.snaps = p->snaps;
+    q.snap_tops = p->snap_tops; q.steps = p->snap_steps; q.snap_k = p->snap_k; q.host_snaps = p->host_snaps;
+    p->pools = nullptr; p->top = nullptr; p->snaps = nullptr; p->snap_tops = nullptr; p->host_snaps = nullptr;
+    p->P = p->top_k = p->snap_steps = p->snap_k = 0;
+    p->ps_cur = nullptr;
+}
+
+extern "C" int momenti_search_multi(momenti_plan* p, int32_t d_lo, int32_t d_hi, int32_t k, double delta,
+                                    momenti_motif* out, int32_t* n_out, int32_t* status, momenti_report* reps)
+{
+    g_err.clear();
+    if (!p || !out || !n_out || !status) return fail(MOMENTI_E_ARG, "NULL argument");
+    if (!p->hashed) return fail(MOMENTI_E_STATE, "momenti_hash has not been called");
+    if (d_lo < 1 || d_hi > p->D || d_lo > d_hi)
+        return fail(MOMENTI_E_ARG, "dimensionalities [%d, %d] outside [1, D=%d]", d_lo, d_hi, p->D);
+    if (k < 1 || k > 4096) return fail(MOMENTI_E_ARG, "k=%d outside [1, 4096]", k);
+    if (!(delta > 0.0 && delta < 1.0)) return fail(MOMENTI_E_ARG, "delta=%g outside (0, 1)", delta);
+    if (p->arena) return fail(MOMENTI_E_STATE, "not available without allocations");
+    const int nd = d_hi - d_lo + 1;
+    if (nd == 1) {
+        momenti_report R{};
+        const int rc = momenti_search(p, d_lo, k, delta, out, n_out, &R);
+        if (rc < 0) return rc;
+        status[0] = rc;
+        if (reps) reps[0] = R;
+        return MOMENTI_OK;
+    }
+    const double delta_rule = p->o.delta_mode == MOMENTI_DELTA_JOINT ? delta / k : delta;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int q = 0; q < nd; ++q) {
+        n_out[q] = 0;
+        status[q] = -1;   // not answered yet
+    }
+    struct Recycle {
+        momenti_plan* p;
+        ~Recycle() { p->recycle = false; p->vsets = 1; p->ps_cur = nullptr; }
+    } recycling{p};
+    p->recycle = true;
+    release_search(p);
+    p->vsets = nd;
+    std::vector<PoolSet> sets(nd);
+    PoolState* ps_block = nullptr;
+    // every allocation of this search, freed before returning (the pools are
+    // not kept from one search to the next)
+    auto release_sets = [&]() {
+        for (auto& q : sets) {
+            pool_in(p, q);
+            dfree(p, p->pools, (size_t)2 * p->P * sizeof(VRec));
+            dfree(p, p->top, (size_t)p->top_k * sizeof(VRec));
+            dfree(p, p->snaps, (size_t)p->snap_steps * sizeof(Snap));
+            dfree(p, p->snap_tops, (size_t)p->snap_steps * p->snap_k * sizeof(VRec));
+            host_free(p, p->host_snaps);
+            p->pools = p->top = p->snap_tops = nullptr; p->snaps = p->host_snaps = nullptr;
+            p->P = p->top_k = p->snap_steps = p->snap_k = 0;
+            q = PoolSet{};
+        }
+        p->ps_cur = nullptr;
+        dfree(p, ps_block, (size_t)nd * sizeof(PoolState));
+        ps_block = nullptr;
+    };
+    struct Guard {
+        std::function<void()> f;
+        ~Guard() { f(); }
+    } guard{release_sets};
+    int rc;
+    int B = std::max(1, std::min({p->o.batch_reps ? p->o.batch_reps : 16, p->L, 64}));
+    int P = p->o.pool_size ? p->o.pool_size : std::max(4096, 128 * k);
+    P = std::max(P, k);
+    if ((rc = dalloc_t(p, &p->status, 4096))) return rc;
+    if ((rc = dalloc_t(p, &p->rctl, sizeof(ReplayCtl)))) return rc;
+    if ((rc = dalloc_t(p, &ps_block, (size_t)nd * sizeof(PoolState)))) return rc;
+    if (!host_alloc(p, (void**)&p->host_status, 4096)) return fail(MOMENTI_E_NOMEM, "host staging allocation failed");
+    for (int q = 0; q < nd; ++q) {
+        if ((rc = alloc_pool(p, P, k, B))) return rc;
+        pool_out(p, sets[q]);
+        sets[q].ps = ps_block + q;
+    }
+    const int64_t tiles = (p->ns + kSortTile - 1) / kSortTile;
+    const int Ds_max = std::max(1, p->D - d_lo + 1);
+    const uint64_t left0 = p->mem_limit - p->bytes;
+    uint32_t cap = 1u << 20;
+    while (cap > (1u << 14) && cand_bytes(cap, nd) + store_bytes(cap) + sort_bytes(1, Ds_max, p->D, p->ns, tiles) > left0)
+        cap >>= 1;
+    if ((rc = alloc_cand(p, cap))) return rc;
+    if ((rc = grow_store(p, cap, 0))) return rc;   // its keep half orders each replay
+    while (B > 1 && sort_bytes(B, Ds_max, p->D, p->ns, tiles) > p->mem_limit - p->bytes) B >>= 1;
+    if ((rc = alloc_sort(p, B, Ds_max))) return rc;
+    {
+        StepGeom gmax{};
+        gmax.ns = p->ns;
+        gmax.nseg = B * Ds_max;
+        p->coll_parts = enum_partials(gmax);
+        if ((rc = dalloc_t(p, &p->coll_part, (size_t)p->coll_parts * 24))) return rc;
+    }
+    if (p->cache == &p->own_cache) {
+        p->own_cache.trim();
+        p->recycle = false;
+    }
+    std::vector<momenti_report> R(nd);
+    for (auto& r : R) {
+        r.K = p->K; r.L_used = p->L; r.r = p->r; r.t_hash_ms = p->t_hash_ms; r.batch_reps = B;
+        r.first_group_lo = p->K;
+    }
+    int64_t n_steps = 0, n_coll = 0, n_cand = 0;
+    auto elapsed = [&]() { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); };
+    // answer for dimensionality index q from pool q at (i, J): TOP of snapshot st
+    auto answer = [&](int q, int st, int i, int J, int code) -> int {
+        PoolSet& ps = sets[q];
+        const Snap& sn = ps.host_snaps[st];
+        const int nt = std::min(sn.top_n, k), dq = d_lo + q;
+        std::vector<VRec> tv(std::max(nt, 1));
+        if (nt)
+            HIP_OK(copy_sync(p, tv.data(), ps.snap_tops + (size_t)st * k, (size_t)nt * sizeof(VRec), hipMemcpyDeviceToHost));
+        momenti_motif* o = out + (size_t)q * k;
+        to_motifs(tv, nt, o);
+        for (int u = 0; u < nt; ++u)
+            o[u].fail_prob = std::exp(log_fail(o[u].dist_max, p->r, dq, i, J, p->K, p->L, p->m, p->o.stop_rule));
+        n_out[q] = nt;
+        status[q] = code;
+        R[q].fail_bound = nt >= k ? o[k - 1].fail_prob : 1.0;
+        if (code == MOMENTI_OK) { R[q].i_stop = i; R[q].j_stop = J; }
+        if (code == MOMENTI_OK_PARTIAL) R[q].budget_round = i;
+        R[q].n_steps = n_steps; R[q].n_collisions = n_coll; R[q].n_cand = R[q].n_verified = n_cand;
+        R[q].peak_bytes = p->peak;
+        R[q].t_search_ms = elapsed();
+        return MOMENTI_OK;
+    };
+    const double elem_x = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
+restart:
+    for (int q = 0; q < nd; ++q)
+        if (status[q] < 0) HIP_OK(launch_pool_reset(sets[q].ps, p->st));
+    n_steps = 0;
+    for (int i = p->K; i >= 1; --i) {
+        for (int j0 = 0; j0 < p->L;) {
+            int cur = 0;
+            while (cur < nd && status[cur] >= 0) ++cur;
+            if (cur == nd) return MOMENTI_OK;   // every dimensionality answered
+            const int dcur = d_lo + cur, nact = nd - cur;
+            const int Bc = std::min(B, p->L - j0);
+            const int Ds = std::max(1, p->D - dcur + 1);
+            StepGeom g;
+            g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
+            g.j0 = j0; g.Ds = Ds; g.nseg = Bc * Ds; g.i = i; g.K = p->K; g.i_lo = i;
+            g.hashed = i > 4; g.dhi = d_hi; g.part = 0; g.nparts = 1;
+            int buf = 0;
+            const double elems = (double)g.nseg * p->ns;
+            const double kb = sort_keys_32(g) ? 4.0 : 8.0;
+            for (int pass = 0; pass < sort_passes(g); ++pass) {
+                const double kin = pass == 0 ? 8.0 : kb;
+                HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
+                HIP_OK(timed(p, KI_SCAN, 8.0 * g.nseg * 256.0 * p->sb.tiles, 0.0, [&] { return launch_scan(g, p->sb, p->st); }));
+                HIP_OK(timed(p, KI_SCATTER, elems * (kin + (pass == 0 ? 0.0 : 4.0) + kb + 4.0), 0.0,
+                             [&] { return launch_scatter(g, p->H, p->sb, pass, buf, p->st); }));
+                buf ^= 1;
+            }
+            const int kt = std::min(i + 1, p->K);
+            const int nw = fp_words(p->D), nq = fq_words(p->D);
+            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + nq)), 0.0, [&] {
+                return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->st);
+            }));
+            bool redo = false;
+            for (g.part = 0; g.part < g.nparts && !redo; ++g.part) {
+                HIP_OK(launch_zero(p->status, 64, p->st));
+                HIP_OK(timed(p, KI_ENUM, 0.0, 0.0, [&] {
+                    return launch_enum(g, p->sb, buf, p->H, p->fps, p->fq, kt, dcur, p->w, p->cand, p->cap,
+                                       st_counters(p), p->coll_part, p->st);
+                }));
+                HIP_OK(timed(p, KI_VERIFY, 0.0, 0.0, [&] {
+                    return launch_verify(p->cand, p->cap, st_counters(p), p->series, p->dtype, p->n, p->ns, p->D,
+                                         p->w, dcur, p->mu, p->isig, p->vrec, p->st, nact);
+                }));
+                (void)elem_x;
+                Counters cnt;
+                HIP_OK(hipMemcpyAsync(p->host_status, p->status, sizeof(Counters), hipMemcpyDeviceToHost, p->st));
+                HIP_OK(hipStreamSynchronize(p->st));
+                std::memcpy(&cnt, p->host_status, sizeof cnt);
+                prof_flush(p);
+                if (cnt.n_units > p->sb.ucap)
+                    return fail(MOMENTI_E_DEVICE, "%u tile rows queued, room for %u", cnt.n_units, p->sb.ucap);
+                if (cnt.n_cand > p->cap) {
+                    if (Bc > 1) {   // fewer repetitions per launch
+                        B = std::max(1, Bc / 2);
+                        redo = true;
+                        break;
+                    }
+                    int np = g.nparts;   // else this repetition in parts
+                    while ((uint64_t)np * p->cap < 2ull * cnt.n_cand * (uint64_t)g.nparts && np < (1 << 16)) np <<= 1;
+                    if (np == g.nparts) return fail(MOMENTI_E_NOMEM, "%u candidates in one step exceed mem_limit", cnt.n_cand);
+                    g.nparts = np;
+                    g.part = -1;
+                    continue;
+                }
+                if (g.part == 0) n_coll += (int64_t)cnt.n_coll;
+                n_cand += cnt.n_cand;
+                // every open dimensionality takes the records of its d
+                for (int q = cur; q < nd; ++q) {
+                    if (status[q] >= 0) continue;
+                    pool_in(p, sets[q]);
+                    rc = replay(p, p->vrec + (size_t)(q - cur) * p->cap, cnt.n_cand, p->keep, k,
+                                (p->K - i) * p->L + j0, Bc, d_lo + q);
+                    pool_out(p, sets[q]);
+                    sets[q].ps = ps_block + q;
+                    if (rc) return rc;
+                }
+            }
+            if (redo) continue;
+            // the stopping rule of every open dimensionality, step by step
+            bool grow = false;
+            for (int st = 0; st < Bc && !grow; ++st) {
+                const int J = j0 + st + 1;
+                ++n_steps;
+                for (int q = cur; q < nd; ++q) {
+                    if (status[q] >= 0) continue;
+                    const Snap& sn = sets[q].host_snaps[st];
+                    if (sn.top_n < k && sn.truncated) {   // pool q dropped what TOP needs
+                        ++R[q].pool_overflow;
+                        pool_in(p, sets[q]);
+                        rc = grow_pool(p, sets[q].P * 2, k, B);
+                        pool_out(p, sets[q]);
+                        sets[q].ps = ps_block + q;
+                        if (rc) return rc;
+                        grow = true;
+                        break;
+                    }
+                    if (sn.top_n == k &&
+                        stop_holds(sn.dist_max, p->r, d_lo + q, i, J, p->K, p->L, p->m, p->o.stop_rule, delta_rule))
+                        if ((rc = answer(q, st, i, J, MOMENTI_OK))) return rc;
+                }
+                if (!grow && ((p->o.max_steps > 0 && n_steps >= p->o.max_steps) ||
+                              (p->o.max_ms > 0.0 && elapsed() >= p->o.max_ms))) {
+                    for (int q = cur; q < nd; ++q)
+                        if (status[q] < 0 && (rc = answer(q, st, i, J, MOMENTI_OK_PARTIAL))) return rc;
+                    if (reps) std::copy(R.begin(), R.end(), reps);
+                    return MOMENTI_OK;
+                }
+            }
+            if (grow) goto restart;   // answered dimensionalities keep their answers
+            j0 += Bc;
+        }
+    }
+    // no step stopped for these: the exact answers
+    for (int q = 0; q < nd; ++q) {
+        if (status[q] >= 0) continue;
+        pool_in(p, sets[q]);
+        momenti_report Rq = R[q];
+        rc = exact_fallback(p, d_lo + q, k, out + (size_t)q * k, &n_out[q], &Rq);
+        pool_out(p, sets[q]);
+        sets[q].ps = ps_block + q;
+        if (rc) return rc;
+        R[q] = Rq;
+        R[q].fallback = 1;
+        R[q].fail_bound = 0.0;
+        R[q].n_steps = n_steps;
+        status[q] = MOMENTI_OK_FALLBACK;
+        R[q].t_search_ms = elapsed();
+    }
+    if (reps) std::copy(R.begin(), R.end(), reps);
+    return MOMENTI_OK;
 }
 
 // ------------------------------------------------------------------ search without allocations

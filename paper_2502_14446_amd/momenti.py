@@ -20,7 +20,8 @@ OK, OK_FALLBACK, OK_PARTIAL = 0, 1, 2
 E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 PROJ = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
-STOP = {"tensor": 0, "lemma52": 1, "tensor_literal": 2}
+STOP = {"tensor": 0, "lemma52": 1, "tensor_literal": 2, "rigorous": 3}
+DELTA_MODE = {"per_motif": 0, "joint": 1}
 
 EXPORTS = [
     "momenti_default_opts", "momenti_prepare", "momenti_hash", "momenti_search", "momenti_topk",
@@ -28,6 +29,7 @@ EXPORTS = [
     "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace", "momenti_get_profile",
     "momenti_set_profile",
     "momenti_topk_batch", "momenti_get_hash_words", "momenti_search_noalloc",
+    "momenti_search_multi",
 ]
 
 
@@ -36,7 +38,8 @@ class Opts(C.Structure):
                 ("r_scale", C.c_double),
                 ("proj", C.c_int32), ("stop_rule", C.c_int32), ("series_on_device", C.c_int32),
                 ("pool_size", C.c_int32), ("batch_reps", C.c_int32), ("profile", C.c_int32),
-                ("merge_pairs", C.c_double), ("max_pairs", C.c_double), ("stream", C.c_void_p)]
+                ("merge_pairs", C.c_double), ("max_pairs", C.c_double), ("stream", C.c_void_p),
+                ("delta_mode", C.c_int32), ("max_steps", C.c_int32), ("max_ms", C.c_double)]
 
 
 class Job(C.Structure):
@@ -51,7 +54,7 @@ class KProf(C.Structure):
 
 class Motif(C.Structure):
     _fields_ = [("a", C.c_int64), ("b", C.c_int64), ("dist_d", C.c_double),
-                ("dist_max", C.c_double), ("dims", C.c_uint64 * 2)]
+                ("dist_max", C.c_double), ("dims", C.c_uint64 * 2), ("fail_prob", C.c_double)]
 
 
 class Report(C.Structure):
@@ -62,7 +65,7 @@ class Report(C.Structure):
                 ("peak_bytes", C.c_uint64), ("fallback", C.c_int32), ("pool_overflow", C.c_int32),
                 ("batch_reps", C.c_int32), ("first_group_lo", C.c_int32),
                 ("budget_round", C.c_int32), ("max_run", C.c_int32),
-                ("group_splits", C.c_int32), ("step_parts", C.c_int32)]
+                ("group_splits", C.c_int32), ("step_parts", C.c_int32), ("fail_bound", C.c_double)]
 
 
 class MomentiError(RuntimeError):
@@ -89,6 +92,7 @@ def lib():
             "momenti_hash": (i32, [vp, vp]),
             "momenti_search": (i32, [vp, i32, i32, d, P(Motif), P(i32), P(Report)]),
             "momenti_search_noalloc": (i32, [vp, i32, i32, d, P(Motif), P(i32), P(Report)]),
+            "momenti_search_multi": (i32, [vp, i32, i32, i32, d, P(Motif), P(i32), P(i32), P(Report)]),
             "momenti_topk": (i32, [vp, i32, i64, i32, i32, i32, i32, d, u64, P(Opts), P(Motif),
                                    P(i32), P(Report)]),
             "momenti_destroy": (None, [vp]),
@@ -121,10 +125,12 @@ def _check(rc: int) -> int:
 def make_opts(seed: int = 0x5EED, K: int = 8, L: int = 200, r: float = 0.0, proj: str = "f32",
               stop: str = "tensor", series_on_device: bool = False, pool_size: int = 0,
               batch_reps: int = 0, profile: int = 0, stream: Optional[int] = None,
-              r_scale: float = 1.0, max_pairs: float = 0.0, merge_pairs: float = 0.0) -> Opts:
+              r_scale: float = 1.0, max_pairs: float = 0.0, merge_pairs: float = 0.0,
+              delta_mode: str = "per_motif", max_steps: int = 0, max_ms: float = 0.0) -> Opts:
     o = Opts()
     lib().momenti_default_opts(C.byref(o))
     o.seed, o.K, o.L, o.r, o.r_scale, o.max_pairs = seed, K, L, r, r_scale, max_pairs
+    o.delta_mode, o.max_steps, o.max_ms = DELTA_MODE[delta_mode], max_steps, max_ms
     o.merge_pairs = merge_pairs
     o.proj, o.stop_rule = PROJ[proj], STOP[stop]
     o.series_on_device = 1 if series_on_device else 0
@@ -139,7 +145,7 @@ def _motifs(arr, count: int) -> List[Dict]:
     for m in arr[:count]:
         dims = tuple(f for f in range(128) if (int(m.dims[f >> 6]) >> (f & 63)) & 1)
         out.append(dict(a=int(m.a), b=int(m.b), dist_d=float(m.dist_d),
-                        dist_max=float(m.dist_max), dims=dims))
+                        dist_max=float(m.dist_max), dims=dims, fail_prob=float(m.fail_prob)))
     return out
 
 
@@ -219,6 +225,17 @@ class Plan:
         rep = Report()
         rc = _check(lib().momenti_search_noalloc(self.h, d, k, delta, arr, C.byref(got), C.byref(rep)))
         return _motifs(arr, got.value), _report(rep), rc
+
+    def search_multi(self, d_lo: int, d_hi: int, k: int, delta: float) -> Dict[int, Tuple[List[Dict], Dict, int]]:
+        """momenti_search_multi: {d: (motifs, report, status)} for every d in [d_lo, d_hi]."""
+        nd = max(d_hi - d_lo + 1, 1)
+        arr = (Motif * (nd * max(k, 1)))()
+        got = (C.c_int32 * nd)()
+        status = (C.c_int32 * nd)()
+        reps = (Report * nd)()
+        _check(lib().momenti_search_multi(self.h, d_lo, d_hi, k, delta, arr, got, status, reps))
+        return {d_lo + q: (_motifs(arr[q * k:(q + 1) * k], got[q]), _report(reps[q]), status[q])
+                for q in range(nd)}
 
     def params(self) -> Dict:
         r, L, nl, nr = C.c_double(), C.c_int32(), C.c_int32(), C.c_int32()

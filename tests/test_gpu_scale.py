@@ -81,7 +81,7 @@ def _traverse(orc, s, w, seed, K, L, k, d, delta, rule, mem_limit=1 << 30, injec
     got, rep, rc = plan.search(d, k, delta)
     tr = plan.trace()
     plan.close()
-    code = {"tensor": orc.STOP_TENSOR, "lemma52": orc.STOP_LEMMA52}[rule]
+    code = {"tensor": orc.STOP_TENSOR, "lemma52": orc.STOP_LEMMA52, "rigorous": orc.STOP_RIGOROUS}[rule]
     ref = orc.lsh_search(s.x, w, d, k, delta, words, K, Lu, r, rule=code, trace=True, cand_cap=trace_cap,
                          fallback=oracle_fallback)
     assert (rep["i_stop"], rep["j_stop"]) == (ref["i_stop"], ref["J_stop"])
@@ -381,3 +381,120 @@ def test_exact_fallback_sweep_equals_the_oracle(orc, case):
     assert rc == mm.OK_FALLBACK and rep["fallback"] == 1
     want = orc.topk_exact_sweep(s.x, w, d, k)
     _compare_motifs(got, want)
+
+
+# --------------------------------------------------------------------------- anytime answers, delta modes, rules
+def test_rigorous_rule_matches_the_oracle(orc):
+    # the rigorous tensoring bound as the stopping rule: every step, TOP and
+    # the stop step as the oracle's search with the same rule; each motif's
+    # reported failure bound is the oracle's bound at the stop step
+    s = synth.make_series(21, 5, 2500, 40, 3, 2, noise=0.02, dtype="f64")
+    got, rep, rc, ref = _traverse(orc, s, 40, 5, 8, 60, 3, 2, 0.1, "rigorous", r_scale=2.0)
+    assert rc == mm.OK and ref["i_stop"] >= 1
+    _compare_motifs(got, ref["motifs"])
+    plan_r = orc.estimate_r(s.x, 40, 5) * 2.0
+    for m in got:
+        want = orc.fail_bound(orc.collision_prob(m["dist_max"], plan_r) ** 2, ref["i_stop"], ref["J_stop"], 8,
+                              rep["L_used"], orc.STOP_RIGOROUS)
+        assert m["fail_prob"] == pytest.approx(want, rel=1e-9, abs=1e-300)
+    assert rep["fail_bound"] == got[-1]["fail_prob"] <= 0.1
+
+
+def test_joint_delta_is_the_per_motif_rule_at_delta_over_k(orc):
+    # Lemma 5.4: with delta_mode "joint" the rule runs at delta / k
+    s = synth.make_series(22, 4, 3000, 40, 3, 2, noise=0.02, dtype="f64")
+    p = dict(w=40, mem_limit=1 << 30)
+    plan, _ = _plan(s, p, "f64", 6, delta_mode="joint")
+    got, rep, rc = plan.search(2, 3, 0.3)
+    plan.close()
+    ref = orc.lsh_pipeline(s.x, 40, 2, 3, 0.1, 6, mem_limit=1 << 30)
+    assert (rep["i_stop"], rep["j_stop"]) == (ref["i_stop"], ref["J_stop"])
+    _compare_motifs(got, ref["motifs"])
+    assert rep["fail_bound"] <= 0.1
+
+
+def test_step_budget_returns_top_with_its_failure_bounds(orc):
+    # an anytime answer after 7 steps: TOP as the oracle has it after its 7th
+    # step, each motif with the rule's bound at that step (section 4: the
+    # search can be stopped at any time with the error probabilities)
+    s = synth.make_series(23, 5, 2500, 40, 3, 2, dtype="f64")
+    plan, _ = _plan(s, dict(w=40, mem_limit=1 << 30), "f64", 5, K=8, L=30, stop="lemma52", max_steps=7)
+    prm = plan.params()
+    got, rep, rc = plan.search(2, 3, 1e-6)
+    plan.close()
+    assert rc == mm.OK_PARTIAL and rep["n_steps"] == 7
+    R, U = orc.draw_projections(5, s.D, 40, 4 * prm["NF"])
+    words = orc.pack(orc.hash_all(s.x, 40, R, U, prm["r"]), prm["NF"], 8)
+    ref = orc.lsh_search(s.x, 40, 2, 3, 1e-6, words, 8, prm["L"], prm["r"], rule=orc.STOP_LEMMA52, trace=True)
+    n = ref["top_size"][6]
+    assert [(m["a"], m["b"]) for m in got] == [tuple(v) for v in ref["top_pairs"][6, :n]]
+    for m in got:        # step 7 is round 8, repetition 7
+        want = orc.fail_bound(orc.collision_prob(m["dist_max"], prm["r"]) ** 2, 8, 7, 8, prm["L"], orc.STOP_LEMMA52)
+        assert m["fail_prob"] == pytest.approx(want, rel=1e-9)
+    assert rep["fail_bound"] == (got[2]["fail_prob"] if len(got) == 3 else 1.0)
+
+
+# --------------------------------------------------------------------------- several dimensionalities
+@pytest.mark.parametrize("case", ["planted", "mostly_fallback"])
+def test_multi_d_search_answers_each_d_as_its_own_search(orc, case):
+    # section 6.3: one traversal for d = 1..4; each d stops at the step of a
+    # search for that d alone, with its answer, and that is the oracle's
+    # search over the same index. "planted": d = 1, 2, 3 stop in rounds 8, 7
+    # and 4, d = 4 never stops and gets the exact answer after the
+    # traversal; "mostly_fallback": only d = 1 stops
+    if case == "planted":
+        s = synth.make_series(31, 5, 3000, 40, 3, 3, noise=0.02, dtype="f64")
+        w, seed, K, k, L, delta, rule, r_scale = 40, 8, 8, 3, 40, 0.1, "tensor", 2.0
+    else:
+        s = synth.make_series(32, 4, 1200, 30, 2, 1, noise=0.05, dtype="f64")
+        w, seed, K, k, L, delta, rule, r_scale = 30, 9, 8, 2, 20, 0.1, "lemma52", 3.0
+    d_lo, d_hi = 1, 4
+    plan, _ = _plan(s, dict(w=w, mem_limit=1 << 30), "f64", seed, K=K, L=L, stop=rule, r_scale=r_scale)
+    prm = plan.params()
+    R, U = orc.draw_projections(seed, s.D, w, 4 * prm["NF"])
+    words = orc.pack(orc.hash_all(s.x, w, R, U, prm["r"]), prm["NF"], K)
+    plan.set_hashes(words)
+    multi = plan.search_multi(d_lo, d_hi, k, delta)
+    single = {d: plan.search(d, k, delta) for d in range(d_lo, d_hi + 1)}
+    again = plan.search_multi(d_lo, d_hi, k, delta)       # the plan's blocks reused: same answers
+    plan.close()
+    code = {"tensor": orc.STOP_TENSOR, "lemma52": orc.STOP_LEMMA52}[rule]
+    statuses = []
+    for d in range(d_lo, d_hi + 1):
+        got, rep, st = multi[d]
+        sg, srep, src = single[d]
+        statuses.append(st)
+        assert st == src, f"d={d}"
+        assert (rep["i_stop"], rep["j_stop"]) == (srep["i_stop"], srep["j_stop"]), f"d={d}"
+        assert rep["fallback"] == srep["fallback"]
+        _compare_motifs(got, sg)
+        assert [m["fail_prob"] for m in got] == pytest.approx([m["fail_prob"] for m in sg], rel=1e-12)
+        ref = orc.lsh_search(s.x, w, d, k, delta, words, K, prm["L"], prm["r"], rule=code)
+        assert (rep["i_stop"], rep["j_stop"]) == (ref["i_stop"], ref["J_stop"]), f"d={d}"
+        _compare_motifs(got, ref["motifs"])
+        g2, r2, s2 = again[d]
+        assert s2 == st and (r2["i_stop"], r2["j_stop"]) == (rep["i_stop"], rep["j_stop"])
+        _compare_motifs(g2, got)
+    want = [mm.OK] * 3 + [mm.OK_FALLBACK] if case == "planted" else [mm.OK] + [mm.OK_FALLBACK] * 3
+    assert statuses == want
+
+
+def test_multi_d_search_with_one_d_and_a_step_budget(orc):
+    # d_lo = d_hi is momenti_search; a step budget ends every open d at that
+    # step with TOP as it stands there (the single searches' anytime answers)
+    s = synth.make_series(33, 4, 2500, 40, 3, 2, dtype="f64")
+    plan, _ = _plan(s, dict(w=40, mem_limit=1 << 30), "f64", 5, K=8, L=30, stop="lemma52")
+    one = plan.search_multi(2, 2, 3, 0.1)[2]
+    ref = plan.search(2, 3, 0.1)
+    plan.close()
+    assert one[2] == ref[2] and (one[1]["i_stop"], one[1]["j_stop"]) == (ref[1]["i_stop"], ref[1]["j_stop"])
+    _compare_motifs(one[0], ref[0])
+    plan, _ = _plan(s, dict(w=40, mem_limit=1 << 30), "f64", 5, K=8, L=30, stop="lemma52", max_steps=7)
+    multi = plan.search_multi(1, 3, 3, 1e-6)
+    single = {d: plan.search(d, 3, 1e-6) for d in (1, 2, 3)}
+    plan.close()
+    for d in (1, 2, 3):
+        got, rep, st = multi[d]
+        assert st == single[d][2] == mm.OK_PARTIAL and rep["n_steps"] == 7
+        _compare_motifs(got, single[d][0])
+        assert [m["fail_prob"] for m in got] == pytest.approx([m["fail_prob"] for m in single[d][0]], rel=1e-12)

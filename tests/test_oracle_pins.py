@@ -562,3 +562,50 @@ def test_openmp_build_gives_the_same_search(orc):
     assert np.array_equal(par["top_size"], res["top_size"])
     assert [(m["a"], m["b"], m["dist_d"]) for m in par["motifs"]] == \
         [(m["a"], m["b"], m["dist_d"]) for m in res["motifs"]]
+
+
+# ----------------------------------------------------------------------------- rigorous tensoring bound
+def _mc_tensored_failure(p, i, J, K, L, N, rng):
+    """Monte Carlo of the failure event of the tensored index: every half-
+    function gets an independent collision depth G with P(G >= s) = p^s;
+    repetition j (left j div m, right j mod m) collides at prefix length i'
+    when the left depth reaches ceil(i'/2) and the right depth floor(i'/2).
+    Failure: no repetition j < J collides at prefix i, and (below round K) no
+    repetition collides at prefix i + 1."""
+    m = math.isqrt(L - 1) + 1 if L > 1 else 1
+    nl, nr = -(-L // m), min(L, m)
+    Dl = rng.geometric(1.0 - p, size=(N, nl)) - 1      # P(Dl >= s) = p^s
+    Er = rng.geometric(1.0 - p, size=(N, nr)) - 1
+    fail = np.ones(N, dtype=bool)
+    for j in range(L):
+        l, r = j // m, j % m
+        for ii in ([i] if j < J else []) + ([i + 1] if i < K else []):
+            fail &= ~((Dl[:, l] >= (ii + 1) // 2) & (Er[:, r] >= ii // 2))
+    return fail.mean()
+
+
+@pytest.mark.parametrize("p,i,J,K,L", [
+    (0.5, 3, 20, 8, 200), (0.3, 1, 7, 8, 200), (0.85, 6, 1, 8, 200), (0.6, 2, 50, 8, 50),
+    (0.9, 8, 5, 8, 30), (0.4, 4, 16, 8, 16), (0.7, 5, 33, 8, 40), (0.55, 1, 12, 4, 12)])
+def test_rigorous_bound_equals_the_geometric_depth_model(orc, p, i, J, K, L):
+    rng = np.random.default_rng(int(p * 1000) + 31 * i + J)
+    N = 400_000
+    mc = _mc_tensored_failure(p, i, J, K, L, N, rng)
+    v = orc.fail_bound(p, i, J, K, L, orc.STOP_RIGOROUS)
+    sig = math.sqrt(max(v * (1 - v), 1e-12) / N)
+    assert abs(mc - v) <= 5 * sig + 1e-9, (mc, v)
+
+
+def test_rigorous_bound_special_cases(orc):
+    R = orc.STOP_RIGOROUS
+    # one repetition: Lemma 5.2's (1 - p^i)
+    assert orc.fail_bound(0.5, 8, 1, 8, 1, R) == pytest.approx(1 - 0.5 ** 8, rel=1e-15)
+    # (below round K the one repetition at prefix i + 1 adds nothing: a collision
+    # there is one at prefix i)
+    assert orc.fail_bound(0.7, 5, 1, 8, 1, R) == pytest.approx(1 - 0.7 ** 5, rel=1e-15)
+    # p = 1: every pair collides, nothing can be missed; p = 0: nothing collides
+    assert orc.fail_bound(1.0, 3, 5, 8, 200, R) == 0.0
+    assert orc.fail_bound(0.0, 3, 5, 8, 200, R) == 1.0
+    # more repetitions never raise the bound
+    vals = [orc.fail_bound(0.6, 4, J, 8, 200, R) for J in range(1, 201)]
+    assert all(u >= v - 1e-15 for u, v in zip(vals, vals[1:]))
