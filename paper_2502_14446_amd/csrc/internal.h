@@ -126,16 +126,24 @@ __host__ __device__ inline uint32_t pair_part(uint32_t a, uint32_t b, int nparts
 // Sort keys of a segment element: the length-i_lo prefix, or its 24-bit hash.
 inline bool sort_keys_32(const StepGeom& g) { return g.hashed || g.i_lo <= 4; }
 inline int sort_passes(const StepGeom& g) { return g.hashed ? 3 : g.i_lo; }
-// 32-bit words of a window's fingerprint row: one byte per dimension, padded
-// with zero bytes to 1, 2, 4, 8 or a multiple of 8 words
-__host__ __device__ inline int fp_words(int D)
+// Fingerprint rows are bit-sliced: a window's digest of dimension f (8 bits
+// in the first-stage row, 16 in the second) is spread over planes, bit k of
+// the digest being bit f of plane k. With D <= 32 a plane has Dp bits (D
+// rounded up to 4, 8, 16 or 32), 32 / Dp planes to a word, plane k in word
+// k / (32 / Dp) at bit (k mod (32 / Dp)) Dp; with D > 32 the dimensions come
+// in chunks of 32, one word per plane, chunk q's plane k in word P q + k
+// (P = 8 or 16 planes). Padding dimensions are zero bits. Two windows'
+// digests differ in dimension f iff some plane differs at f, so the number
+// of differing digests is the popcount of the OR of the XORed words, folded
+// over the planes that share a word.
+__host__ __device__ inline int plane_bits(int D) { return D <= 4 ? 4 : D <= 8 ? 8 : D <= 16 ? 16 : 32; }
+// 32-bit words of a first-stage row (8 planes): 1, 2, 4, 8 or 8 per chunk
+__host__ __device__ inline int fp_words(int D) { return D <= 32 ? plane_bits(D) / 4 : 8 * ((D + 31) / 32); }
+// 32-bit words of a second-stage row (16 planes), in whole 16-byte pieces
+__host__ __device__ inline int fq_words(int D)
 {
-    const int w = (D + 3) / 4;
-    return w <= 1 ? 1 : w <= 2 ? 2 : w <= 4 ? 4 : (w + 7) / 8 * 8;
+    return D <= 32 ? (plane_bits(D) / 2 < 4 ? 4 : plane_bits(D) / 2) : 16 * ((D + 31) / 32);
 }
-// 32-bit words of a window's second-stage fingerprint row: 16 bits per
-// dimension, padded with zero halfwords to whole 16-byte chunks
-__host__ __device__ inline int fq_words(int D) { return (D + 7) / 8 * 4; }
 constexpr int kSortTile = 4096;
 
 // Stable LSD sort of every segment of the batch by its length-i hash prefix,
@@ -146,10 +154,10 @@ hipError_t launch_hist(const StepGeom& g, const uint32_t* H, const SortBufs& b, 
 hipError_t launch_scan(const StepGeom& g, const SortBufs& b, hipStream_t s);
 hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& b, int pass, int cur,
                           hipStream_t s);
-// Fingerprint rows of the batch, fps[jb][a][fp_words(D)]: byte f digests
-// dimension f's length-i_lo prefix (the prefix itself when i_lo = 1), padded
-// with zero bytes to whole words; and second-stage rows fq[jb][a][fq_words(D)]
-// with a 16-bit digest per dimension (the prefix itself when i_lo <= 2).
+// Fingerprint rows of the batch, fps[jb][a][fp_words(D)]: an 8-bit digest
+// of every dimension's length-i_lo prefix (the prefix itself when i_lo = 1);
+// and second-stage rows fq[jb][a][fq_words(D)] with a 16-bit digest per
+// dimension (the prefix itself when i_lo <= 2); both bit-sliced.
 hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, uint32_t* fq,
                           hipStream_t s);
 // Runs of >= 2 equal length-i_lo prefixes and the pairs of every run (one

@@ -427,14 +427,13 @@ hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& 
 
 // ------------------------------------------------------------------ enumeration
 // Fingerprint rows of a batch: for every repetition of the batch and every
-// window, one byte per dimension digesting that dimension's length-i_lo
-// prefix (equal prefixes give equal bytes), four to a word, padded with zero
-// bytes ([jb][a][fp_words(D)]); and a second-stage row with a 16-bit digest
-// per dimension ([jb][a][fq_words(D)]). The pairs of a run are screened with
-// the bytes for >= d colliding dimensions a word at a time; those that pass
-// are screened again with the 16-bit digests (one contiguous row per
-// window), and the few left have their per-dimension prefixes rebuilt from
-// the index and counted exactly.
+// window, an 8-bit digest of each dimension's length-i_lo prefix (equal
+// prefixes give equal digests), bit-sliced into 8 planes ([jb][a][fp_words]);
+// and a second-stage row of 16-bit digests in 16 planes ([jb][a][fq_words]).
+// The pairs of a run are screened with the first rows for >= d equal
+// digests (OR of the XORed plane words, then a popcount); those that pass
+// are screened again with the second rows, and the few left have their
+// per-dimension prefixes rebuilt from the index and counted exactly.
 __device__ inline uint32_t prefix_digest8(uint64_t prefix, int i_lo)
 {
     // one symbol is its own digest; longer prefixes are mixed by a
@@ -446,6 +445,68 @@ __device__ inline uint32_t prefix_digest16(uint64_t prefix, int i_lo)
     return i_lo <= 2 ? (uint32_t)(prefix & 0xFFFFu) : (uint32_t)((prefix * 0x9E3779B97F4A7C15ull) >> 48);
 }
 
+// Transpose of an 8 x 8 bit matrix held as 64 bits, row r in byte r and
+// column c in bit c of it: afterwards byte c, bit r holds the old byte r,
+// bit c (three rounds of masked delta swaps, Hacker's Delight section 7-3).
+__host__ __device__ inline uint64_t transpose8(uint64_t x)
+{
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x ^= t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x ^= t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    x ^= t ^ (t << 28);
+    return x;
+}
+
+// Plane k (k < 8) of a chunk from its groups of 8 dimensions, transposed:
+// group g's byte k holds plane k's bits for dimensions 8 g .. 8 g + 7.
+__host__ __device__ inline uint32_t plane_of(const uint64_t (&t)[4], int k)
+{
+    return (uint32_t)((t[0] >> (8 * k)) & 0xFFu) | (uint32_t)((t[1] >> (8 * k)) & 0xFFu) << 8 |
+           (uint32_t)((t[2] >> (8 * k)) & 0xFFu) << 16 | (uint32_t)((t[3] >> (8 * k)) & 0xFFu) << 24;
+}
+
+// Words of 8 planes (planes 8 h .. 8 h + 7 of a row) with DP-bit planes.
+template <int DP>
+__host__ __device__ inline void plane_words(const uint64_t (&t)[4], uint32_t* out)
+{
+    constexpr int G = 32 / DP;   // planes per word
+#pragma unroll
+    for (int q = 0; q < 8 / G; ++q) out[q] = 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k / G] |= plane_of(t, k) << ((k % G) * DP);
+}
+
+// Number of dimensions whose digests differ, from the OR of XORed words of
+// DP-bit planes (32 / DP planes to the word folded onto the low DP bits).
+template <int DP>
+__host__ __device__ inline int fold_count(uint32_t o)
+{
+    if (DP <= 16) o |= o >> 16;
+    if (DP <= 8) o |= o >> 8;
+    if (DP <= 4) o |= o >> 4;
+    return __builtin_popcount(DP == 32 ? o : (o & ((1u << DP) - 1u)));
+}
+
+// A chunk's first-stage words (DP / 4) and second-stage words (max(4, DP / 2):
+// planes 0..7 from the low digest bytes, 8..15 from the high ones) from its
+// transposed groups.
+template <int DP>
+__host__ __device__ inline void chunk_words(const uint64_t (&t8)[4], const uint64_t (&tl)[4], const uint64_t (&th)[4],
+                                            uint32_t* o8, uint32_t* oq)
+{
+    plane_words<DP>(t8, o8);
+    plane_words<DP>(tl, oq);
+    if (DP == 4) {
+        plane_words<DP>(th, oq + 1);
+        oq[2] = oq[3] = 0u;
+    } else {
+        plane_words<DP>(th, oq + DP / 4);
+    }
+}
+
+template <int DP>
 __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H, StepGeom g, int reps,
                                                  uint32_t* __restrict__ fps, uint32_t* __restrict__ fq)
 {
@@ -463,45 +524,50 @@ __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H,
     const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
     const int nw = fp_words(g.D), nq = fq_words(g.D);
     uint32_t* fw = fps + gid * nw;
-    uint4* qw = reinterpret_cast<uint4*>(fq + gid * nq);
-    // the fingerprint row leaves in 8- or 16-byte stores (w0..w3: the last
-    // four completed words), so that each store fills whole pieces of lines
-    uint32_t word = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-    uint32_t q4[4] = {0, 0, 0, 0};
-    const int nf = 4 * nw > 2 * nq ? 4 * nw : 2 * nq;
-    for (int f = 0; f < nf; ++f) {
-        uint32_t d8 = 0, d16 = 0;
-        if (f < g.D) {
-            const uint32_t L = H[((int64_t)f * g.NF + l) * g.ns + a];
-            const uint32_t R = H[((int64_t)f * g.NF + g.NL + r) * g.ns + a];
-            const uint64_t pre = make_key<uint64_t>(L, R, g.i_lo);
-            d8 = prefix_digest8(pre, g.i_lo);
-            d16 = prefix_digest16(pre, g.i_lo);
-        }
-        if (f < 4 * nw) {
-            word |= d8 << (8 * (f & 3));
-            if ((f & 3) == 3) {
-                w0 = w1; w1 = w2; w2 = w3; w3 = word;
-                word = 0;
-                const int wi = f >> 2;   // the word just completed
-                if (nw == 1)
-                    fw[0] = w3;
-                else if (nw == 2) {
-                    if (wi == 1) *reinterpret_cast<uint2*>(fw) = make_uint2(w2, w3);
-                } else if ((wi & 3) == 3) {
-                    reinterpret_cast<uint4*>(fw)[wi >> 2] = make_uint4(w0, w1, w2, w3);
+    uint32_t* qw = fq + gid * nq;
+    // chunks of 32 dimensions (one chunk unless D > 32), each as four groups
+    // of 8 whose digests are gathered byte by byte and then transposed
+    for (int c0 = 0; c0 < g.D; c0 += 32) {
+        uint64_t t8[4], tl[4], th[4];
+#pragma unroll
+        for (int gq = 0; gq < 4; ++gq) {
+            uint64_t b8 = 0, bl = 0, bh = 0;
+            if (8 * gq < DP) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int f = c0 + 8 * gq + u;
+                    if (f < g.D) {
+                        const uint32_t L = H[((int64_t)f * g.NF + l) * g.ns + a];
+                        const uint32_t R = H[((int64_t)f * g.NF + g.NL + r) * g.ns + a];
+                        const uint64_t pre = make_key<uint64_t>(L, R, g.i_lo);
+                        const uint32_t d16 = prefix_digest16(pre, g.i_lo);
+                        b8 |= (uint64_t)prefix_digest8(pre, g.i_lo) << (8 * u);
+                        bl |= (uint64_t)(d16 & 0xFFu) << (8 * u);
+                        bh |= (uint64_t)(d16 >> 8) << (8 * u);
+                    }
                 }
             }
+            t8[gq] = transpose8(b8);
+            tl[gq] = transpose8(bl);
+            th[gq] = transpose8(bh);
         }
-        if (f < 2 * nq) {
-            // halfword f of the row: word (f >> 1) of chunk (f >> 3)
-            const int wq = (f >> 1) & 3;
-            q4[wq] |= d16 << (16 * (f & 1));
-            if ((f & 7) == 7) {
-                qw[f >> 3] = make_uint4(q4[0], q4[1], q4[2], q4[3]);
-                q4[0] = q4[1] = q4[2] = q4[3] = 0;
-            }
+        // the chunk's words leave in whole 16-byte stores where rows allow
+        constexpr int W8 = DP / 4, WQ = DP / 2 < 4 ? 4 : DP / 2;
+        uint32_t o8[W8], oq[WQ];
+        chunk_words<DP>(t8, tl, th, o8, oq);
+        uint32_t* f8 = fw + (c0 / 32) * 8;
+        if constexpr (W8 == 1)
+            f8[0] = o8[0];
+        else if constexpr (W8 == 2)
+            *reinterpret_cast<uint2*>(f8) = make_uint2(o8[0], o8[1]);
+        else {
+#pragma unroll
+            for (int v = 0; v < W8 / 4; ++v)
+                reinterpret_cast<uint4*>(f8)[v] = make_uint4(o8[4 * v], o8[4 * v + 1], o8[4 * v + 2], o8[4 * v + 3]);
         }
+        uint4* q4 = reinterpret_cast<uint4*>(qw + (c0 / 32) * 16);
+#pragma unroll
+        for (int v = 0; v < WQ / 4; ++v) q4[v] = make_uint4(oq[4 * v], oq[4 * v + 1], oq[4 * v + 2], oq[4 * v + 3]);
     }
 }
 
@@ -509,35 +575,44 @@ hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32
                           hipStream_t s)
 {
     const int64_t blocks = (g.ns + 255) / 256 * reps;   // (tile, repetition) pairs
-    hipLaunchKernelGGL(k_fptable, dim3((unsigned)blocks), dim3(256), 0, s, H, g, reps, fps, fq);
+    const dim3 grid((unsigned)blocks);
+    switch (plane_bits(g.D)) {
+    case 4: hipLaunchKernelGGL(k_fptable<4>, grid, dim3(256), 0, s, H, g, reps, fps, fq); break;
+    case 8: hipLaunchKernelGGL(k_fptable<8>, grid, dim3(256), 0, s, H, g, reps, fps, fq); break;
+    case 16: hipLaunchKernelGGL(k_fptable<16>, grid, dim3(256), 0, s, H, g, reps, fps, fq); break;
+    default: hipLaunchKernelGGL(k_fptable<32>, grid, dim3(256), 0, s, H, g, reps, fps, fq); break;
+    }
     return hipGetLastError();
 }
 
-// Second stage: do the 16-bit digest rows of windows a and b agree in >= d
-// dimensions? (SWAR per halfword as for bytes below; the rows carry
-// 2 nq - D zero halfwords of padding on both sides.)
-__device__ inline bool second_stage(const uint32_t* __restrict__ fq, int nq, int D, int d, uint32_t a,
-                                    uint32_t b)
+// Second stage: do the 16-bit digests of windows a and b agree in >= d
+// dimensions? (Rows of 16 planes; with D > 32, one popcount per chunk.)
+__host__ __device__ inline bool second_stage(const uint32_t* __restrict__ fq, int nq, int D, int d, uint32_t a,
+                                             uint32_t b)
 {
     const uint4* ra = reinterpret_cast<const uint4*>(fq + (int64_t)a * nq);
     const uint4* rb = reinterpret_cast<const uint4*>(fq + (int64_t)b * nq);
     int z = 0;
-    for (int c = 0; c < nq / 4; ++c) {
-        const uint4 x = ra[c], y = rb[c];
-        const uint32_t v[4] = {x.x ^ y.x, x.y ^ y.y, x.z ^ y.z, x.w ^ y.w};
+    if (D <= 32) {
+        uint32_t o = 0;
+        for (int c = 0; c < nq / 4; ++c) {
+            const uint4 x = ra[c], y = rb[c];
+            o |= (x.x ^ y.x) | (x.y ^ y.y) | (x.z ^ y.z) | (x.w ^ y.w);
+        }
+        const int dp = plane_bits(D);
+        z = dp == 4 ? fold_count<4>(o) : dp == 8 ? fold_count<8>(o) : dp == 16 ? fold_count<16>(o) : fold_count<32>(o);
+    } else {
+        for (int c = 0; c < nq / 4; c += 4) {   // a chunk: 16 words
+            uint32_t o = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) z += __popc(((v[q] & 0x7FFF7FFFu) + 0x7FFF7FFFu) | v[q] | 0x7FFF7FFFu);
+            for (int v = 0; v < 4; ++v) {
+                const uint4 x = ra[c + v], y = rb[c + v];
+                o |= (x.x ^ y.x) | (x.y ^ y.y) | (x.z ^ y.z) | (x.w ^ y.w);
+            }
+            z += __builtin_popcount(o);
+        }
     }
-    // z = 30 nq + non-zero halfwords; equal digests >= d iff non-zero <= D - d
-    return z <= 30 * nq + D - d;
-}
-
-// Bytes of x that are not zero, plus 28 (SWAR: the top bit of a byte of
-// ((x & 0x7F..) + 0x7F..) | x is set iff the byte is non-zero, and no carry
-// crosses a byte; the other 28 bits are forced to one).
-__device__ inline int nonzero_bytes_28(uint32_t x)
-{
-    return __popc(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
+    return z <= D - d;   // digests differ in at most D - d dimensions
 }
 
 constexpr int kFpRegs = 8;   // fingerprint words kept in registers (32 dimensions)
@@ -572,19 +647,24 @@ __host__ __device__ inline int tile_member_words(int nw)
     return (nw > kFpRegs ? 2 : 3) * lds_row_words(nw) + 2;
 }
 
-// Sum over the nw words of nonzero_bytes_28(own ^ partner): the lane's own
-// row (its first NW words in registers, the rest at own_tail, only when TAIL)
-// against the partner's (pw). With D dimensions the rows have 4 nw - D
-// padding bytes, zero on both sides, so a pair has >= d equal digests iff the
-// sum is <= 28 nw + D - d.
+// Dimensions whose first-stage digests differ between the lane's own row
+// (its first NW words in registers, the rest at own_tail, only when TAIL)
+// and the partner's (pw). NW < 8 means D <= 16 and planes of 4 NW bits;
+// NW = 8 is one 32-dimension chunk, and TAIL rows add a chunk per 8 words.
 template <int NW, bool TAIL, typename GetW>
-__device__ inline int screen(const uint32_t (&ofp)[NW], const uint32_t* own_tail, const GetW& pw, int nw)
+__host__ __device__ inline int screen(const uint32_t (&ofp)[NW], const uint32_t* own_tail, const GetW& pw, int nw)
 {
-    int z = 0;
+    uint32_t o = 0;
 #pragma unroll
-    for (int wd = 0; wd < NW; ++wd) z += nonzero_bytes_28(ofp[wd] ^ pw(wd));
+    for (int wd = 0; wd < NW; ++wd) o |= ofp[wd] ^ pw(wd);
+    int z = fold_count<4 * NW>(o);
     if (TAIL)
-        for (int wd = NW; wd < nw; ++wd) z += nonzero_bytes_28(own_tail[wd] ^ pw(wd));
+        for (int c = NW; c < nw; c += 8) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int wd = 0; wd < 8; ++wd) t |= own_tail[c + wd] ^ pw(c + wd);
+            z += __builtin_popcount(t);
+        }
     return z;
 }
 
@@ -703,7 +783,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nw = TAIL ? fp_words(g.D) : NW;   // NW = min(nw, kFpRegs); TAIL iff nw > NW
     const int nq = fq_words(g.D);
-    const int zmax = 28 * nw + g.D - d;
+    const int zmax = g.D - d;   // digests may differ in at most D - d dimensions
     int npend = 0;   // uniform across the wavefront
     unsigned long long ncoll = 0, nmemb = 0, nscr = 0;
     uint32_t maxrun = 0;
@@ -894,7 +974,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_tiles(const uint32_t* __restric
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nw = TAIL ? fp_words(g.D) : NW;   // NW = min(nw, kFpRegs); TAIL iff nw > NW
     const int nq = fq_words(g.D);
-    const int zmax = 28 * nw + g.D - d;
+    const int zmax = g.D - d;   // digests may differ in at most D - d dimensions
     // LDS rows of fingerprint words at an odd stride, so that lanes reading
     // consecutive rows hit distinct banks
     const int ldw = lds_row_words(nw);
@@ -958,8 +1038,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_tiles(const uint32_t* __restric
                     // partners: u + 1 + v in P (v < nA / 2, the last one only for
                     // u < nA / 2 when nA is even), or every member v of Q
                     const uint32_t* P0 = same ? fpA + (size_t)(u + 1) * ldw : fpB;
-                    const int nv = same ? ((nA & 1) == 0 && u >= nA / 2 ? nA / 2 - 1 : nA / 2) : nB;
-                    // row of partner v (tile P is stored once when TAIL: wrap)
+                    const int nv = same ? ((nA & 1) == 0 && u >= nA / 2 ? nA / 2 - 1 : nA / 2) : nB;                    // row of partner v (tile P is stored once when TAIL: wrap)
                     auto prow = [&](int v) -> const uint32_t* {
                         if (!TAIL || !same) return P0 + (size_t)v * ldw;
                         int qq = u + 1 + v;
@@ -992,16 +1071,26 @@ __global__ __launch_bounds__(256, 4) void k_enum_tiles(const uint32_t* __restric
                         int z[UP];
 #pragma unroll
                         for (int c = 0; c < UP; ++c) {
-                            z[c] = 0;
+                            uint32_t o = 0;
 #pragma unroll
-                            for (int wd = 0; wd < NW; ++wd) z[c] += nonzero_bytes_28(ofp[wd] ^ pw[c][wd]);
+                            for (int wd = 0; wd < NW; ++wd) o |= ofp[wd] ^ pw[c][wd];
+                            z[c] = fold_count<4 * NW>(o);
                         }
                         if (TAIL)
-                            // the rest of the lane's own row is read once for the UP partners
-                            for (int wd = NW; wd < nw; ++wd) {
-                                const uint32_t o = ofw[wd];
+                            // the rest of the lane's own row is read once for the UP
+                            // partners, a 32-dimension chunk (8 words) at a time
+                            for (int c0 = NW; c0 < nw; c0 += 8) {
+                                uint32_t t[UP];
 #pragma unroll
-                                for (int c = 0; c < UP; ++c) z[c] += nonzero_bytes_28(o ^ pr[c][wd]);
+                                for (int c = 0; c < UP; ++c) t[c] = 0u;
+#pragma unroll
+                                for (int wd = 0; wd < 8; ++wd) {
+                                    const uint32_t o = ofw[c0 + wd];
+#pragma unroll
+                                    for (int c = 0; c < UP; ++c) t[c] |= o ^ pr[c][c0 + wd];
+                                }
+#pragma unroll
+                                for (int c = 0; c < UP; ++c) z[c] += __popc(t[c]);
                             }
                         // most steps pass no partner: one test of the smallest count first
                         int zmin = z[0];
