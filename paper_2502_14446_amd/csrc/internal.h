@@ -4,6 +4,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 #include <stdint.h>
 
 namespace mm {
@@ -115,7 +117,20 @@ struct StepGeom {
     int part, nparts;    // emit only the candidates (a, b) with pair_part(a, b, nparts) == part
                          // (nparts a power of two; 1 = all): a step whose candidates do not fit
                          // in memory at once is enumerated in parts
+    int fq;              // 1: second-stage rows are built and screen the pairs (second_stage_pays)
 };
+// Does the second screen pay for its table? A pair passes the first one by
+// chance when >= d - 1 of the other D - 1 dimensions have equal 8-bit digests
+// without equal prefixes, about C(D - 1, d - 1) 2^(-8 (d - 1)) of the pairs
+// (the digests of unequal prefixes agree with probability 2^-8). Below 2^-24
+// those pairs go straight to the exact test: a few thousand per 10^11 pairs.
+inline int second_stage_pays(int D, int d)
+{
+    if (d <= 1) return 0;   // every pair of a run passes both screens
+    double lp = -8.0 * (d - 1) * 0.6931471805599453;
+    for (int q = 0; q < d - 1; ++q) lp += std::log((double)(D - 1 - q) / (double)(q + 1));
+    return lp > -24.0 * 0.6931471805599453 ? 1 : 0;
+}
 // Part of a candidate pair when a step is enumerated in parts.
 __host__ __device__ inline uint32_t pair_part(uint32_t a, uint32_t b, int nparts)
 {

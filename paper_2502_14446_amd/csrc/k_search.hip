@@ -565,9 +565,11 @@ __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H,
             for (int v = 0; v < W8 / 4; ++v)
                 reinterpret_cast<uint4*>(f8)[v] = make_uint4(o8[4 * v], o8[4 * v + 1], o8[4 * v + 2], o8[4 * v + 3]);
         }
-        uint4* q4 = reinterpret_cast<uint4*>(qw + (c0 / 32) * 16);
+        if (g.fq) {
+            uint4* q4 = reinterpret_cast<uint4*>(qw + (c0 / 32) * 16);
 #pragma unroll
-        for (int v = 0; v < WQ / 4; ++v) q4[v] = make_uint4(oq[4 * v], oq[4 * v + 1], oq[4 * v + 2], oq[4 * v + 3]);
+            for (int v = 0; v < WQ / 4; ++v) q4[v] = make_uint4(oq[4 * v], oq[4 * v + 1], oq[4 * v + 2], oq[4 * v + 3]);
+        }
     }
 }
 
@@ -818,7 +820,9 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t t = qstart + 64 * r + lane;
-                kq[r] = t < g.ns ? ks[t] : (KT)0;
+                // keys and indices stream through once: non-temporal loads leave
+                // the caches to the fingerprint rows gathered below
+                kq[r] = t < g.ns ? __builtin_nontemporal_load(ks + t) : (KT)0;
                 // lane 0 holds the key before the window, lane 63 the one after it
                 const int64_t te = lane == 0 ? t - 1 : t + 1;
                 kedge[r] = ((lane == 0 || lane == 63) && te >= 0 && te < g.ns) ? ks[te] : (KT)0;
@@ -839,7 +843,8 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
             if (!__ballot(sflags != 0)) continue;
             // the four windows' indices in one round of loads
 #pragma unroll
-            for (int r = 0; r < 4; ++r) xr[r] = ((sflags >> (2 * r)) & 3u) ? is[qstart + 64 * r + lane] : 0u;
+            for (int r = 0; r < 4; ++r)
+                xr[r] = ((sflags >> (2 * r)) & 3u) ? __builtin_nontemporal_load(is + qstart + 64 * r + lane) : 0u;
         }
 #pragma unroll 1
         for (int r = 0; r < 4; ++r) {
@@ -887,7 +892,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_runs(const KT* __restrict__ key
                 if (act && z <= zmax) {
                     const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
                     if (2 * (int64_t)(b - a) > (int64_t)w &&   // else a trivial match
-                        second_stage(qbase, nq, g.D, d, a, b)) {
+                        (!g.fq || second_stage(qbase, nq, g.D, d, a, b))) {
                         ++nscr;
                         judge_pair(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     }
@@ -1051,7 +1056,7 @@ __global__ __launch_bounds__(256, 4) void k_enum_tiles(const uint32_t* __restric
                         const uint32_t xu = idA[u], y = same ? idA[qq] : idB[qq];
                         const uint32_t a = xu < y ? xu : y, b = xu < y ? y : xu;
                         if (2 * (int64_t)(b - a) <= (int64_t)w) return;   // trivial match
-                        if (!second_stage(qbase, nq, g.D, d, a, b)) return;
+                        if (!(!g.fq || second_stage(qbase, nq, g.D, d, a, b))) return;
                         ++nscr;
                         judge_pair(a, b, H, g, f, j, kt, d, cand, cap, cnt);
                     };

@@ -1275,7 +1275,7 @@ extern "C" int momenti_search(momenti_plan* p, int32_t d, int32_t k, double delt
         StepGeom g;
         g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
         g.j0 = 0; g.Ds = Ds; g.nseg = Dp; g.i = p->K; g.K = p->K; g.i_lo = p->K; g.hashed = 0;
-        g.dhi = d; g.part = 0; g.nparts = 1;
+        g.dhi = d; g.part = 0; g.nparts = 1; g.fq = 0;
         int buf = 0;
         const double elems = (double)Dp * p->ns, kb = p->K <= 4 ? 4.0 : 8.0;
         for (int pass = 0; pass < p->K; ++pass) {
@@ -1457,6 +1457,7 @@ restart:
             g.hashed = i_lo > 4;   // longer prefixes are grouped by a 24-bit hash (3 passes)
             g.dhi = d;
             g.part = 0; g.nparts = 1;
+            g.fq = second_stage_pays(p->D, d);
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
             const double kb = sort_keys_32(g) ? 4.0 : 8.0;
@@ -1471,7 +1472,7 @@ restart:
             const int kt = std::min(i_hi + 1, p->K);
             const int nw = fp_words(p->D);
             const int nq = fq_words(p->D);
-            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + nq)), 0.0, [&] {
+            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + (g.fq ? nq : 0))), 0.0, [&] {
                 return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->st);
             }));
             // Enumeration, verification and (single-round groups) replay, in
@@ -2015,6 +2016,7 @@ restart:
             g.ns = p->ns; g.D = p->D; g.NF = p->NF; g.NL = p->NL; g.m = p->m;
             g.j0 = j0; g.Ds = Ds; g.nseg = Bc * Ds; g.i = i; g.K = p->K; g.i_lo = i;
             g.hashed = i > 4; g.dhi = d_hi; g.part = 0; g.nparts = 1;
+            g.fq = second_stage_pays(p->D, dcur);
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
             const double kb = sort_keys_32(g) ? 4.0 : 8.0;
@@ -2028,7 +2030,7 @@ restart:
             }
             const int kt = std::min(i + 1, p->K);
             const int nw = fp_words(p->D), nq = fq_words(p->D);
-            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + nq)), 0.0, [&] {
+            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + (g.fq ? nq : 0))), 0.0, [&] {
                 return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->st);
             }));
             bool redo = false;
