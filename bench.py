@@ -288,6 +288,8 @@ def main() -> int:
     ap.add_argument("--max-pairs", type=float, default=5e13,
                     help="work budget in colliding pairs per round group (0: none)")
     ap.add_argument("--workers", type=int, default=4, help="series in flight (batch workloads)")
+    ap.add_argument("--n", type=float, default=0,
+                    help="series length instead of the workload's (e.g. the scal5 sweep 1e4 .. 1e8)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -307,7 +309,7 @@ def main() -> int:
     if args.workload in synth.BATCHES:
         return bench_batch(args, torch, mm, synth)
     t_gen = time.perf_counter()
-    s, p = synth.workload(args.workload)
+    s, p = synth.workload(args.workload, n=int(args.n) if args.n else None)
     proj = args.proj or p["proj"]
     cmp_proj = None if (args.no_compare or args.proj) else p.get("compare_proj")
     seed = synth.LSH_SEED[args.workload]

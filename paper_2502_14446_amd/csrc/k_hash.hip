@@ -13,6 +13,7 @@
 //                on MFMA; the epilogue quantises floor(v / r + U) and packs the
 //                four one-byte symbols of a half-function into one word.
 #include <hip/hip_runtime.h>
+
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
@@ -393,6 +394,8 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
 // for row l % 32 of A and column l % 32 of B; D as in the FP32 kernel.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2v __attribute__((ext_vector_type(2)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
 typedef int intx4 __attribute__((ext_vector_type(4)));
 
@@ -406,14 +409,23 @@ __host__ __device__ inline size_t lowp_stage_bytes(int proj, int Cpad)
     return proj == 2 ? (size_t)2 * Cpad * kRS * 2 : (size_t)2 * Cpad * kRS8;
 }
 
-template <typename T, int WB>
-__device__ inline double load_tile_offset(const T* __restrict__ xf, int64_t n, int64_t a_blk, int wpad,
-                                          float* xs)
+// The series tile four times, copy s shifted left by s elements
+// (xs4[s][i] = x[a_blk + i + s] - ref): the run of values x_hat_a[t .. t + 7]
+// a lane needs starts at a multiple of four in copy a mod 4, so it arrives
+// in aligned 16-byte reads. Copies lie XL apart, XL = WB + wpad rounded up to
+// 8 mod 64 elements: the four lanes that read the same offset of different
+// copies then hit different LDS banks.
+__host__ __device__ inline int shifted_stride(int WB, int wpad) { return (WB + wpad + 63) / 64 * 64 + 8; }
+template <typename T>
+__device__ inline double load_tile_shifted(const T* __restrict__ xf, int64_t n, int64_t a_blk, int XL, float* xs4)
 {
     const double ref = (double)xf[a_blk < n ? a_blk : n - 1];
-    for (int q = threadIdx.x; q < WB + wpad; q += 256) {
-        int64_t g = a_blk + q;
-        xs[q] = g < n ? (float)((double)xf[g] - ref) : 0.0f;
+    for (int q = threadIdx.x; q < XL; q += blockDim.x) {
+        const int64_t g = a_blk + q;
+        const float v = g < n ? (float)((double)xf[g] - ref) : 0.0f;
+#pragma unroll
+        for (int sh = 0; sh < 4; ++sh)
+            if (q >= sh) xs4[sh * XL + q - sh] = v;
     }
     return ref;
 }
@@ -444,25 +456,26 @@ __device__ inline void quantize_store(const floatx16 (&acc)[MB][NB], const float
         }
 }
 
-template <typename T, int MB, int NB>
-__global__ __launch_bounds__(256, 2) void k_proj_bf16(const T* __restrict__ x, int64_t n, int64_t ns,
+template <typename T, int MB, int NB, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_proj_bf16(const T* __restrict__ x, int64_t n, int64_t ns,
                                                    int w, int wpad, const double* __restrict__ mu,
                                                    const double* __restrict__ isig,
                                                    const __bf16* __restrict__ R,
                                                    const float* __restrict__ U, int Cpad, int NF,
                                                    int K, float inv_r, uint32_t* __restrict__ H)
 {
-    constexpr int WB = 4 * 32 * NB;
+    constexpr int WB = WAVES * 32 * NB, NT = 64 * WAVES;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float* xs = reinterpret_cast<float*>(smem_raw);
+    float* xs4 = reinterpret_cast<float*>(smem_raw);
+    const int XL = shifted_stride(WB, wpad);
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
-    const double ref = load_tile_offset<T, WB>(x + (int64_t)f * n, n, a_blk, wpad, xs);
-    __syncthreads();
+    const double ref = load_tile_shifted<T>(x + (int64_t)f * n, n, a_blk, XL, xs4);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 31, kk = lane >> 5;
     const int wbase = wave * 32 * NB;
     float sc[NB], off[NB];
+    const float* xb[NB];   // this lane's Hankel run: copy col mod 4, aligned
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int64_t a = a_blk + wbase + nb * 32 + col;
@@ -470,6 +483,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16(const T* __restrict__ x, i
         const double sg = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
         sc[nb] = (float)sg;
         off[nb] = (float)(-(m - ref) * sg);
+        xb[nb] = xs4 + (col & 3) * XL + wbase + nb * 32 + (col & ~3) + 8 * kk;
     }
     floatx16 acc[MB][NB];
 #pragma unroll
@@ -483,21 +497,21 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16(const T* __restrict__ x, i
     // from L2 for its own 64 windows); the next chunk is fetched into
     // registers while the current one feeds the MFMAs.
     const __bf16* Rf = R + (int64_t)f * Cpad * wpad;
-    __bf16* rs = reinterpret_cast<__bf16*>(xs + WB + wpad);   // 2 x [MB * 32][kRS]
+    __bf16* rs = reinterpret_cast<__bf16*>(xs4 + 4 * XL);      // 2 x [MB * 32][kRS]
     constexpr int PIECES = MB * 32 * (kRT / 8);                // 16-byte pieces per chunk
-    constexpr int ITEMS = (PIECES + 255) / 256;
+    constexpr int ITEMS = (PIECES + NT - 1) / NT;
     bf16x8 pre[ITEMS];
     auto fetch = [&](int t0) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int id = threadIdx.x + 256 * it, row = id / (kRT / 8), seg = id % (kRT / 8);
+            const int id = threadIdx.x + NT * it, row = id / (kRT / 8), seg = id % (kRT / 8);
             if (id < PIECES) pre[it] = *reinterpret_cast<const bf16x8*>(Rf + (int64_t)row * wpad + t0 + 8 * seg);
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int id = threadIdx.x + 256 * it, row = id / (kRT / 8), seg = id % (kRT / 8);
+            const int id = threadIdx.x + NT * it, row = id / (kRT / 8), seg = id % (kRT / 8);
             if (id < PIECES) *reinterpret_cast<bf16x8*>(rs + ((size_t)buf * MB * 32 + row) * kRS + 8 * seg) = pre[it];
         }
     };
@@ -505,28 +519,49 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16(const T* __restrict__ x, i
     fetch(0);
     stash(0);
     __syncthreads();
+    constexpr int NST = kRT / 16;   // MFMA steps of 16 t per chunk
     for (int c = 0; c < nchunks; ++c) {
         const int cur = c & 1;
         if (c + 1 < nchunks) fetch((c + 1) * kRT);
-        const __bf16* rb = rs + (size_t)cur * MB * 32 * kRS;
-#pragma unroll
-        for (int st = 0; st < kRT / 16; ++st) {
-            const int tl = st * 16 + 8 * kk, tb = c * kRT + tl;
-            bf16x8 av[MB], bv[NB];
+        const __bf16* rb = rs + (size_t)cur * MB * 32 * kRS + (size_t)col * kRS + 8 * kk;
+        // operands of step st + 1 are read from LDS while step st runs
+        bf16x8 av[2][MB];
+        float4 xv[2][NB][2];
+        auto load_step = [&](int st, int slot) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
-                av[mb] = *reinterpret_cast<const bf16x8*>(rb + (size_t)(mb * 32 + col) * kRS + tl);
+                av[slot][mb] = *reinterpret_cast<const bf16x8*>(rb + (size_t)mb * 32 * kRS + st * 16);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const float* xp = xs + wbase + nb * 32 + col + tb;
+                const float4* xp = reinterpret_cast<const float4*>(
+                    __builtin_assume_aligned(xb[nb] + c * kRT + st * 16, 16));
+                xv[slot][nb][0] = xp[0];
+                xv[slot][nb][1] = xp[1];
+            }
+        };
+        load_step(0, 0);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) bv[nb][q] = (__bf16)fmaf(xp[q], sc[nb], off[nb]);
+        for (int st = 0; st < NST; ++st) {
+            const int sl = st & 1;
+            if (st + 1 < NST) load_step(st + 1, sl ^ 1);
+            bf16x8 bv[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                // x_hat in FP32, rounded to bf16 two at a time
+                const float4 lo = xv[sl][nb][0], hi = xv[sl][nb][1];
+                const float s0 = sc[nb], o0 = off[nb];
+                const bf16x2 p0 = __builtin_convertvector((floatx2v){fmaf(lo.x, s0, o0), fmaf(lo.y, s0, o0)}, bf16x2);
+                const bf16x2 p1 = __builtin_convertvector((floatx2v){fmaf(lo.z, s0, o0), fmaf(lo.w, s0, o0)}, bf16x2);
+                const bf16x2 p2 = __builtin_convertvector((floatx2v){fmaf(hi.x, s0, o0), fmaf(hi.y, s0, o0)}, bf16x2);
+                const bf16x2 p3 = __builtin_convertvector((floatx2v){fmaf(hi.z, s0, o0), fmaf(hi.w, s0, o0)}, bf16x2);
+                bv[nb] = __builtin_shufflevector(__builtin_shufflevector(p0, p1, 0, 1, 2, 3),
+                                                 __builtin_shufflevector(p2, p3, 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
             }
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[sl][mb], bv[nb], acc[mb][nb], 0, 0, 0);
         }
         if (c + 1 < nchunks) stash(cur ^ 1);
         __syncthreads();
@@ -535,25 +570,26 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16(const T* __restrict__ x, i
                            H + (int64_t)f * NF * ns);
 }
 
-template <typename T, int MB, int NB>
-__global__ __launch_bounds__(256, 3) void k_proj_fp8(const T* __restrict__ x, int64_t n, int64_t ns,
+template <typename T, int MB, int NB, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 12 / WAVES) void k_proj_fp8(const T* __restrict__ x, int64_t n, int64_t ns,
                                                   int w, int wpad, const double* __restrict__ mu,
                                                   const double* __restrict__ isig,
                                                   const uint8_t* __restrict__ R,
                                                   const float* __restrict__ U, int Cpad, int NF,
                                                   int K, float inv_r, uint32_t* __restrict__ H)
 {
-    constexpr int WB = 4 * 32 * NB;
+    constexpr int WB = WAVES * 32 * NB, NT = 64 * WAVES;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float* xs = reinterpret_cast<float*>(smem_raw);
+    float* xs4 = reinterpret_cast<float*>(smem_raw);
+    const int XL = shifted_stride(WB, wpad);
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
-    const double ref = load_tile_offset<T, WB>(x + (int64_t)f * n, n, a_blk, wpad, xs);
-    __syncthreads();
+    const double ref = load_tile_shifted<T>(x + (int64_t)f * n, n, a_blk, XL, xs4);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 31, kk = lane >> 5;
     const int wbase = wave * 32 * NB;
     float sc[NB], off[NB];
+    const float* xb[NB];   // this lane's Hankel run: copy col mod 4, aligned
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int64_t a = a_blk + wbase + nb * 32 + col;
@@ -561,6 +597,7 @@ __global__ __launch_bounds__(256, 3) void k_proj_fp8(const T* __restrict__ x, in
         const double sg = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
         sc[nb] = (float)sg;
         off[nb] = (float)(-(m - ref) * sg);
+        xb[nb] = xs4 + (col & 3) * XL + wbase + nb * 32 + (col & ~3) + 32 * kk;
     }
     floatx16 acc[MB][NB];
 #pragma unroll
@@ -572,21 +609,21 @@ __global__ __launch_bounds__(256, 3) void k_proj_fp8(const T* __restrict__ x, in
     // projection rows staged through LDS as in the bf16 kernel (kRT8 steps of
     // t per chunk, one byte each)
     const uint8_t* Rf = R + (int64_t)f * Cpad * wpad;
-    uint8_t* rs = reinterpret_cast<uint8_t*>(xs + WB + wpad);   // 2 x [MB * 32][kRS8]
+    uint8_t* rs = reinterpret_cast<uint8_t*>(xs4 + 4 * XL);     // 2 x [MB * 32][kRS8]
     constexpr int PIECES = MB * 32 * (kRT8 / 16);               // 16-byte pieces per chunk
-    constexpr int ITEMS = (PIECES + 255) / 256;
+    constexpr int ITEMS = (PIECES + NT - 1) / NT;
     intx4 pre[ITEMS];
     auto fetch = [&](int t0) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int id = threadIdx.x + 256 * it, row = id / (kRT8 / 16), seg = id % (kRT8 / 16);
+            const int id = threadIdx.x + NT * it, row = id / (kRT8 / 16), seg = id % (kRT8 / 16);
             if (id < PIECES) pre[it] = *reinterpret_cast<const intx4*>(Rf + (int64_t)row * wpad + t0 + 16 * seg);
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int id = threadIdx.x + 256 * it, row = id / (kRT8 / 16), seg = id % (kRT8 / 16);
+            const int id = threadIdx.x + NT * it, row = id / (kRT8 / 16), seg = id % (kRT8 / 16);
             if (id < PIECES) *reinterpret_cast<intx4*>(rs + ((size_t)buf * MB * 32 + row) * kRS8 + 16 * seg) = pre[it];
         }
     };
@@ -600,20 +637,22 @@ __global__ __launch_bounds__(256, 3) void k_proj_fp8(const T* __restrict__ x, in
         const uint8_t* rb = rs + (size_t)cur * MB * 32 * kRS8;
 #pragma unroll
         for (int st = 0; st < kRT8 / 64; ++st) {
-        const int tl = st * 64 + 32 * kk, tb = c * kRT8 + tl;
+        const int tl = st * 64 + 32 * kk;
         intx8 av[MB], bv[NB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
             av[mb] = *reinterpret_cast<const intx8*>(rb + (size_t)(mb * 32 + col) * kRS8 + tl);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const float* xp = xs + wbase + nb * 32 + col + tb;
+            const float4* xp = reinterpret_cast<const float4*>(
+                __builtin_assume_aligned(xb[nb] + c * kRT8 + st * 64, 16));
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                int v = __builtin_amdgcn_cvt_pk_fp8_f32(fmaf(xp[4 * q + 0], sc[nb], off[nb]),
-                                                        fmaf(xp[4 * q + 1], sc[nb], off[nb]), 0, false);
-                v = __builtin_amdgcn_cvt_pk_fp8_f32(fmaf(xp[4 * q + 2], sc[nb], off[nb]),
-                                                    fmaf(xp[4 * q + 3], sc[nb], off[nb]), v, true);
+                const float4 v4 = xp[q];
+                int v = __builtin_amdgcn_cvt_pk_fp8_f32(fmaf(v4.x, sc[nb], off[nb]),
+                                                        fmaf(v4.y, sc[nb], off[nb]), 0, false);
+                v = __builtin_amdgcn_cvt_pk_fp8_f32(fmaf(v4.z, sc[nb], off[nb]),
+                                                    fmaf(v4.w, sc[nb], off[nb]), v, true);
                 bv[nb][q] = v;
             }
         }
@@ -639,23 +678,27 @@ static hipError_t go_lowp(int proj, const T* x, int64_t n, int64_t ns, int D, in
     // windows per wave: 64 for bf16 (two 32-wide MFMA columns share each
     // projection operand), 32 for fp8, whose Hankel operand costs four times
     // the VALU work per MFMA (measured; either way two or more waves per SIMD)
+    // four waves of 64 (bf16) or 32 (fp8) windows per work-group, two (bf16)
+    // or three (fp8) work-groups per CU: eight-wave groups and a lower
+    // occupancy measured slower
+    constexpr int WAVES = 4;
     if (proj == 2) {
-        constexpr int NB = 2, WB = 4 * 32 * NB;
+        constexpr int NB = 2, WB = WAVES * 32 * NB;
         dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-        const size_t lds = (size_t)(WB + wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
+        const size_t lds = (size_t)4 * shifted_stride(WB, wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
         if (lds > 65536)
-            (void)hipFuncSetAttribute((const void*)k_proj_bf16<T, MB, NB>,
+            (void)hipFuncSetAttribute((const void*)k_proj_bf16<T, MB, NB, WAVES>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_proj_bf16<T, MB, NB>), grid, dim3(256), lds, s, x, n, ns, w, wpad, mu,
+        hipLaunchKernelGGL((k_proj_bf16<T, MB, NB, WAVES>), grid, dim3(64 * WAVES), lds, s, x, n, ns, w, wpad, mu,
                            isig, (const __bf16*)R, U, Cpad, NF, K, inv_r, H);
     } else {
-        constexpr int NB = 1, WB = 4 * 32 * NB;
+        constexpr int NB = 1, WB = WAVES * 32 * NB;
         dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-        const size_t lds = (size_t)(WB + wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
+        const size_t lds = (size_t)4 * shifted_stride(WB, wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
         if (lds > 65536)
-            (void)hipFuncSetAttribute((const void*)k_proj_fp8<T, MB, NB>,
+            (void)hipFuncSetAttribute((const void*)k_proj_fp8<T, MB, NB, WAVES>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_proj_fp8<T, MB, NB>), grid, dim3(256), lds, s, x, n, ns, w, wpad, mu,
+        hipLaunchKernelGGL((k_proj_fp8<T, MB, NB, WAVES>), grid, dim3(64 * WAVES), lds, s, x, n, ns, w, wpad, mu,
                            isig, (const uint8_t*)R, U, Cpad, NF, K, inv_r, H);
     }
     return hipGetLastError();

@@ -1498,11 +1498,13 @@ restart:
                 {
                     // sizes known only now: the enumeration read every key once and
                     // every run member's index and fingerprint row once (pairs that
-                    // pass the screen re-read 4 D index words: negligible);
+                    // pass the screen re-read 4 D index words: negligible), and
+                    // screened each pair of a run with one XOR and one OR per row
+                    // word, a popcount per 32 dimensions and a compare;
                     // verification read 2 D w samples per candidate
                     const uint32_t nc = std::min(cnt.n_cand, p->cap);
                     prof_set(p, enum_slot, elems * kb + (double)cnt.n_memb * (4.0 + 4.0 * nw),
-                             (double)cnt.n_coll * (5.0 * nw + 1.0));
+                             (double)cnt.n_coll * (2.0 * nw + (p->D + 31) / 32 + 1.0));
                     prof_set(p, verify_slot, (double)nc * (2.0 * p->D * p->w * elem_x + 32.0 * p->D + sizeof(VRec)),
                              (double)nc * 6.0 * p->D * p->w);
                     prof_flush(p);

@@ -113,9 +113,27 @@ def plant(rng: np.random.Generator, x: np.ndarray, w: int, motifs: Sequence[Moti
     return out
 
 
+def plant_sine(rng: np.random.Generator, x: np.ndarray, w: int, motifs: Sequence[Motif],
+               noise: float) -> np.ndarray:
+    """Plant each motif as a sinusoid (period uniform in [w/10, w/2], amplitude
+    1, random phase; one shape per dimension of the motif) written over both
+    windows from the series' level at the window start, then add independent
+    N(0, noise^2) noise to both copies."""
+    out = x.copy()
+    t = np.arange(w, dtype=np.float64)
+    for m in motifs:
+        for f in m.dims:
+            period = rng.uniform(w / 10.0, w / 2.0)
+            phase = rng.uniform(0.0, 2.0 * math.pi)
+            shape = np.sin(2.0 * math.pi * t / period + phase)
+            for p in (m.p1, m.p2):
+                out[f, p:p + w] = out[f, p] + shape - shape[0] + noise * rng.standard_normal(w)
+    return out
+
+
 def make_series(seed: int, D: int, n: int, w: int, n_motifs: int, motif_dims: int,
                 noise: float = 0.05, dtype: str = "f64", sinusoids: bool = False,
-                min_gap: int = 0) -> Series:
+                min_gap: int = 0, motif: str = "walk") -> Series:
     rng = np.random.default_rng(seed)
     x = random_walk(rng, D, n)
     if sinusoids:
@@ -126,7 +144,7 @@ def make_series(seed: int, D: int, n: int, w: int, n_motifs: int, motif_dims: in
         for p1, p2 in pos:
             dims = tuple(sorted(int(v) for v in rng.choice(D, size=motif_dims, replace=False)))
             motifs.append(Motif(dims, p1, p2))
-        x = plant(rng, x, w, motifs, noise)
+        x = plant_sine(rng, x, w, motifs, noise) if motif == "sine" else plant(rng, x, w, motifs, noise)
     if dtype == "f32":
         x = x.astype(np.float32).astype(np.float64)
     return Series(np.ascontiguousarray(x), w, motifs, dtype)
@@ -150,10 +168,21 @@ WORKLOADS = {
     # large fp8: D=128, n=1e6, w=500, d=16, k=50, delta=0.01, 64 GB cap
     "rw128_1m": dict(D=128, n=1_000_000, w=500, d=16, k=50, delta=0.01, n_motifs=50,
                      motif_dims=16, dtype="f32", proj="fp8", mem_limit=64_000_000_000, r_scale=6.0),
+    # the paper's scalability series (section 7, "Scalability"): D=5 random
+    # walk, one sinusoidal motif of length 300 in 2 dimensions with Gaussian
+    # noise, the top-1 2-dimensional motif; n from 1e4 to 1e8 (--n). Noise
+    # 0.04 (per-dimension distance of the planted pair about 1.4) and r at 4
+    # times the estimate: with the estimate itself no step stops above the
+    # exact fallback at n = 2e4
+    "scal5": dict(D=5, n=1_000_000, w=300, d=2, k=1, delta=0.1, n_motifs=1, motif_dims=2,
+                  dtype="f32", proj="f32", motif="sine", noise=0.04, r_scale=4.0,
+                  mem_limit=200_000_000_000),
 }
 
-DATA_SEED = {"tiny": 0xD00D01, "rw8_1m": 0xD00D02, "rwsin32_4m": 0xD00D03, "rw128_1m": 0xD00D05}
-LSH_SEED = {"tiny": 0x15A001, "rw8_1m": 0x15A002, "rwsin32_4m": 0x15A003, "rw128_1m": 0x15A005}
+DATA_SEED = {"tiny": 0xD00D01, "rw8_1m": 0xD00D02, "rwsin32_4m": 0xD00D03, "rw128_1m": 0xD00D05,
+             "scal5": 0xD00D06}
+LSH_SEED = {"tiny": 0x15A001, "rw8_1m": 0x15A002, "rwsin32_4m": 0x15A003, "rw128_1m": 0x15A005,
+            "scal5": 0x15A006}
 
 
 def workload(name: str, n: int | None = None, seed: int | None = None) -> Tuple[Series, dict]:
@@ -172,7 +201,8 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> Tuple[
         s = Series(z["x"], p["w"], motifs, p["dtype"])
     else:
         s = make_series(sd, p["D"], nn, p["w"], p["n_motifs"], p["motif_dims"], dtype=p["dtype"],
-                        sinusoids=p.get("sinusoids", False), min_gap=p.get("min_gap", 0))
+                        sinusoids=p.get("sinusoids", False), min_gap=p.get("min_gap", 0),
+                        noise=p.get("noise", 0.05), motif=p.get("motif", "walk"))
         if path:
             os.makedirs(cache, exist_ok=True)
             width = 2 + max((len(m.dims) for m in s.motifs), default=0)
