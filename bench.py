@@ -147,8 +147,11 @@ def flip_rate(plan, series, p, seed: int, r: float, cells: int = 4096) -> dict:
 
 
 def bench_batch(args, torch, mm, synth) -> int:
-    """Many independent series through momenti_topk_batch: one step is the
-    whole batch; also timed with one worker for comparison."""
+    """Many independent series through momenti_topk_batch, in waves of
+    --wave series (each wave one call, --workers in flight); one step is the
+    whole batch. With --tune the repetitions per launch come from the
+    autotuner run on the batch's largest series; the first wave is also
+    timed with one worker (the series one at a time)."""
     spec = dict(synth.BATCHES[args.workload])
     spec_r = spec.pop("r_scale", 1.0)
     ser = synth.batch_workload(synth.BATCH_SEED, **spec)
@@ -158,9 +161,28 @@ def bench_batch(args, torch, mm, synth) -> int:
     units = sum((q["n"] - q["w"] + 1) * q["D"] for _, q in ser)
     r_scale = args.r_scale if args.r_scale > 0 else spec_r
     kw = dict(mem_limit=8 << 30, seed=0x15A004, max_pairs=args.max_pairs, r_scale=r_scale)
+    tuned = None
+    if args.tune:
+        big = max(range(len(ser)), key=lambda q: ser[q][1]["n"] * ser[q][1]["D"])
+        xq, pq = ser[big]
+        plan = mm.Plan(pq["n"], pq["D"], pq["w"], "f32", kw["mem_limit"], device_series=True,
+                       seed=kw["seed"], max_pairs=kw["max_pairs"], r_scale=r_scale)
+        plan.hash(jobs[big]["series"])
+        best, bms = plan.tune(pq["d"], pq["k"], pq["delta"], cands=(2, 4, 8, 16, 32))
+        plan.close()
+        tuned = {"series": big, "n": pq["n"], "D": pq["D"], "batch_reps": best, "search_ms": bms}
+        kw["batch_reps"] = best
+        log(f"[bench] tuned on series {big} (n={pq['n']}, D={pq['D']}): {best} repetitions per launch")
+    wave = max(1, args.wave)
 
-    def run(workers):
-        res, rc = mm.topk_batch(jobs, workers=workers, **kw)
+    def run(workers, count=None):
+        res, rc = [], 0
+        last = len(jobs) if count is None else count
+        for q0 in range(0, last, wave):
+            r, c = mm.topk_batch(jobs[q0:min(last, q0 + wave)], workers=workers, **kw)
+            res += r
+            rc = rc or c
+            log(f"[bench]   series {q0}..{min(last, q0 + wave) - 1} done")
         return res, rc
 
     for wi in range(args.warmup):
@@ -172,9 +194,15 @@ def bench_batch(args, torch, mm, synth) -> int:
         log(f"[bench] batch step {si}: rc {rc}")
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    n0 = min(wave, len(jobs))
     t1 = time.perf_counter()
-    run(1)
+    run(args.workers, n0)
+    msw = (time.perf_counter() - t1) * 1000.0
+    t1 = time.perf_counter()
+    res1, _ = run(1, n0)
     ms1 = (time.perf_counter() - t1) * 1000.0
+    same = all([(m["a"], m["b"]) for m in a[0]] == [(m["a"], m["b"]) for m in b[0]] and a[2] == b[2]
+               for a, b in zip(res[:n0], res1))
     st = [r[2] for r in res]
     planted = sum(len({(m.p1, m.p2) for m in x.motifs} & {(g["a"], g["b"]) for g in r[0]})
                   for (x, _), r in zip(ser, res))
@@ -183,10 +211,12 @@ def bench_batch(args, torch, mm, synth) -> int:
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "series": len(jobs), "workers": args.workers,
+        "config": {"workload": args.workload, "series": len(jobs), "workers": args.workers, "wave": wave,
                    "max_pairs": args.max_pairs, "r_scale": r_scale,
                    **{k: v for k, v in spec.items() if k != "count"}},
-        "series_per_s": len(jobs) / (ms / 1000.0), "ms_one_worker": ms1,
+        "series_per_s": len(jobs) / (ms / 1000.0),
+        "first_wave": {"series": n0, "ms_workers": msw, "ms_one_worker": ms1, "answers_identical": same},
+        "tuned": tuned,
         "status_counts": {str(v): st.count(v) for v in sorted(set(st))},
         "planted_recovered": planted, "planted_total": sum(len(x.motifs) for x, _ in ser),
         "roofline": None, "cpu_baseline": None,
@@ -288,6 +318,9 @@ def main() -> int:
     ap.add_argument("--max-pairs", type=float, default=5e13,
                     help="work budget in colliding pairs per round group (0: none)")
     ap.add_argument("--workers", type=int, default=4, help="series in flight (batch workloads)")
+    ap.add_argument("--wave", type=int, default=64, help="series per batch call (batch workloads)")
+    ap.add_argument("--tune", action="store_true",
+                    help="batch workloads: repetitions per launch from the autotuner")
     ap.add_argument("--n", type=float, default=0,
                     help="series length instead of the workload's (e.g. the scal5 sweep 1e4 .. 1e8)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -343,6 +376,7 @@ def main() -> int:
         "stop": {proj: [rep["i_stop"], rep["j_stop"]]}, "r": prm["r"], "status": {proj: rc},
         "n_cand": rep["n_cand"], "n_collisions": rep["n_collisions"],
         "planted_recovered": {proj: f"{len(planted & set(found))}/{len(planted)}"},
+        "top3": [[m["a"], m["b"], m["dist_d"], m["dist_max"]] for m in got[:3]],
     }
     if prof_on and lead["prof"]:
         out["kernel_ms_per_step"] = {proj: {k: round(v["ms"], 3) for k, v in lead["prof"].items() if v["launches"]}}
@@ -360,6 +394,8 @@ def main() -> int:
             dd, dm, dims, _ = oracle.distd(s.x, p["w"], m["a"], m["b"], p["d"])
             err = max(err, abs(m["dist_d"] - dd) / dd, abs(m["dist_max"] - dm) / dm)
         out["dist_rel_err_vs_fp64"] = {proj: err}
+        out["planted_dist"] = [[m.p1, m.p2, *oracle.distd(s.x, p["w"], m.p1, m.p2, p["d"])[:2]]
+                               for m in s.motifs[:10]]
     lead["plan"].close()
     if cmp_proj:
         leg = run_leg(args, torch, mm, s, p, x, cmp_proj, seed, r_scale, args.compare_steps, 1, prof_on)

@@ -252,6 +252,19 @@ int momenti_search_noalloc(momenti_plan* p, int32_t d, int32_t k, double delta, 
 int momenti_search_multi(momenti_plan* p, int32_t d_lo, int32_t d_hi, int32_t k, double delta,
                          momenti_motif* out, int32_t* n_out, int32_t* status, momenti_report* reps);
 
+/* Autotuning of the repetitions traversed per launch (opts.batch_reps),
+ * which changes the cost of a search but not its steps or answer (the
+ * verified pairs are replayed in step order). Runs momenti_search(p, d, k,
+ * delta) once untimed, then once per candidate cands[0 .. ncand) (1 .. 64,
+ * ncand 1 .. 16), checks that every answer and stop step equals the first,
+ * and keeps the fastest in the plan's options (later searches use it).
+ * best_reps receives it (as the search used it: mem_limit may lower a
+ * candidate), best_ms (nullable) its search time. Returns MOMENTI_OK, an
+ * error of momenti_search, E_DEVICE if two answers differ, E_STATE for a plan
+ * in scratch mode. */
+int momenti_tune(momenti_plan* p, int32_t d, int32_t k, double delta, const int32_t* cands, int32_t ncand,
+                 int32_t* best_reps, double* best_ms);
+
 /* One call: prepare + hash + search + destroy. Arguments as above. */
 int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_t w, int32_t d,
                  int32_t k, double delta, uint64_t mem_limit, const momenti_opts* opts,

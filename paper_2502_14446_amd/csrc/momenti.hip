@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <mutex>
 #include <new>
 #include <string>
@@ -2255,6 +2256,71 @@ extern "C" int momenti_search_noalloc(momenti_plan* p, int32_t d, int32_t k, dou
     p->prof.on = prof_on;
     if (rc >= 0 && e != hipSuccess) return fail(MOMENTI_E_DEVICE, "search without allocations: %s", hipGetErrorString(e));
     return rc;
+}
+
+// ------------------------------------------------------------------ autotuning
+// The repetitions traversed per launch (B) change only the cost of a search:
+// the ordered replay makes TOP after every step, the stop step and the answer
+// independent of B. The tuner runs the search once per candidate B on the
+// plan's index (after one untimed search for the allocations), checks that
+// every answer is the same, and keeps the fastest B in the plan's options.
+extern "C" int momenti_tune(momenti_plan* p, int32_t d, int32_t k, double delta, const int32_t* cands,
+                            int32_t ncand, int32_t* best_reps, double* best_ms)
+{
+    g_err.clear();
+    if (!p || !cands || !best_reps) return fail(MOMENTI_E_ARG, "NULL argument");
+    if (ncand < 1 || ncand > 16) return fail(MOMENTI_E_ARG, "ncand=%d outside [1, 16]", ncand);
+    if (!p->hashed) return fail(MOMENTI_E_STATE, "momenti_hash has not been called");
+    if (p->arena) return fail(MOMENTI_E_STATE, "not available without allocations");
+    const int saved = p->o.batch_reps;
+    std::vector<momenti_motif> ref((size_t)std::max(k, 1)), out((size_t)std::max(k, 1));
+    momenti_report rref{}, r{};
+    int nref = -1, rcref = 0, n = 0;
+    double bt = std::numeric_limits<double>::infinity();
+    int bB = 0;
+    std::vector<int> tried;
+    for (int q = -1; q < ncand; ++q) {
+        const int B = q < 0 ? cands[0] : cands[q];
+        if (B < 1 || B > 64) {
+            p->o.batch_reps = saved;
+            return fail(MOMENTI_E_ARG, "candidate batch size %d outside [1, 64]", B);
+        }
+        p->o.batch_reps = B;
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rc = momenti_search(p, d, k, delta, out.data(), &n, &r);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (rc < 0) {
+            p->o.batch_reps = saved;
+            return rc;
+        }
+        if (q < 0) {   // the untimed first search: the reference answer
+            ref = out;
+            nref = n;
+            rref = r;
+            rcref = rc;
+            continue;
+        }
+        bool same = rc == rcref && n == nref && r.i_stop == rref.i_stop && r.j_stop == rref.j_stop;
+        for (int u = 0; same && u < n; ++u)
+            same = out[u].a == ref[u].a && out[u].b == ref[u].b && out[u].dist_d == ref[u].dist_d &&
+                   out[u].dist_max == ref[u].dist_max;
+        if (!same) {
+            p->o.batch_reps = saved;
+            return fail(MOMENTI_E_DEVICE, "the answer with %d repetitions per launch differs from the one with %d",
+                        B, cands[0]);
+        }
+        // B as the search used it (the memory budget may lower it)
+        if (std::find(tried.begin(), tried.end(), r.batch_reps) != tried.end()) continue;
+        tried.push_back(r.batch_reps);
+        if (ms < bt) {
+            bt = ms;
+            bB = r.batch_reps;
+        }
+    }
+    p->o.batch_reps = bB;
+    *best_reps = bB;
+    if (best_ms) *best_ms = bt;
+    return MOMENTI_OK;
 }
 
 extern "C" int momenti_topk(const void* series, int32_t dtype, int64_t n, int32_t D, int32_t w,

@@ -29,7 +29,7 @@ EXPORTS = [
     "momenti_get_hashes", "momenti_set_hashes", "momenti_set_trace", "momenti_get_profile",
     "momenti_set_profile",
     "momenti_topk_batch", "momenti_get_hash_words", "momenti_search_noalloc",
-    "momenti_search_multi",
+    "momenti_search_multi", "momenti_tune",
 ]
 
 
@@ -93,6 +93,7 @@ def lib():
             "momenti_search": (i32, [vp, i32, i32, d, P(Motif), P(i32), P(Report)]),
             "momenti_search_noalloc": (i32, [vp, i32, i32, d, P(Motif), P(i32), P(Report)]),
             "momenti_search_multi": (i32, [vp, i32, i32, i32, d, P(Motif), P(i32), P(i32), P(Report)]),
+            "momenti_tune": (i32, [vp, i32, i32, d, P(i32), i32, P(i32), P(d)]),
             "momenti_topk": (i32, [vp, i32, i64, i32, i32, i32, i32, d, u64, P(Opts), P(Motif),
                                    P(i32), P(Report)]),
             "momenti_destroy": (None, [vp]),
@@ -236,6 +237,13 @@ class Plan:
         _check(lib().momenti_search_multi(self.h, d_lo, d_hi, k, delta, arr, got, status, reps))
         return {d_lo + q: (_motifs(arr[q * k:(q + 1) * k], got[q]), _report(reps[q]), status[q])
                 for q in range(nd)}
+
+    def tune(self, d: int, k: int, delta: float, cands=(4, 8, 16, 32)) -> Tuple[int, float]:
+        """momenti_tune: the fastest repetitions per launch among cands (kept by the plan)."""
+        arr = (C.c_int32 * len(cands))(*cands)
+        best, ms = C.c_int32(), C.c_double()
+        _check(lib().momenti_tune(self.h, d, k, delta, arr, len(cands), C.byref(best), C.byref(ms)))
+        return best.value, ms.value
 
     def params(self) -> Dict:
         r, L, nl, nr = C.c_double(), C.c_int32(), C.c_int32(), C.c_int32()

@@ -498,3 +498,21 @@ def test_multi_d_search_with_one_d_and_a_step_budget(orc):
         assert st == single[d][2] == mm.OK_PARTIAL and rep["n_steps"] == 7
         _compare_motifs(got, single[d][0])
         assert [m["fail_prob"] for m in got] == pytest.approx([m["fail_prob"] for m in single[d][0]], rel=1e-12)
+
+
+# --------------------------------------------------------------------------- autotuning
+def test_tuner_keeps_the_answer_and_the_plan_uses_its_choice(orc):
+    # repetitions per launch change the cost only: the tuner checks every
+    # candidate's answer against the first and keeps the fastest; the next
+    # search runs with it and gives the oracle's answer and stop step
+    s = synth.make_series(34, 5, 3000, 40, 3, 2, noise=0.02, dtype="f64")
+    plan, _ = _plan(s, dict(w=40, mem_limit=1 << 30), "f64", 8, K=8, L=40, stop="tensor", r_scale=2.0)
+    best, ms = plan.tune(2, 3, 0.1, cands=(1, 3, 8, 40))
+    got, rep, rc = plan.search(2, 3, 0.1)
+    prm = plan.params()
+    plan.close()
+    assert best in (1, 3, 8, 40) and ms > 0.0 and rep["batch_reps"] == best
+    ref = orc.lsh_pipeline(s.x, 40, 2, 3, 0.1, 8, L_max=40, mem_limit=1 << 30, r_scale=2.0)
+    assert (rep["i_stop"], rep["j_stop"]) == (ref["i_stop"], ref["J_stop"]) and rc == mm.OK
+    _compare_motifs(got, ref["motifs"])
+    assert prm["L"] == 40
