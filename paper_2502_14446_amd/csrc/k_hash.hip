@@ -136,24 +136,45 @@ hipError_t launch_stats(const void* x, int dtype, int64_t n, int64_t ns, int D, 
 // two-pass definition, the normal form (x - mu) / sigma (zeros if flat), and
 // its dot product with each sample vector, all sequential in t, without
 // fused multiply-add (the library is built with -ffp-contract=off).
+// One wavefront takes G sampled windows, staged in LDS with coalesced loads
+// when they fit, and one lane per (window, vector): the lanes of a window
+// walk the same LDS words (broadcast reads), each with its own vector.
+// Every lane computes its window's statistics itself, in the same order.
 // ---------------------------------------------------------------------------
+constexpr int kRsLds = 48 * 1024;   // LDS for the staged windows of one wavefront
+
 template <typename T>
-__global__ void k_rsample(const T* __restrict__ x, int64_t n, int D, int w,
-                          const int64_t* __restrict__ win, int S, const double* __restrict__ vec,
-                          int nvec, double* __restrict__ dots)
+__global__ __launch_bounds__(64) void k_rsample(const T* __restrict__ x, int64_t n, int D, int w,
+                                                const int64_t* __restrict__ win, int S,
+                                                const double* __restrict__ vec, int nvec, int VT,
+                                                int G, bool staged, double* __restrict__ dots)
 {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (int64_t)D * S) return;
-    const int f = (int)(id / S);
-    const T* xa = x + (int64_t)f * n + win[id];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);
+    const int64_t total = (int64_t)D * S;
+    const int64_t id0 = (int64_t)blockIdx.x * G;
+    const int lane = threadIdx.x, slot = lane / VT, vi = lane - slot * VT;
+    if (staged) {
+        for (int g = 0; g < G; ++g) {
+            const int64_t id = id0 + g;
+            if (id >= total) break;
+            const T* src = x + (id / S) * n + win[id];
+            for (int t = lane; t < w; t += 64) xs[(size_t)g * w + t] = src[t];
+        }
+        __syncthreads();
+    }
+    const int64_t id = id0 + slot;
+    if (slot >= G || id >= total) return;
+    const T* xa = staged ? xs + (size_t)slot * w : x + (id / S) * n + win[id];
     double mu, m2, sigma;
     direct_stats(xa, w, mu, m2, sigma);
     const bool flat = sigma <= kFlatRel * fabs(mu);
-    for (int v = 0; v < nvec; ++v) {
+    for (int v = vi; v < nvec; v += VT) {
+        const double* vv = vec + (int64_t)v * w;
         double dot = 0.0;
         for (int t = 0; t < w; ++t) {
             double z = flat ? 0.0 : ((double)xa[t] - mu) / sigma;
-            dot = dot + vec[(int64_t)v * w + t] * z;
+            dot = dot + vv[t] * z;
         }
         dots[id * nvec + v] = dot;
     }
@@ -163,13 +184,20 @@ hipError_t launch_rsample(const void* x, int dtype, int64_t n, int D, int w, con
                           int S, const double* vec, int nvec, double* dots, hipStream_t s)
 {
     const int64_t total = (int64_t)D * S;
-    dim3 grid((unsigned)((total + 127) / 128));
+    const size_t elem = dtype == 0 ? 8 : 4;
+    // lanes per window (one per vector, up to 64) and windows per wavefront
+    const int VT = nvec < 64 ? nvec : 64;
+    int G = 64 / VT;
+    while (G > 1 && (size_t)G * w * elem > (size_t)kRsLds) --G;
+    const bool staged = (size_t)G * w * elem <= (size_t)kRsLds;
+    const size_t lds = staged ? (size_t)G * w * elem : 0;
+    dim3 grid((unsigned)((total + G - 1) / G));
     if (dtype == 0)
-        hipLaunchKernelGGL(k_rsample<double>, grid, dim3(128), 0, s, (const double*)x, n, D, w,
-                           win, S, vec, nvec, dots);
+        hipLaunchKernelGGL(k_rsample<double>, grid, dim3(64), lds, s, (const double*)x, n, D, w,
+                           win, S, vec, nvec, VT, G, staged, dots);
     else
-        hipLaunchKernelGGL(k_rsample<float>, grid, dim3(128), 0, s, (const float*)x, n, D, w,
-                           win, S, vec, nvec, dots);
+        hipLaunchKernelGGL(k_rsample<float>, grid, dim3(64), lds, s, (const float*)x, n, D, w,
+                           win, S, vec, nvec, VT, G, staged, dots);
     return hipGetLastError();
 }
 

@@ -526,25 +526,36 @@ __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H,
     uint32_t* fw = fps + gid * nw;
     uint32_t* qw = fq + gid * nq;
     // chunks of 32 dimensions (one chunk unless D > 32), each as four groups
-    // of 8 whose digests are gathered byte by byte and then transposed
+    // of 8 whose digests are gathered byte by byte and then transposed. Every
+    // index word of a chunk is loaded before the first is used (a dimension
+    // past D reloads the last one and is masked out), so a thread waits out
+    // one memory latency per chunk, not one per dimension.
+    constexpr int CD = DP < 32 ? DP : 32;   // dimensions per chunk
+    const int64_t lstep = (int64_t)g.NF * g.ns;
+    const uint32_t* Lb = H + (int64_t)l * g.ns + a;
+    const uint32_t* Rb = H + (int64_t)(g.NL + r) * g.ns + a;
     for (int c0 = 0; c0 < g.D; c0 += 32) {
+        uint32_t Lw[CD], Rw[CD];
+#pragma unroll
+        for (int u = 0; u < CD; ++u) {
+            const int f = c0 + u < g.D ? c0 + u : g.D - 1;
+            Lw[u] = Lb[f * lstep];
+            Rw[u] = __builtin_nontemporal_load(Rb + f * lstep);
+        }
         uint64_t t8[4], tl[4], th[4];
 #pragma unroll
         for (int gq = 0; gq < 4; ++gq) {
             uint64_t b8 = 0, bl = 0, bh = 0;
-            if (8 * gq < DP) {
+            if (8 * gq < CD) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int f = c0 + 8 * gq + u;
-                    if (f < g.D) {
-                        const uint32_t L = H[((int64_t)f * g.NF + l) * g.ns + a];
-                        const uint32_t R = H[((int64_t)f * g.NF + g.NL + r) * g.ns + a];
-                        const uint64_t pre = make_key<uint64_t>(L, R, g.i_lo);
-                        const uint32_t d16 = prefix_digest16(pre, g.i_lo);
-                        b8 |= (uint64_t)prefix_digest8(pre, g.i_lo) << (8 * u);
-                        bl |= (uint64_t)(d16 & 0xFFu) << (8 * u);
-                        bh |= (uint64_t)(d16 >> 8) << (8 * u);
-                    }
+                    const int uu = 8 * gq + u;
+                    const uint64_t pre = make_key<uint64_t>(Lw[uu], Rw[uu], g.i_lo);
+                    const uint32_t d16 = prefix_digest16(pre, g.i_lo);
+                    const uint64_t keep = c0 + uu < g.D ? 0xFFull : 0ull;
+                    b8 |= ((uint64_t)prefix_digest8(pre, g.i_lo) & keep) << (8 * u);
+                    bl |= ((uint64_t)(d16 & 0xFFu) & keep) << (8 * u);
+                    bh |= ((uint64_t)(d16 >> 8) & keep) << (8 * u);
                 }
             }
             t8[gq] = transpose8(b8);
