@@ -241,9 +241,19 @@ __global__ __launch_bounds__(256) void k_proj_f64(const T* __restrict__ x, int64
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
     const T* xf = x + (int64_t)f * n;
-    for (int q = threadIdx.x; q < WB + wpad; q += 256) {
-        int64_t g = a_blk + q;
-        xs[q] = g < n ? xf[g] : T(0);
+    // the tile's loads in batches of eight per thread before the first use
+    for (int q0 = 0; q0 < WB + wpad; q0 += 8 * 256) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 256 + (int)threadIdx.x;
+            v[u] = q < WB + wpad && a_blk + q < n ? xf[a_blk + q] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 256 + (int)threadIdx.x;
+            if (q < WB + wpad) xs[q] = v[u];
+        }
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -318,9 +328,19 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
     const T* xf = x + (int64_t)f * n;
-    for (int q = threadIdx.x; q < WB + wpad; q += 256) {
-        int64_t g = a_blk + q;
-        xs[q] = g < n ? xf[g] : T(0);
+    // the tile's loads in batches of eight per thread before the first use
+    for (int q0 = 0; q0 < WB + wpad; q0 += 8 * 256) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 256 + (int)threadIdx.x;
+            v[u] = q < WB + wpad && a_blk + q < n ? xf[a_blk + q] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 256 + (int)threadIdx.x;
+            if (q < WB + wpad) xs[q] = v[u];
+        }
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -444,16 +464,31 @@ __host__ __device__ inline size_t lowp_stage_bytes(int proj, int Cpad)
 // 8 mod 64 elements: the four lanes that read the same offset of different
 // copies then hit different LDS banks.
 __host__ __device__ inline int shifted_stride(int WB, int wpad) { return (WB + wpad + 63) / 64 * 64 + 8; }
+// Loads are issued in batches of eight per thread before the first is
+// used, so a work-group waits out one memory latency per batch rather than
+// one per element it stages.
 template <typename T>
 __device__ inline double load_tile_shifted(const T* __restrict__ xf, int64_t n, int64_t a_blk, int XL, float* xs4)
 {
+    constexpr int PRE = 8;
     const double ref = (double)xf[a_blk < n ? a_blk : n - 1];
-    for (int q = threadIdx.x; q < XL; q += blockDim.x) {
-        const int64_t g = a_blk + q;
-        const float v = g < n ? (float)((double)xf[g] - ref) : 0.0f;
+    for (int q0 = 0; q0 < XL; q0 += PRE * (int)blockDim.x) {
+        T v[PRE];
 #pragma unroll
-        for (int sh = 0; sh < 4; ++sh)
-            if (q >= sh) xs4[sh * XL + q - sh] = v;
+        for (int u = 0; u < PRE; ++u) {
+            const int q = q0 + u * (int)blockDim.x + (int)threadIdx.x;
+            const int64_t g = a_blk + q;
+            v[u] = q < XL && g < n ? xf[g] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < PRE; ++u) {
+            const int q = q0 + u * (int)blockDim.x + (int)threadIdx.x;
+            if (q >= XL) break;
+            const float y = a_blk + q < n ? (float)((double)v[u] - ref) : 0.0f;
+#pragma unroll
+            for (int sh = 0; sh < 4; ++sh)
+                if (q >= sh) xs4[sh * XL + q - sh] = y;
+        }
     }
     return ref;
 }
@@ -463,7 +498,14 @@ __device__ inline void quantize_store(const floatx16 (&acc)[MB][NB], const float
                                       int64_t a0, int col, int kk, int64_t ns, int NF, int K,
                                       float inv_r, uint32_t* __restrict__ Hf)
 {
+    // sym_of for four positions at once, in few VALU operations: the clamp
+    // is one median, floor and conversion one instruction, and since
+    // (h + 128) mod 256 is the low byte of h with its top bit flipped, the
+    // four low bytes are gathered by two byte permutes and flipped by one
+    // XOR; positions past K / 2 are masked to zero.
     const int half = K / 2;
+    const uint32_t keep = half >= 4 ? 0xFFFFFFFFu : ~(0xFFFFFFFFu >> (8 * half));
+    const uint32_t flip = 0x80808080u & keep;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -471,15 +513,22 @@ __device__ inline void quantize_store(const floatx16 (&acc)[MB][NB], const float
             const int c0 = mb * 32 + 8 * g + 4 * kk;
             const int F = c0 / 4;
             if (F >= NF) continue;
+            const float4 u4 = *reinterpret_cast<const float4*>(Uf0 + c0);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int64_t a = a0 + nb * 32 + col;
                 if (a >= ns) continue;
-                uint32_t word = 0;
+                int h[4];
+                const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
 #pragma unroll
-                for (int p = 0; p < 4; ++p)
-                    if (p < half) word |= sym_of(fmaf(acc[mb][nb][4 * g + p], inv_r, Uf0[c0 + p])) << (24 - 8 * p);
-                Hf[(int64_t)F * ns + a] = word;
+                for (int p = 0; p < 4; ++p) {
+                    const float v = __builtin_amdgcn_fmed3f(fmaf(acc[mb][nb][4 * g + p], inv_r, uu[p]), -1.0e9f, 1.0e9f);
+                    h[p] = (int)floorf(v);
+                }
+                // byte 3 <- h0, byte 2 <- h1, byte 1 <- h2, byte 0 <- h3
+                const uint32_t lo = __builtin_amdgcn_perm((uint32_t)h[2], (uint32_t)h[3], 0x0c0c0400u);
+                const uint32_t hi = __builtin_amdgcn_perm((uint32_t)h[0], (uint32_t)h[1], 0x04000c0cu);
+                Hf[(int64_t)F * ns + a] = ((lo | hi) & keep) ^ flip;
             }
         }
 }
@@ -548,35 +597,46 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_proj_bf16(const T* __
     stash(0);
     __syncthreads();
     constexpr int NST = kRT / 16;   // MFMA steps of 16 t per chunk
+    // Hankel reuse: window block nb at step s reads the run of block 0 at
+    // step s + 2 nb (its windows start 32 nb later), so one fragment
+    // F(s) = 8 values at xb[0] + 16 s serves block 0 at step s and block 1 at
+    // step s - 2. Fragments live in a ring of four (slot s mod 4); F(s + 3)
+    // is read during step s.
+    static_assert(NB == 2, "the fragment ring assumes two window blocks");
+    const int S = nchunks * NST;   // steps in all; block 1 reads up to F(S + 1)
+    float4 fr[4][2];
+    auto load_frag = [&](int sg, int slot) {
+        const float4* xp = reinterpret_cast<const float4*>(__builtin_assume_aligned(xb[0] + 16 * sg, 16));
+        fr[slot][0] = xp[0];
+        fr[slot][1] = xp[1];
+    };
+    load_frag(0, 0);
+    load_frag(1, 1);
+    load_frag(2, 2);
     for (int c = 0; c < nchunks; ++c) {
         const int cur = c & 1;
         if (c + 1 < nchunks) fetch((c + 1) * kRT);
         const __bf16* rb = rs + (size_t)cur * MB * 32 * kRS + (size_t)col * kRS + 8 * kk;
-        // operands of step st + 1 are read from LDS while step st runs
+        // projection rows of step st + 1 are read from LDS while step st runs
         bf16x8 av[2][MB];
-        float4 xv[2][NB][2];
-        auto load_step = [&](int st, int slot) {
+        auto load_rows = [&](int st, int slot) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
                 av[slot][mb] = *reinterpret_cast<const bf16x8*>(rb + (size_t)mb * 32 * kRS + st * 16);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const float4* xp = reinterpret_cast<const float4*>(
-                    __builtin_assume_aligned(xb[nb] + c * kRT + st * 16, 16));
-                xv[slot][nb][0] = xp[0];
-                xv[slot][nb][1] = xp[1];
-            }
         };
-        load_step(0, 0);
+        load_rows(0, 0);
 #pragma unroll
         for (int st = 0; st < NST; ++st) {
             const int sl = st & 1;
-            if (st + 1 < NST) load_step(st + 1, sl ^ 1);
+            const int sg = c * NST + st;
+            if (st + 1 < NST) load_rows(st + 1, sl ^ 1);
+            if (sg + 3 <= S + 1) load_frag(sg + 3, (st + 3) & 3);
             bf16x8 bv[NB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 // x_hat in FP32, rounded to bf16 two at a time
-                const float4 lo = xv[sl][nb][0], hi = xv[sl][nb][1];
+                const int slot = (st + 2 * nb) & 3;
+                const float4 lo = fr[slot][0], hi = fr[slot][1];
                 const float s0 = sc[nb], o0 = off[nb];
                 const bf16x2 p0 = __builtin_convertvector((floatx2v){fmaf(lo.x, s0, o0), fmaf(lo.y, s0, o0)}, bf16x2);
                 const bf16x2 p1 = __builtin_convertvector((floatx2v){fmaf(lo.z, s0, o0), fmaf(lo.w, s0, o0)}, bf16x2);
