@@ -172,9 +172,11 @@ hipError_t launch_scatter(const StepGeom& g, const uint32_t* H, const SortBufs& 
 // Fingerprint rows of the batch, fps[jb][a][fp_words(D)]: an 8-bit digest
 // of every dimension's length-i_lo prefix (the prefix itself when i_lo = 1);
 // and second-stage rows fq[jb][a][fq_words(D)] with a 16-bit digest per
-// dimension (the prefix itself when i_lo <= 2); both bit-sliced.
+// dimension (the prefix itself when i_lo <= 2); both bit-sliced. The same
+// pass over the index words writes the histogram of the sort's pass 0 into
+// b.hist (the batch's segments), so that pass starts from the scan.
 hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, uint32_t* fq,
-                          hipStream_t s);
+                          const SortBufs& b, hipStream_t s);
 // Runs of >= 2 equal length-i_lo prefixes and the pairs of every run (one
 // launch); `part` holds enum_partials(g) per-work-group triples of counts
 // (pairs in runs, run members, screened pairs). kt = min(i_hi + 1, K).

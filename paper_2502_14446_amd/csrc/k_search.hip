@@ -508,92 +508,114 @@ __host__ __device__ inline void chunk_words(const uint64_t (&t8)[4], const uint6
 
 template <int DP>
 __global__ __launch_bounds__(256) void k_fptable(const uint32_t* __restrict__ H, StepGeom g, int reps,
-                                                 uint32_t* __restrict__ fps, uint32_t* __restrict__ fq)
+                                                 int64_t tiles, uint32_t* __restrict__ fps,
+                                                 uint32_t* __restrict__ fq, uint32_t* __restrict__ hist)
 {
-    // work-group m = (tile of 256 windows) * reps + repetition, with each XCD
-    // taking one contiguous range of m: the batch's repetitions of a tile run
-    // back to back on one XCD, and the left half-function words they share
-    // (one left function serves g.m consecutive repetitions) come from its L2
+    // work-group m = (sort tile) * reps + repetition, with each XCD taking
+    // one contiguous range of m: the batch's repetitions of a tile run back
+    // to back on one XCD, and the left half-function words they share (one
+    // left function serves g.m consecutive repetitions) come from its L2.
+    // A work-group walks its sort tile 256 windows at a time, one window per
+    // thread, and also counts the tile's sort digits of pass 0 for every
+    // segment dimension (f < Ds): the histogram the radix sort's first pass
+    // would otherwise read the index words again for.
+    __shared__ uint32_t cnt[32][256];
     const int64_t nb = (int64_t)gridDim.x;
     const int64_t q = nb / 8, rr = nb % 8, x = blockIdx.x % 8;
     const int64_t m = x * q + (x < rr ? x : rr) + blockIdx.x / 8;
     const int jb = (int)(m % reps);
-    const int64_t a = (m / reps) * 256 + threadIdx.x;
-    if (a >= g.ns) return;
-    const int64_t gid = (int64_t)jb * g.ns + a;
+    const int64_t tile = m / reps;
+    const int64_t t0 = tile * kSortTile;
     const int j = g.j0 + jb, l = j / g.m, r = j - l * g.m;
     const int nw = fp_words(g.D), nq = fq_words(g.D);
-    uint32_t* fw = fps + gid * nw;
-    uint32_t* qw = fq + gid * nq;
+    constexpr int CD = DP < 32 ? DP : 32;   // dimensions per chunk
+    const int64_t lstep = (int64_t)g.NF * g.ns;
     // chunks of 32 dimensions (one chunk unless D > 32), each as four groups
     // of 8 whose digests are gathered byte by byte and then transposed. Every
     // index word of a chunk is loaded before the first is used (a dimension
     // past D reloads the last one and is masked out), so a thread waits out
     // one memory latency per chunk, not one per dimension.
-    constexpr int CD = DP < 32 ? DP : 32;   // dimensions per chunk
-    const int64_t lstep = (int64_t)g.NF * g.ns;
-    const uint32_t* Lb = H + (int64_t)l * g.ns + a;
-    const uint32_t* Rb = H + (int64_t)(g.NL + r) * g.ns + a;
     for (int c0 = 0; c0 < g.D; c0 += 32) {
-        uint32_t Lw[CD], Rw[CD];
+        const int nh = g.Ds - c0 < CD ? (g.Ds - c0 > 0 ? g.Ds - c0 : 0) : CD;   // segment dimensions here
+        for (int v = threadIdx.x; v < nh * 256; v += 256) (&cnt[0][0])[v] = 0;
+        __syncthreads();
+        for (int64_t a = t0 + threadIdx.x; a < t0 + kSortTile && a < g.ns; a += 256) {
+            const int64_t gid = (int64_t)jb * g.ns + a;
+            const uint32_t* Lb = H + (int64_t)l * g.ns + a;
+            const uint32_t* Rb = H + (int64_t)(g.NL + r) * g.ns + a;
+            uint32_t Lw[CD], Rw[CD];
 #pragma unroll
-        for (int u = 0; u < CD; ++u) {
-            const int f = c0 + u < g.D ? c0 + u : g.D - 1;
-            Lw[u] = Lb[f * lstep];
-            Rw[u] = __builtin_nontemporal_load(Rb + f * lstep);
-        }
-        uint64_t t8[4], tl[4], th[4];
-#pragma unroll
-        for (int gq = 0; gq < 4; ++gq) {
-            uint64_t b8 = 0, bl = 0, bh = 0;
-            if (8 * gq < CD) {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int uu = 8 * gq + u;
-                    const uint64_t pre = make_key<uint64_t>(Lw[uu], Rw[uu], g.i_lo);
-                    const uint32_t d16 = prefix_digest16(pre, g.i_lo);
-                    const uint64_t keep = c0 + uu < g.D ? 0xFFull : 0ull;
-                    b8 |= ((uint64_t)prefix_digest8(pre, g.i_lo) & keep) << (8 * u);
-                    bl |= ((uint64_t)(d16 & 0xFFu) & keep) << (8 * u);
-                    bh |= ((uint64_t)(d16 >> 8) & keep) << (8 * u);
-                }
+            for (int u = 0; u < CD; ++u) {
+                const int f = c0 + u < g.D ? c0 + u : g.D - 1;
+                Lw[u] = Lb[f * lstep];
+                Rw[u] = __builtin_nontemporal_load(Rb + f * lstep);
             }
-            t8[gq] = transpose8(b8);
-            tl[gq] = transpose8(bl);
-            th[gq] = transpose8(bh);
-        }
-        // the chunk's words leave in whole 16-byte stores where rows allow
-        constexpr int W8 = DP / 4, WQ = DP / 2 < 4 ? 4 : DP / 2;
-        uint32_t o8[W8], oq[WQ];
-        chunk_words<DP>(t8, tl, th, o8, oq);
-        uint32_t* f8 = fw + (c0 / 32) * 8;
-        if constexpr (W8 == 1)
-            f8[0] = o8[0];
-        else if constexpr (W8 == 2)
-            *reinterpret_cast<uint2*>(f8) = make_uint2(o8[0], o8[1]);
-        else {
+            uint64_t t8[4], tl[4], th[4];
 #pragma unroll
-            for (int v = 0; v < W8 / 4; ++v)
-                reinterpret_cast<uint4*>(f8)[v] = make_uint4(o8[4 * v], o8[4 * v + 1], o8[4 * v + 2], o8[4 * v + 3]);
-        }
-        if (g.fq) {
-            uint4* q4 = reinterpret_cast<uint4*>(qw + (c0 / 32) * 16);
+            for (int gq = 0; gq < 4; ++gq) {
+                uint64_t b8 = 0, bl = 0, bh = 0;
+                if (8 * gq < CD) {
 #pragma unroll
-            for (int v = 0; v < WQ / 4; ++v) q4[v] = make_uint4(oq[4 * v], oq[4 * v + 1], oq[4 * v + 2], oq[4 * v + 3]);
+                    for (int u = 0; u < 8; ++u) {
+                        const int uu = 8 * gq + u;
+                        const uint64_t pre = make_key<uint64_t>(Lw[uu], Rw[uu], g.i_lo);
+                        const uint32_t d16 = prefix_digest16(pre, g.i_lo);
+                        const uint64_t keep = c0 + uu < g.D ? 0xFFull : 0ull;
+                        b8 |= ((uint64_t)prefix_digest8(pre, g.i_lo) & keep) << (8 * u);
+                        bl |= ((uint64_t)(d16 & 0xFFu) & keep) << (8 * u);
+                        bh |= ((uint64_t)(d16 >> 8) & keep) << (8 * u);
+                        // pass 0's digit: the low byte of the sort key
+                        if (uu < nh) {
+                            const uint32_t dg = g.hashed ? (uint32_t)((pre * 0x9E3779B97F4A7C15ull) >> 40) & 255u
+                                                         : (uint32_t)pre & 255u;
+                            atomicAdd(&cnt[uu][dg], 1u);
+                        }
+                    }
+                }
+                t8[gq] = transpose8(b8);
+                tl[gq] = transpose8(bl);
+                th[gq] = transpose8(bh);
+            }
+            // the chunk's words leave in whole 16-byte stores where rows allow
+            constexpr int W8 = DP / 4, WQ = DP / 2 < 4 ? 4 : DP / 2;
+            uint32_t o8[W8], oq[WQ];
+            chunk_words<DP>(t8, tl, th, o8, oq);
+            uint32_t* f8 = fps + gid * nw + (c0 / 32) * 8;
+            if constexpr (W8 == 1)
+                f8[0] = o8[0];
+            else if constexpr (W8 == 2)
+                *reinterpret_cast<uint2*>(f8) = make_uint2(o8[0], o8[1]);
+            else {
+#pragma unroll
+                for (int v = 0; v < W8 / 4; ++v)
+                    reinterpret_cast<uint4*>(f8)[v] = make_uint4(o8[4 * v], o8[4 * v + 1], o8[4 * v + 2], o8[4 * v + 3]);
+            }
+            if (g.fq) {
+                uint4* q4 = reinterpret_cast<uint4*>(fq + gid * nq + (c0 / 32) * 16);
+#pragma unroll
+                for (int v = 0; v < WQ / 4; ++v) q4[v] = make_uint4(oq[4 * v], oq[4 * v + 1], oq[4 * v + 2], oq[4 * v + 3]);
+            }
         }
+        __syncthreads();
+        // the tile's pass-0 counts of the chunk's segment dimensions: segment
+        // jb * Ds + f, layout [segment][tile][digit]
+        for (int u = 0; u < nh; ++u)
+            hist[(((int64_t)jb * g.Ds + c0 + u) * tiles + tile) * 256 + threadIdx.x] = cnt[u][threadIdx.x];
+        __syncthreads();
     }
 }
 
 hipError_t launch_fptable(const uint32_t* H, const StepGeom& g, int reps, uint32_t* fps, uint32_t* fq,
-                          hipStream_t s)
+                          const SortBufs& b, hipStream_t s)
 {
-    const int64_t blocks = (g.ns + 255) / 256 * reps;   // (tile, repetition) pairs
-    const dim3 grid((unsigned)blocks);
+    const int64_t tiles = (g.ns + kSortTile - 1) / kSortTile;
+    if (tiles != b.tiles) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(tiles * reps));   // (sort tile, repetition) pairs
     switch (plane_bits(g.D)) {
-    case 4: hipLaunchKernelGGL(k_fptable<4>, grid, dim3(256), 0, s, H, g, reps, fps, fq); break;
-    case 8: hipLaunchKernelGGL(k_fptable<8>, grid, dim3(256), 0, s, H, g, reps, fps, fq); break;
-    case 16: hipLaunchKernelGGL(k_fptable<16>, grid, dim3(256), 0, s, H, g, reps, fps, fq); break;
-    default: hipLaunchKernelGGL(k_fptable<32>, grid, dim3(256), 0, s, H, g, reps, fps, fq); break;
+    case 4: hipLaunchKernelGGL(k_fptable<4>, grid, dim3(256), 0, s, H, g, reps, tiles, fps, fq, b.hist); break;
+    case 8: hipLaunchKernelGGL(k_fptable<8>, grid, dim3(256), 0, s, H, g, reps, tiles, fps, fq, b.hist); break;
+    case 16: hipLaunchKernelGGL(k_fptable<16>, grid, dim3(256), 0, s, H, g, reps, tiles, fps, fq, b.hist); break;
+    default: hipLaunchKernelGGL(k_fptable<32>, grid, dim3(256), 0, s, H, g, reps, tiles, fps, fq, b.hist); break;
     }
     return hipGetLastError();
 }

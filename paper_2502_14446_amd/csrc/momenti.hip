@@ -1462,20 +1462,22 @@ restart:
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
             const double kb = sort_keys_32(g) ? 4.0 : 8.0;
+            const int kt = std::min(i_hi + 1, p->K);
+            const int nw = fp_words(p->D);
+            const int nq = fq_words(p->D);
+            // the fingerprint tables, with the histogram of the sort's pass 0
+            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + (g.fq ? nq : 0))), 0.0, [&] {
+                return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->sb, p->st);
+            }));
             for (int pass = 0; pass < sort_passes(g); ++pass) {
                 const double kin = pass == 0 ? 8.0 : kb;   // pass 0 reads two index words
-                HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
+                if (pass > 0)
+                    HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
                 HIP_OK(timed(p, KI_SCAN, 8.0 * g.nseg * 256.0 * p->sb.tiles, 0.0, [&] { return launch_scan(g, p->sb, p->st); }));
                 HIP_OK(timed(p, KI_SCATTER, elems * (kin + (pass == 0 ? 0.0 : 4.0) + kb + 4.0), 0.0,
                              [&] { return launch_scatter(g, p->H, p->sb, pass, buf, p->st); }));
                 buf ^= 1;
             }
-            const int kt = std::min(i_hi + 1, p->K);
-            const int nw = fp_words(p->D);
-            const int nq = fq_words(p->D);
-            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + (g.fq ? nq : 0))), 0.0, [&] {
-                return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->st);
-            }));
             // Enumeration, verification and (single-round groups) replay, in
             // g.nparts parts when one repetition's candidates do not fit in
             // memory at once: merging a step's records into the pool part by
@@ -2023,19 +2025,21 @@ restart:
             int buf = 0;
             const double elems = (double)g.nseg * p->ns;
             const double kb = sort_keys_32(g) ? 4.0 : 8.0;
+            const int kt = std::min(i + 1, p->K);
+            const int nw = fp_words(p->D), nq = fq_words(p->D);
+            // the fingerprint tables, with the histogram of the sort's pass 0
+            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + (g.fq ? nq : 0))), 0.0, [&] {
+                return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->sb, p->st);
+            }));
             for (int pass = 0; pass < sort_passes(g); ++pass) {
                 const double kin = pass == 0 ? 8.0 : kb;
-                HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
+                if (pass > 0)
+                    HIP_OK(timed(p, KI_HIST, elems * kin, 0.0, [&] { return launch_hist(g, p->H, p->sb, pass, buf, p->st); }));
                 HIP_OK(timed(p, KI_SCAN, 8.0 * g.nseg * 256.0 * p->sb.tiles, 0.0, [&] { return launch_scan(g, p->sb, p->st); }));
                 HIP_OK(timed(p, KI_SCATTER, elems * (kin + (pass == 0 ? 0.0 : 4.0) + kb + 4.0), 0.0,
                              [&] { return launch_scatter(g, p->H, p->sb, pass, buf, p->st); }));
                 buf ^= 1;
             }
-            const int kt = std::min(i + 1, p->K);
-            const int nw = fp_words(p->D), nq = fq_words(p->D);
-            HIP_OK(timed(p, KI_FPTABLE, (double)Bc * p->ns * (p->D * 8.0 + 4.0 * (nw + (g.fq ? nq : 0))), 0.0, [&] {
-                return launch_fptable(p->H, g, Bc, p->fps, p->fq, p->st);
-            }));
             bool redo = false;
             for (g.part = 0; g.part < g.nparts && !redo; ++g.part) {
                 HIP_OK(launch_zero(p->status, 64, p->st));
