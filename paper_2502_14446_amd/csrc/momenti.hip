@@ -306,6 +306,14 @@ struct momenti_plan {
     int snap_steps = 0, snap_k = 0;
     unsigned char* host_status = nullptr;
     Snap* host_snaps = nullptr;
+    // pinned host blocks the plan keeps for its next search (pinning memory
+    // is slow): freed by momenti_destroy
+    struct HostBlock {
+        void* ptr;
+        size_t cap;
+        bool used;
+    };
+    std::vector<HostBlock> host_blocks;
 
     uint64_t bytes = 0, peak = 0;
     Profiler prof;
@@ -384,20 +392,39 @@ static int dalloc_t(momenti_plan* p, T** ptr, size_t bytes)
 }
 
 // Host staging buffers: pinned, except under momenti_search_noalloc (plain
-// memory: no allocating HIP call there).
+// memory: no allocating HIP call there). Pinned blocks stay with the plan
+// after a search and serve the next one when large enough.
 static bool host_alloc(momenti_plan* p, void** ptr, size_t bytes)
 {
     if (p->arena) {
         *ptr = std::malloc(bytes);
         return *ptr != nullptr;
     }
-    return hipHostMalloc(ptr, bytes, 0) == hipSuccess;
+    for (auto& b : p->host_blocks)
+        if (!b.used && b.cap >= bytes) {
+            b.used = true;
+            *ptr = b.ptr;
+            return true;
+        }
+    const size_t cap = (bytes + 4095) / 4096 * 4096;
+    if (hipHostMalloc(ptr, cap, 0) != hipSuccess) return false;
+    p->host_blocks.push_back({*ptr, cap, true});
+    return true;
 }
 
 static void host_free(momenti_plan* p, void* ptr)
 {
     if (!ptr) return;
-    if (p->arena) std::free(ptr); else (void)hipHostFree(ptr);
+    if (p->arena) {
+        std::free(ptr);
+        return;
+    }
+    for (auto& b : p->host_blocks)
+        if (b.ptr == ptr) {
+            b.used = false;
+            return;
+        }
+    (void)hipHostFree(ptr);
 }
 
 static void dfree(momenti_plan* p, void* ptr, size_t bytes)
@@ -585,6 +612,8 @@ void momenti_destroy(momenti_plan* p)
     for (hipEvent_t e : p->prof.spare) (void)hipEventDestroy(e);
     p->prof.spare.clear();
     release_search(p);
+    for (auto& b : p->host_blocks) (void)hipHostFree(b.ptr);
+    p->host_blocks.clear();
     if (p->own_series) dfree(p, p->series, series_bytes(p));
     dfree(p, p->mu, (size_t)p->D * p->ns * 8);
     dfree(p, p->isig, (size_t)p->D * p->ns * 8);
