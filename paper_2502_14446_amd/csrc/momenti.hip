@@ -2402,12 +2402,27 @@ extern "C" int momenti_topk_batch(const momenti_job* jobs, int32_t count, uint64
             const momenti_job& jb = jobs[q];
             momenti_report rr{};
             n_out[q] = 0;
-            momenti_plan* p = nullptr;
-            int rc = prepare_impl(&p, jb.n, jb.D, jb.w, jb.dtype, mem_limit, &o, &cache);
-            if (rc == MOMENTI_OK) {
-                rc = momenti_hash(p, jb.series);
-                if (rc == MOMENTI_OK) rc = momenti_search(p, jb.d, jb.k, jb.delta, out + off[q], &n_out[q], &rr);
-                momenti_destroy(p);
+            auto run = [&]() {
+                momenti_plan* p = nullptr;
+                int r = prepare_impl(&p, jb.n, jb.D, jb.w, jb.dtype, mem_limit, &o, &cache);
+                if (r == MOMENTI_OK) {
+                    r = momenti_hash(p, jb.series);
+                    if (r == MOMENTI_OK) r = momenti_search(p, jb.d, jb.k, jb.delta, out + off[q], &n_out[q], &rr);
+                    momenti_destroy(p);
+                }
+                return r;
+            };
+            int rc = run();
+            if (rc == MOMENTI_E_NOMEM) {
+                // blocks reused from earlier series can be larger than asked
+                // for, and a series close to its limit then runs out: run it
+                // again on exact, fresh blocks, as a series on its own would
+                cache.trim();
+                cache.exact = true;
+                rr = momenti_report{};
+                n_out[q] = 0;
+                rc = run();
+                cache.exact = false;
             }
             status[q] = rc;
             if (reps) reps[q] = rr;
