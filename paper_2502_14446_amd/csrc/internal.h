@@ -163,7 +163,8 @@ constexpr int kSortTile = 4096;
 
 // Stable LSD sort of every segment of the batch by its length-i hash prefix,
 // one byte per pass (pass 0 reads the keys straight from the index); each
-// pass is histogram + scan + scatter from buffer `cur` to buffer `cur ^ 1`.
+// pass is histogram + scan + scatter from buffer `cur` to buffer `cur ^ 1`,
+// except that launch_fptable writes pass 0's histogram.
 hipError_t launch_hist(const StepGeom& g, const uint32_t* H, const SortBufs& b, int pass, int cur,
                        hipStream_t s);
 hipError_t launch_scan(const StepGeom& g, const SortBufs& b, hipStream_t s);

@@ -6,9 +6,11 @@
 //  * sort_prefixes  stable LSD radix sort of every segment by the length-i
 //                   hash prefix of repetition j (left half-function j div m,
 //                   right half-function j mod m; section 6.1), one byte per
-//                   pass. Pass 0 builds the keys straight from the index.
-//                   Tiles of 4096 elements are ranked in LDS with wave ballots
-//                   and written out digit by digit (coalesced).
+//                   pass. Pass 0 builds the keys straight from the index; its
+//                   histogram comes from the fingerprint-table kernel, which
+//                   reads the same index words. Tiles of 4096 elements are
+//                   ranked in LDS with wave ballots and written out digit by
+//                   digit (coalesced).
 //  * k_enum         windows with equal prefixes are adjacent and, the sort
 //                   being stable, in increasing window order; each element
 //                   walks the rest of its run. For every non-trivial pair it
