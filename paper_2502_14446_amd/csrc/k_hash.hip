@@ -143,18 +143,18 @@ hipError_t launch_stats(const void* x, int dtype, int64_t n, int64_t ns, int D, 
 // ---------------------------------------------------------------------------
 constexpr int kRsLds = 48 * 1024;   // LDS for the staged windows of one wavefront
 
-template <typename T>
+template <typename T, bool staged>
 __global__ __launch_bounds__(64) void k_rsample(const T* __restrict__ x, int64_t n, int D, int w,
                                                 const int64_t* __restrict__ win, int S,
                                                 const double* __restrict__ vec, int nvec, int VT,
-                                                int G, bool staged, double* __restrict__ dots)
+                                                int G, double* __restrict__ dots)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* xs = reinterpret_cast<T*>(smem_raw);
     const int64_t total = (int64_t)D * S;
     const int64_t id0 = (int64_t)blockIdx.x * G;
     const int lane = threadIdx.x, slot = lane / VT, vi = lane - slot * VT;
-    if (staged) {
+    if constexpr (staged) {
         for (int g = 0; g < G; ++g) {
             const int64_t id = id0 + g;
             if (id >= total) break;
@@ -165,7 +165,11 @@ __global__ __launch_bounds__(64) void k_rsample(const T* __restrict__ x, int64_t
     }
     const int64_t id = id0 + slot;
     if (slot >= G || id >= total) return;
-    const T* xa = staged ? xs + (size_t)slot * w : x + (id / S) * n + win[id];
+    // (the staged window is read through the LDS array itself, so that its
+    // loads are LDS loads rather than generic ones)
+    const T* xa;
+    if constexpr (staged) xa = xs + (size_t)slot * w;
+    else xa = x + (id / S) * n + win[id];
     double mu, m2, sigma;
     direct_stats(xa, w, mu, m2, sigma);
     const bool flat = sigma <= kFlatRel * fabs(mu);
@@ -192,12 +196,21 @@ hipError_t launch_rsample(const void* x, int dtype, int64_t n, int D, int w, con
     const bool staged = (size_t)G * w * elem <= (size_t)kRsLds;
     const size_t lds = staged ? (size_t)G * w * elem : 0;
     dim3 grid((unsigned)((total + G - 1) / G));
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_rsample<double>, grid, dim3(64), lds, s, (const double*)x, n, D, w,
-                           win, S, vec, nvec, VT, G, staged, dots);
-    else
-        hipLaunchKernelGGL(k_rsample<float>, grid, dim3(64), lds, s, (const float*)x, n, D, w,
-                           win, S, vec, nvec, VT, G, staged, dots);
+    if (dtype == 0) {
+        if (staged)
+            hipLaunchKernelGGL((k_rsample<double, true>), grid, dim3(64), lds, s, (const double*)x, n, D, w,
+                               win, S, vec, nvec, VT, G, dots);
+        else
+            hipLaunchKernelGGL((k_rsample<double, false>), grid, dim3(64), lds, s, (const double*)x, n, D, w,
+                               win, S, vec, nvec, VT, G, dots);
+    } else {
+        if (staged)
+            hipLaunchKernelGGL((k_rsample<float, true>), grid, dim3(64), lds, s, (const float*)x, n, D, w,
+                               win, S, vec, nvec, VT, G, dots);
+        else
+            hipLaunchKernelGGL((k_rsample<float, false>), grid, dim3(64), lds, s, (const float*)x, n, D, w,
+                               win, S, vec, nvec, VT, G, dots);
+    }
     return hipGetLastError();
 }
 
