@@ -230,6 +230,34 @@ __device__ inline uint32_t sym_of(double u)
     return (uint32_t)(((int)h + 128) & 255);
 }
 
+// The per-window statistics of a lane's NB windows (a0 + WS nb), loaded at
+// the kernel's start with clamped indices (no branch, so the loads overlap
+// the tile's); windows past the end get 0.
+template <int NB, int WS>
+__device__ inline void window_stats(const double* __restrict__ mu, const double* __restrict__ isig,
+                                    int64_t a0, int64_t ns, double (&m)[NB], double (&sg)[NB])
+{
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int64_t a = a0 + nb * WS;
+        const int64_t ac = a < ns ? a : ns - 1;
+        m[nb] = mu[ac];
+        sg[nb] = isig[ac];
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+        if (a0 + nb * WS >= ns) m[nb] = sg[nb] = 0.0;
+}
+
+// The offsets U_f (Cpad values) copied into LDS by the first Cpad threads;
+// the epilogue reads them there, so no global load waits behind its stores
+// (the vector memory counter counts both).
+template <typename U_T>
+__device__ inline void stage_offsets(const U_T* __restrict__ Uf, int Cpad, U_T* us)
+{
+    if ((int)threadIdx.x < Cpad) us[threadIdx.x] = Uf[threadIdx.x];
+}
+
 // ---------------------------------------------------------------------------
 // FP64 projection: v_mfma_f64_16x16x4f64. A (16 x 4): lane l holds
 // A[l % 16][l / 16]; B (4 x 16) = x_hat^T: lane l holds B[l / 16][l % 16];
@@ -254,6 +282,11 @@ __global__ __launch_bounds__(256) void k_proj_f64(const T* __restrict__ x, int64
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
     const T* xf = x + (int64_t)f * n;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, kq = lane >> 4;
+    const int wbase = wave * 16 * NB;
+    double m_[NB], s_[NB];
+    window_stats<NB, 16>(mu + (int64_t)f * ns, isig + (int64_t)f * ns, a_blk + wbase + col, ns, m_, s_);
     // the tile's loads in batches of eight per thread before the first use
     for (int q0 = 0; q0 < WB + wpad; q0 += 8 * 256) {
         T v[8];
@@ -268,18 +301,10 @@ __global__ __launch_bounds__(256) void k_proj_f64(const T* __restrict__ x, int64
             if (q < WB + wpad) xs[q] = v[u];
         }
     }
+    double* us = reinterpret_cast<double*>(smem_raw + ((size_t)(WB + wpad) * sizeof(T) + 15) / 16 * 16);   // [Cpad]
+    stage_offsets(U + (int64_t)f * Cpad, Cpad, us);
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = lane & 15, kq = lane >> 4;
     const int acol = 4 * (col & 3) + (col >> 2);   // hash column carried by A row `col`
-    const int wbase = wave * 16 * NB;
-    double m_[NB], s_[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        int64_t a = a_blk + wbase + nb * 16 + col;
-        m_[nb] = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
-        s_[nb] = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
-    }
     doublex4 acc[MB16][NB];
 #pragma unroll
     for (int mb = 0; mb < MB16; ++mb)
@@ -306,7 +331,7 @@ __global__ __launch_bounds__(256) void k_proj_f64(const T* __restrict__ x, int64
         const int c0 = mb * 16 + 4 * kq;
         const int F = c0 / 4;
         if (F >= NF) continue;
-        const double* Uf = U + (int64_t)f * Cpad + c0;
+        const double* Uf = us + c0;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int64_t a = a_blk + wbase + nb * 16 + col;
@@ -341,6 +366,11 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
     const T* xf = x + (int64_t)f * n;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 31, kk = lane >> 5;
+    const int wbase = wave * 32 * NB;
+    double m_[NB], s_[NB];
+    window_stats<NB, 32>(mu + (int64_t)f * ns, isig + (int64_t)f * ns, a_blk + wbase + col, ns, m_, s_);
     // the tile's loads in batches of eight per thread before the first use
     for (int q0 = 0; q0 < WB + wpad; q0 += 8 * 256) {
         T v[8];
@@ -356,16 +386,6 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
         }
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = lane & 31, kk = lane >> 5;
-    const int wbase = wave * 32 * NB;
-    double m_[NB], s_[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        int64_t a = a_blk + wbase + nb * 32 + col;
-        m_[nb] = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
-        s_[nb] = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
-    }
     floatx16 acc[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -395,6 +415,8 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
             if (id < PIECES) *reinterpret_cast<floatx4*>(rs + ((size_t)buf * kRT32 + tr) * RW + 4 * seg) = pre[it];
         }
     };
+    float* us = rs + (size_t)2 * kRT32 * RW;   // [Cpad]
+    stage_offsets(U + (int64_t)f * Cpad, Cpad, us);
     const int nchunks = wpad / kRT32;
     fetch(0);
     stash(0);
@@ -429,7 +451,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
             const int c0 = mb * 32 + 8 * g + 4 * kk;
             const int F = c0 / 4;
             if (F >= NF) continue;
-            const float* Uf = U + (int64_t)f * Cpad + c0;
+            const float* Uf = us + c0;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int64_t a = a_blk + wbase + nb * 32 + col;
@@ -462,12 +484,13 @@ typedef int intx4 __attribute__((ext_vector_type(4)));
 
 // LDS staging of the low-precision projection rows: chunks of kRT (bf16) or
 // kRT8 (fp8) steps of t, rows padded to kRS / kRS8 elements (16 bytes of
-// padding against bank conflicts; every row start stays 16-byte aligned).
+// padding against bank conflicts; every row start stays 16-byte aligned),
+// followed by the Cpad offsets U_f.
 constexpr int kRT = 64, kRS = kRT + 8;
 constexpr int kRT8 = 64, kRS8 = kRT8 + 16;
 __host__ __device__ inline size_t lowp_stage_bytes(int proj, int Cpad)
 {
-    return proj == 2 ? (size_t)2 * Cpad * kRS * 2 : (size_t)2 * Cpad * kRS8;
+    return (proj == 2 ? (size_t)2 * Cpad * kRS * 2 : (size_t)2 * Cpad * kRS8) + (size_t)Cpad * sizeof(float);
 }
 
 // The series tile four times, copy s shifted left by s elements
@@ -507,7 +530,7 @@ __device__ inline double load_tile_shifted(const T* __restrict__ xf, int64_t n, 
 }
 
 template <int MB, int NB>
-__device__ inline void quantize_store(const floatx16 (&acc)[MB][NB], const float* __restrict__ Uf0,
+__device__ inline void quantize_store(const floatx16 (&acc)[MB][NB], const float* Uf0,
                                       int64_t a0, int col, int kk, int64_t ns, int NF, int K,
                                       float inv_r, uint32_t* __restrict__ Hf)
 {
@@ -560,19 +583,18 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_proj_bf16(const T* __
     const int XL = shifted_stride(WB, wpad);
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
-    const double ref = load_tile_shifted<T>(x + (int64_t)f * n, n, a_blk, XL, xs4);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 31, kk = lane >> 5;
     const int wbase = wave * 32 * NB;
+    double m_[NB], s_[NB];
+    window_stats<NB, 32>(mu + (int64_t)f * ns, isig + (int64_t)f * ns, a_blk + wbase + col, ns, m_, s_);
+    const double ref = load_tile_shifted<T>(x + (int64_t)f * n, n, a_blk, XL, xs4);
     float sc[NB], off[NB];
     const float* xb[NB];   // this lane's Hankel run: copy col mod 4, aligned
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-        const int64_t a = a_blk + wbase + nb * 32 + col;
-        const double m = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
-        const double sg = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
-        sc[nb] = (float)sg;
-        off[nb] = (float)(-(m - ref) * sg);
+        sc[nb] = (float)s_[nb];
+        off[nb] = (float)(-(m_[nb] - ref) * s_[nb]);
         xb[nb] = xs4 + (col & 3) * XL + wbase + nb * 32 + (col & ~3) + 8 * kk;
     }
     floatx16 acc[MB][NB];
@@ -605,6 +627,8 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_proj_bf16(const T* __
             if (id < PIECES) *reinterpret_cast<bf16x8*>(rs + ((size_t)buf * MB * 32 + row) * kRS + 8 * seg) = pre[it];
         }
     };
+    float* us = reinterpret_cast<float*>(rs + (size_t)2 * MB * 32 * kRS);   // [MB * 32]
+    stage_offsets(U + (int64_t)f * Cpad, MB * 32, us);
     const int nchunks = wpad / kRT;
     fetch(0);
     stash(0);
@@ -667,8 +691,7 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_proj_bf16(const T* __
         if (c + 1 < nchunks) stash(cur ^ 1);
         __syncthreads();
     }
-    quantize_store<MB, NB>(acc, U + (int64_t)f * Cpad, a_blk + wbase, col, kk, ns, NF, K, inv_r,
-                           H + (int64_t)f * NF * ns);
+    quantize_store<MB, NB>(acc, us, a_blk + wbase, col, kk, ns, NF, K, inv_r, H + (int64_t)f * NF * ns);
 }
 
 template <typename T, int MB, int NB, int WAVES>
@@ -685,19 +708,18 @@ __global__ __launch_bounds__(64 * WAVES, 12 / WAVES) void k_proj_fp8(const T* __
     const int XL = shifted_stride(WB, wpad);
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
-    const double ref = load_tile_shifted<T>(x + (int64_t)f * n, n, a_blk, XL, xs4);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 31, kk = lane >> 5;
     const int wbase = wave * 32 * NB;
+    double m_[NB], s_[NB];
+    window_stats<NB, 32>(mu + (int64_t)f * ns, isig + (int64_t)f * ns, a_blk + wbase + col, ns, m_, s_);
+    const double ref = load_tile_shifted<T>(x + (int64_t)f * n, n, a_blk, XL, xs4);
     float sc[NB], off[NB];
     const float* xb[NB];   // this lane's Hankel run: copy col mod 4, aligned
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-        const int64_t a = a_blk + wbase + nb * 32 + col;
-        const double m = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
-        const double sg = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
-        sc[nb] = (float)sg;
-        off[nb] = (float)(-(m - ref) * sg);
+        sc[nb] = (float)s_[nb];
+        off[nb] = (float)(-(m_[nb] - ref) * s_[nb]);
         xb[nb] = xs4 + (col & 3) * XL + wbase + nb * 32 + (col & ~3) + 32 * kk;
     }
     floatx16 acc[MB][NB];
@@ -728,6 +750,8 @@ __global__ __launch_bounds__(64 * WAVES, 12 / WAVES) void k_proj_fp8(const T* __
             if (id < PIECES) *reinterpret_cast<intx4*>(rs + ((size_t)buf * MB * 32 + row) * kRS8 + 16 * seg) = pre[it];
         }
     };
+    float* us = reinterpret_cast<float*>(rs + (size_t)2 * MB * 32 * kRS8);   // [MB * 32]
+    stage_offsets(U + (int64_t)f * Cpad, MB * 32, us);
     const int nchunks = wpad / kRT8;
     fetch(0);
     stash(0);
@@ -767,8 +791,7 @@ __global__ __launch_bounds__(64 * WAVES, 12 / WAVES) void k_proj_fp8(const T* __
         if (c + 1 < nchunks) stash(cur ^ 1);
         __syncthreads();
     }
-    quantize_store<MB, NB>(acc, U + (int64_t)f * Cpad, a_blk + wbase, col, kk, ns, NF, K, inv_r,
-                           H + (int64_t)f * NF * ns);
+    quantize_store<MB, NB>(acc, us, a_blk + wbase, col, kk, ns, NF, K, inv_r, H + (int64_t)f * NF * ns);
 }
 
 template <typename T, int MB>
@@ -812,7 +835,7 @@ static hipError_t go_f64(const T* x, int64_t n, int64_t ns, int D, int w, int wp
 {
     constexpr int NB = 2, WB = 4 * 16 * NB;
     dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-    size_t lds = (size_t)(WB + wpad) * sizeof(T);
+    size_t lds = ((size_t)(WB + wpad) * sizeof(T) + 15) / 16 * 16 + (size_t)Cpad * sizeof(double);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_proj_f64<T, MB16, NB>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -828,7 +851,7 @@ static hipError_t go_f32(const T* x, int64_t n, int64_t ns, int D, int w, int wp
 {
     constexpr int NB = 2, WB = 4 * 32 * NB;
     dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-    size_t lds = f32_series_bytes<T, WB>(wpad) + (size_t)2 * kRT32 * (MB * 32 + 4) * sizeof(float);
+    size_t lds = f32_series_bytes<T, WB>(wpad) + (size_t)(2 * kRT32 * (MB * 32 + 4) + Cpad) * sizeof(float);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_proj_f32<T, MB, NB>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
