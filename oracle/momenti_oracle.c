@@ -917,6 +917,7 @@ int32_t orc_lsh_search(const double* x, int64_t n, int32_t D, int32_t w, int32_t
             }
             pcnt = 0;
             for (int32_t f = 0; f < D; ++f) {
+                if (dim_pairs[f].cnt == 0) continue;   /* no list yet (p may be NULL) */
                 memcpy(pairs + pcnt, dim_pairs[f].p, sizeof(pair_t) * (size_t)dim_pairs[f].cnt);
                 pcnt += dim_pairs[f].cnt;
             }
