@@ -366,11 +366,6 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
     const int f = blockIdx.y;
     const int64_t a_blk = (int64_t)blockIdx.x * WB;
     const T* xf = x + (int64_t)f * n;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = lane & 31, kk = lane >> 5;
-    const int wbase = wave * 32 * NB;
-    double m_[NB], s_[NB];
-    window_stats<NB, 32>(mu + (int64_t)f * ns, isig + (int64_t)f * ns, a_blk + wbase + col, ns, m_, s_);
     // the tile's loads in batches of eight per thread before the first use
     for (int q0 = 0; q0 < WB + wpad; q0 += 8 * 256) {
         T v[8];
@@ -386,6 +381,16 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
         }
     }
     __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 31, kk = lane >> 5;
+    const int wbase = wave * 32 * NB;
+    double m_[NB], s_[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        int64_t a = a_blk + wbase + nb * 32 + col;
+        m_[nb] = a < ns ? mu[(int64_t)f * ns + a] : 0.0;
+        s_[nb] = a < ns ? isig[(int64_t)f * ns + a] : 0.0;
+    }
     floatx16 acc[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -415,8 +420,6 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
             if (id < PIECES) *reinterpret_cast<floatx4*>(rs + ((size_t)buf * kRT32 + tr) * RW + 4 * seg) = pre[it];
         }
     };
-    float* us = rs + (size_t)2 * kRT32 * RW;   // [Cpad]
-    stage_offsets(U + (int64_t)f * Cpad, Cpad, us);
     const int nchunks = wpad / kRT32;
     fetch(0);
     stash(0);
@@ -451,7 +454,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_f32(const T* __restrict__ x, in
             const int c0 = mb * 32 + 8 * g + 4 * kk;
             const int F = c0 / 4;
             if (F >= NF) continue;
-            const float* Uf = us + c0;
+            const float* Uf = U + (int64_t)f * Cpad + c0;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int64_t a = a_blk + wbase + nb * 32 + col;
@@ -695,7 +698,7 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_proj_bf16(const T* __
 }
 
 template <typename T, int MB, int NB, int WAVES>
-__global__ __launch_bounds__(64 * WAVES, 12 / WAVES) void k_proj_fp8(const T* __restrict__ x, int64_t n, int64_t ns,
+__global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_proj_fp8(const T* __restrict__ x, int64_t n, int64_t ns,
                                                   int w, int wpad, const double* __restrict__ mu,
                                                   const double* __restrict__ isig,
                                                   const uint8_t* __restrict__ R,
@@ -799,12 +802,10 @@ static hipError_t go_lowp(int proj, const T* x, int64_t n, int64_t ns, int D, in
                           const double* mu, const double* isig, const void* R, const float* U,
                           int Cpad, int NF, int K, float inv_r, uint32_t* H, hipStream_t s)
 {
-    // windows per wave: 64 for bf16 (two 32-wide MFMA columns share each
-    // projection operand), 32 for fp8, whose Hankel operand costs four times
-    // the VALU work per MFMA (measured; either way two or more waves per SIMD)
-    // four waves of 64 (bf16) or 32 (fp8) windows per work-group, two (bf16)
-    // or three (fp8) work-groups per CU: eight-wave groups and a lower
-    // occupancy measured slower
+    // windows per wave: 64 (two 32-wide MFMA columns share each projection
+    // operand read from LDS); four waves per work-group and two work-groups
+    // per CU: eight-wave groups and a lower occupancy measured slower, and
+    // fp8 with 32 windows per wave and three work-groups per CU 4% slower
     constexpr int WAVES = 4;
     if (proj == 2) {
         constexpr int NB = 2, WB = WAVES * 32 * NB;
@@ -816,7 +817,7 @@ static hipError_t go_lowp(int proj, const T* x, int64_t n, int64_t ns, int D, in
         hipLaunchKernelGGL((k_proj_bf16<T, MB, NB, WAVES>), grid, dim3(64 * WAVES), lds, s, x, n, ns, w, wpad, mu,
                            isig, (const __bf16*)R, U, Cpad, NF, K, inv_r, H);
     } else {
-        constexpr int NB = 1, WB = WAVES * 32 * NB;
+        constexpr int NB = 2, WB = WAVES * 32 * NB;
         dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
         const size_t lds = (size_t)4 * shifted_stride(WB, wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
         if (lds > 65536)
@@ -851,7 +852,7 @@ static hipError_t go_f32(const T* x, int64_t n, int64_t ns, int D, int w, int wp
 {
     constexpr int NB = 2, WB = 4 * 32 * NB;
     dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-    size_t lds = f32_series_bytes<T, WB>(wpad) + (size_t)(2 * kRT32 * (MB * 32 + 4) + Cpad) * sizeof(float);
+    size_t lds = f32_series_bytes<T, WB>(wpad) + (size_t)2 * kRT32 * (MB * 32 + 4) * sizeof(float);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_proj_f32<T, MB, NB>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
