@@ -427,6 +427,12 @@ def main() -> int:
         r_cpu = oracle.estimate_r(s.x, p["w"], seed) * r_scale
         out["cpu_baseline"] = cpu_baseline(s, p, seed, r_cpu)
         out["cpu_baseline"]["gpu_same_unit"] = units / (lead["ms"] / 1000.0)
+        # the metric's own unit: the time the oracle would take for the whole
+        # workload at the rate it reached on the sample (an estimate, linear
+        # in the number of windows)
+        out["cpu_baseline"]["tts_s_scaled"] = {
+            "value": units / out["cpu_baseline"]["value"], "unit": "s",
+            "how": "the whole workload's subseq·dims divided by the sample's rate"}
     print(json.dumps(out), flush=True)
     return 0
 
