@@ -9,7 +9,10 @@ workloads take and small cases do not:
 * a pool of verified pairs too small for TOP (eviction, restart with a larger pool);
 * searches under a memory cap that splits a round group and enumerates one
   repetition in parts, and repeated searches on one plan within the cap;
-* the batch entry point against the oracle.
+* the batch entry point against the oracle;
+* the benchmark's workloads at full size: rw8_1m against its exact top-10,
+  rwsin32_4m (BF16 and FP32) against the oracle's distances, hash bands and
+  planted motifs.
 
 Tolerances as in test_gpu_parity.py: candidates, TOP after every step, the stop
 step and motif indices identical; distances within 1e-9 relative.
@@ -344,6 +347,62 @@ def test_bench_workload_answer_against_the_exact_golden(orc):
             W = sum(orc.prefix(words, prm["L"], f, J - 1, a, i) == orc.prefix(words, prm["L"], f, J - 1, b, i)
                     for f in range(s.D))
             assert W < p["d"], f"device index: ({a}, {b}) collides in {W} dimensions at ({i}, {J})"
+
+
+# --------------------------------------------------------------------------- the headline workload
+def test_headline_workload_bf16_against_fp32_and_the_oracle(orc):
+    # rwsin32_4m (D = 32, n = 4 194 304, w = 1000, d = 8, k = 10, random walks
+    # mixed with sinusoids, r x4): the benchmark's workload and launch
+    # configuration, BF16 projection against FP32. Its exact top-10 is out of
+    # reach here (about 2.8e14 pair-dimensions), so the test checks what holds
+    # at any size:
+    #  * r is the oracle's estimate (section 6.1) times the workload's factor;
+    #  * sampled symbols (runs of 16 windows in every dimension, with windows at
+    #    the series' ends): FP32 within its band of the oracle's FP64 hash,
+    #    BF16 within its band of the rounded-input emulation;
+    #  * both precisions stop at the same step with the same k motifs, whose
+    #    dist_d, dist_max and dimensions are the oracle's FP64 d-dimensional
+    #    distance of each pair (Eq. distdmax);
+    #  * every planted motif is among them.
+    s, p = synth.workload("rwsin32_4m")
+    seed = synth.LSH_SEED["rwsin32_4m"]
+    w, D = p["w"], s.D
+    ns = s.n - w + 1
+    x64 = s.x.astype(np.float64)
+    r_want = orc.estimate_r(x64, w, seed) * p["r_scale"]
+    rng = np.random.default_rng(0x4EAD)
+    starts = [[0, ns - 16] + [int(a) for a in rng.integers(0, ns - 16, 2)] for _ in range(D)]
+    answers = {}
+    for proj in ("bf16", "f32"):
+        plan, _ = _plan(s, p, proj, seed, r_scale=p["r_scale"])
+        prm = plan.params()
+        assert prm["r"] == r_want
+        R, U = orc.draw_projections(seed, D, w, 4 * prm["NF"])
+        for f in range(D):
+            for a0 in starts[f]:
+                xs = x64[f, a0: a0 + 16 + w - 1]
+                gsym = _unpack(plan.hash_words(f, a0, 16)[None], 8)[0]
+                if proj == "f32":
+                    by, pre, sab = orc.hash_dim(xs, w, R[f], U[f], prm["r"])
+                    band = _band("f32", w, pre, sab, prm["r"])
+                else:
+                    by, pre, sab, amb = orc.hash_dim_lowp(xs, w, R[f], U[f], prm["r"], proj)
+                    band = _lowp_band(w, pre, sab, amb, prm["r"], proj)
+                bad_out, bad_in, _, _ = _check_symbols(gsym, by, pre, band, 8)
+                assert bad_out == 0 and bad_in == 0, (proj, f, a0)
+        got, rep, rc = plan.search(p["d"], p["k"], p["delta"])
+        plan.close()
+        assert rc == mm.OK and len(got) == p["k"], (proj, rc, len(got))
+        answers[proj] = ([(m["a"], m["b"]) for m in got], (rep["i_stop"], rep["j_stop"]))
+        for m in got:
+            dd, dm, dims, _ = orc.distd(x64, w, m["a"], m["b"], p["d"])
+            assert m["dist_d"] == pytest.approx(dd, rel=1e-9) and m["dist_max"] == pytest.approx(dm, rel=1e-9)
+            assert tuple(m["dims"]) == dims
+        assert [m["dist_d"] for m in got] == sorted(m["dist_d"] for m in got)
+        planted = {(q.p1, q.p2) for q in s.motifs}
+        assert planted <= set(answers[proj][0]), (proj, planted - set(answers[proj][0]))
+    assert answers["bf16"] == answers["f32"]
+    print(f"rwsin32_4m: BF16 and FP32 answer alike, stop {answers['bf16'][1]}, {len(s.motifs)} planted found")
 
 
 # --------------------------------------------------------------------------- exact answer on the device
