@@ -181,7 +181,10 @@ typedef struct {
 void momenti_default_opts(momenti_opts* o);
 
 /* Plan a search over series of length n (>= w + 1) with D (1..128) dimensions
- * and window w (4..8192). mem_limit bounds the device bytes the plan may hold
+ * and window w (4..8192; with a BF16 projection at most 7616 for 128 hash
+ * columns, since its work-group keeps four shifted copies of its series tile
+ * and two chunks of projection rows in one CU's 160 KiB of LDS: E_ARG names
+ * the limit). mem_limit bounds the device bytes the plan may hold
  * (series copy, statistics, index, traversal buffers); the number of
  * repetitions is the largest L' <= opts.L whose index fits (index size
  * O(K L D n), Theorem "space"):

@@ -91,6 +91,11 @@ hipError_t launch_rsample(const void* x, int dtype, int64_t n, int D, int w, con
 hipError_t launch_proj(int proj, const void* x, int dtype, int64_t n, int64_t ns, int D, int w,
                        const double* mu, const double* isig, const void* R, const void* U,
                        int Cpad, int wpad, int NF, int K, double inv_r, uint32_t* H, hipStream_t s);
+// LDS bytes one work-group of the BF16 (proj 2) or FP8 (proj 3) projection
+// takes for Cpad columns and rows padded to wpad; at most kMaxLdsBytes fit a
+// CU. (The FP64 and FP32 kernels stay far below it for any w <= kMaxW.)
+size_t lowp_lds_bytes(int proj, int Cpad, int wpad);
+constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // ---- index traversal (k_search.hip) ----
 struct SortBufs {

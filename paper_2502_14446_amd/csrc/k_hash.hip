@@ -797,6 +797,14 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_proj_fp8(const T* __r
     quantize_store<MB, NB>(acc, us, a_blk + wbase, col, kk, ns, NF, K, inv_r, H + (int64_t)f * NF * ns);
 }
 
+// Both low-precision kernels take four waves of 64 windows per work-group.
+constexpr int kLowpWB = 4 * 32 * 2;
+
+size_t lowp_lds_bytes(int proj, int Cpad, int wpad)
+{
+    return (size_t)4 * shifted_stride(kLowpWB, wpad) * sizeof(float) + lowp_stage_bytes(proj, Cpad);
+}
+
 template <typename T, int MB>
 static hipError_t go_lowp(int proj, const T* x, int64_t n, int64_t ns, int D, int w, int wpad,
                           const double* mu, const double* isig, const void* R, const float* U,
@@ -807,10 +815,12 @@ static hipError_t go_lowp(int proj, const T* x, int64_t n, int64_t ns, int D, in
     // per CU: eight-wave groups and a lower occupancy measured slower, and
     // fp8 with 32 windows per wave and three work-groups per CU 4% slower
     constexpr int WAVES = 4;
+    const size_t lds = lowp_lds_bytes(proj, MB * 32, wpad);
+    if (lds > kMaxLdsBytes) return hipErrorInvalidValue;   // refused when the plan is made
     if (proj == 2) {
         constexpr int NB = 2, WB = WAVES * 32 * NB;
+        static_assert(WB == kLowpWB, "tile width");
         dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-        const size_t lds = (size_t)4 * shifted_stride(WB, wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void*)k_proj_bf16<T, MB, NB, WAVES>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -818,8 +828,8 @@ static hipError_t go_lowp(int proj, const T* x, int64_t n, int64_t ns, int D, in
                            isig, (const __bf16*)R, U, Cpad, NF, K, inv_r, H);
     } else {
         constexpr int NB = 2, WB = WAVES * 32 * NB;
+        static_assert(WB == kLowpWB, "tile width");
         dim3 grid((unsigned)((ns + WB - 1) / WB), (unsigned)D);
-        const size_t lds = (size_t)4 * shifted_stride(WB, wpad) * sizeof(float) + lowp_stage_bytes(proj, MB * 32);
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void*)k_proj_fp8<T, MB, NB, WAVES>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -675,6 +675,19 @@ static int prepare_impl(momenti_plan** out, int64_t n, int32_t D, int32_t w, int
     const int C = 4 * p->NF;
     p->Cpad = ((C + 31) / 32) * 32;
     p->wpad = ((w + 63) / 64) * 64;
+    if (o.proj == MOMENTI_PROJ_BF16 || o.proj == MOMENTI_PROJ_FP8) {
+        // the projection's work-group holds four shifted copies of its series
+        // tile and two chunks of projection rows in LDS
+        const int proj = o.proj == MOMENTI_PROJ_BF16 ? 2 : 3;
+        if (lowp_lds_bytes(proj, p->Cpad, p->wpad) > kMaxLdsBytes) {
+            int wmax = p->wpad;
+            while (wmax > 64 && lowp_lds_bytes(proj, p->Cpad, wmax) > kMaxLdsBytes) wmax -= 64;
+            const int C0 = p->Cpad;
+            delete p;
+            return fail(MOMENTI_E_ARG, "w=%d too long for the %s projection with %d hash columns (at most %d)", w,
+                        proj == 2 ? "BF16" : "FP8", C0, wmax);
+        }
+    }
     p->st = (hipStream_t)o.stream;
     p->prof.on = o.profile != 0;
     p->prof.enum_only = o.profile == 2;

@@ -48,6 +48,13 @@ def test_argument_errors_are_reported_without_touching_a_gpu():
     o.K = 8
     # mem_limit below the one-repetition index
     assert lib.momenti_prepare(ctypes.byref(h), 1000, 2, 50, 1, 1 << 20, ctypes.byref(o)) == mm.E_NOMEM
+    # the BF16 projection's work-group tile (four shifted copies of the series
+    # tile and two chunks of projection rows) must fit a CU's 160 KiB of LDS:
+    # w <= 7616 with 128 hash columns (refused before the device is touched)
+    ob = mm.make_opts(proj="bf16")
+    assert lib.momenti_prepare(ctypes.byref(h), 9000, 1, 8192, 1, 1 << 30, ctypes.byref(ob)) == mm.E_ARG
+    assert b"too long for the BF16 projection" in lib.momenti_last_error()
+    assert b"at most 7616" in lib.momenti_last_error()
     # search on a NULL plan
     out = (mm.Motif * 1)()
     n = ctypes.c_int32()

@@ -149,6 +149,32 @@ def test_lowp_hash_with_several_lds_chunks(orc, proj, w, D, n):
     plan.close()
 
 
+@pytest.mark.parametrize("proj,w", [("bf16", 7616), ("fp8", 8192)])
+def test_lowp_hash_at_the_longest_windows(orc, proj, w):
+    # the longest windows whose work-group tile fits the CU's LDS: BF16 up to
+    # w = 7616 (163 456 of 163 840 bytes), FP8 up to the ABI's 8192; one
+    # window more is refused when the plan is made
+    s = synth.make_series(300 + w % 97, 1, w + 700, w, 0, 0, dtype="f32")
+    p = dict(w=w, mem_limit=1 << 30)
+    seed = 79
+    plan, _ = _plan(s, p, proj, seed)
+    prm = plan.params()
+    R, U = orc.draw_projections(seed, s.D, w, 4 * prm["NF"])
+    r = prm["r"]
+    assert r == orc.estimate_r(s.x, w, seed)
+    by, pre, sab, amb = orc.hash_dim_lowp(s.x[0], w, R[0], U[0], r, proj)
+    gsym = _unpack(plan.hashes(), 8)
+    bad_out, bad_in, near, diff = _check_symbols(gsym, by[None], pre[None], _lowp_band(w, pre, sab, amb, r, proj)[None], 8)
+    print(f"{proj} w={w}: symbols={by.size} band={near} differing={diff}")
+    assert bad_out == 0 and bad_in == 0
+    plan.close()
+    if proj == "bf16":
+        longer = synth.make_series(301, 1, w + 64 + 700, w + 64, 0, 0, dtype="f32")
+        with pytest.raises(mm.MomentiError) as e:
+            _plan(longer, dict(w=w + 64, mem_limit=1 << 30), proj, seed)
+        assert e.value.code == mm.E_ARG and "at most 7616" in str(e.value)
+
+
 # --------------------------------------------------------------------------- pool
 def test_pool_too_small_for_top_restarts_to_the_oracle_answer(orc):
     # a pool of k = 3 verified pairs: the best pairs are neighbours of one
