@@ -175,6 +175,49 @@ def test_lowp_hash_at_the_longest_windows(orc, proj, w):
         assert e.value.code == mm.E_ARG and "at most 7616" in str(e.value)
 
 
+@pytest.mark.parametrize("proj", ["f64", "f32"])
+def test_longest_window_end_to_end(orc, proj):
+    # w = 8192, the longest window the ABI takes (statistics, the r sample and
+    # the projection tile at their largest): r equal to the oracle's, symbols
+    # within their bands (at this w the FP32 bound, linear in w, is wider than
+    # half a symbol, so for FP32 that part checks little: 15 of 162 036
+    # symbols differ from the FP64 hash), and with the FP64 projection (bit-exact symbols) the
+    # search's answer and stop step equal to the oracle's (Algorithm 1) and
+    # its motif to the exact one; non-trivial pairs lie more than w / 2 apart,
+    # so the 4 501 windows hold one motif and the search ends in the exact
+    # answer (the diagonal sweep, n_s > 4096)
+    w, k = 8192, 1
+    s = synth.make_series(0x8192, 1, w + 4500, w, 0, 0, dtype=proj)
+    p = dict(w=w, mem_limit=1 << 30)
+    seed = 81
+    plan, _ = _plan(s, p, proj, seed, L=20)
+    prm = plan.params()
+    assert prm["L"] == 20
+    r = orc.estimate_r(s.x, w, seed)
+    assert prm["r"] == r
+    R, U = orc.draw_projections(seed, s.D, w, 4 * prm["NF"])
+    ref, pre, sab = _oracle_symbols(orc, s.x, w, R, U, r)
+    gsym = _unpack(plan.hashes(), 8)
+    bad_out, bad_in, near, diff = _check_symbols(gsym, ref, pre, _band(proj, w, pre, sab, r), 8)
+    print(f"{proj} w={w}: symbols={ref.size} band={near} differing={diff}")
+    assert bad_out == 0 and bad_in == 0
+    got, rep, rc = plan.search(1, k, 0.1)
+    plan.close()
+    ex = orc.topk_exact(s.x, w, 1, k)
+    assert len(ex) == k and len(got) == k
+    if proj == "f64":
+        assert diff == 0
+        res = orc.lsh_pipeline(s.x, w, 1, k, 0.1, seed, L_max=20, mem_limit=1 << 30)
+        assert (rep["i_stop"], rep["j_stop"]) == (res["i_stop"], res["J_stop"])
+        assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in res["motifs"]]
+        if res["i_stop"] == 0:
+            assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ex]
+    for m in got:
+        dd, dm, dims, _ = orc.distd(s.x, w, m["a"], m["b"], 1)
+        assert m["dist_d"] == pytest.approx(dd, rel=1e-9) and tuple(m["dims"]) == dims
+    assert got[0]["dist_d"] >= ex[0]["dist_d"] * (1 - 1e-9)
+
+
 # --------------------------------------------------------------------------- pool
 def test_pool_too_small_for_top_restarts_to_the_oracle_answer(orc):
     # a pool of k = 3 verified pairs: the best pairs are neighbours of one
