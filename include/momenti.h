@@ -94,7 +94,8 @@ typedef struct momenti_plan momenti_plan;   /* opaque, owned by the library */
 typedef struct {
     uint64_t seed;            /* seed of the random projections (Philox4x32-10 streams) */
     int32_t K;                /* maximum concatenations: even, 2..8 (default 8, section 7 defaults) */
-    int32_t L;                /* maximum repetitions, 1..1024 (default 200) */
+    int32_t L;                /* maximum repetitions, 1..256 (default 200; 256 makes the
+                                 128 hash columns the projection tile holds) */
     double r;                 /* quantisation width of Eq. drp; <= 0 estimates it (section 6.1) */
     double r_scale;           /* with r <= 0: use r_scale times the estimate (<= 0 means 1).
                                  Section 6.1 leaves r free (any r keeps the guarantee; section

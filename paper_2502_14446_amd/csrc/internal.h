@@ -80,6 +80,10 @@ struct ReplayCtl {
 
 constexpr int kMaxD = 128;
 constexpr int kMaxW = 8192;
+// Repetitions: L = 256 gives m = 16 and 16 + 16 half-functions, 4 (ceil(L / m)
+// + min(L, m)) = 128 hash columns, the projection tile's width (4 MFMA blocks
+// of 32); L = 257 would need 132.
+constexpr int kMaxL = 256;
 constexpr double kFlatRel = 1e-8;      // sigma <= kFlatRel * |mu|: flat window
 
 // ---- index construction (k_hash.hip) ----

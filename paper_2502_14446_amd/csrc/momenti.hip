@@ -646,7 +646,7 @@ static int prepare_impl(momenti_plan** out, int64_t n, int32_t D, int32_t w, int
     if (n - w + 1 > ((int64_t)1 << 31)) return fail(MOMENTI_E_ARG, "too many windows");
     if (dtype != MOMENTI_F64 && dtype != MOMENTI_F32) return fail(MOMENTI_E_ARG, "bad dtype %d", dtype);
     if (o.K < 2 || o.K > 8 || (o.K & 1)) return fail(MOMENTI_E_ARG, "K=%d must be even in [2, 8]", o.K);
-    if (o.L < 1 || o.L > 1024) return fail(MOMENTI_E_ARG, "L=%d outside [1, 1024]", o.L);
+    if (o.L < 1 || o.L > kMaxL) return fail(MOMENTI_E_ARG, "L=%d outside [1, %d]", o.L, kMaxL);
     if (o.proj < MOMENTI_PROJ_F64 || o.proj > MOMENTI_PROJ_FP8)
         return fail(MOMENTI_E_ARG, "projection precision %d not available", o.proj);
     if (o.stop_rule < MOMENTI_STOP_TENSOR || o.stop_rule > MOMENTI_STOP_RIGOROUS)

@@ -46,6 +46,11 @@ def test_argument_errors_are_reported_without_touching_a_gpu():
     o.K = 5
     assert lib.momenti_prepare(ctypes.byref(h), 1000, 2, 50, 1, 1 << 30, ctypes.byref(o)) == mm.E_ARG
     o.K = 8
+    # more repetitions than the projection's 128 hash columns serve (L <= 256)
+    o.L = 257
+    assert lib.momenti_prepare(ctypes.byref(h), 1000, 2, 50, 1, 1 << 30, ctypes.byref(o)) == mm.E_ARG
+    assert b"L=257 outside [1, 256]" in lib.momenti_last_error()
+    o.L = 200
     # mem_limit below the one-repetition index
     assert lib.momenti_prepare(ctypes.byref(h), 1000, 2, 50, 1, 1 << 20, ctypes.byref(o)) == mm.E_NOMEM
     # the BF16 projection's work-group tile (four shifted copies of the series
