@@ -203,8 +203,10 @@ int momenti_prepare(momenti_plan** out, int64_t n, int32_t D, int32_t w, int32_t
  * statistics, the r estimate (unless fixed by opts.r), and the tensored hash
  * index of every window of every dimension. series: [D][n] of the plan's
  * dtype, host or device memory per opts.series_on_device (device memory is
- * borrowed until momenti_destroy). May be called again with new data.
- * Errors: E_ARG (null series), E_NOMEM, E_DEVICE. */
+ * borrowed until momenti_destroy). May be called again with new data; until
+ * such a call succeeds the plan has no index (searches return E_STATE).
+ * Errors: E_ARG (null series, or a value that is NaN or infinite: the message
+ * names the first, series[f][t]), E_NOMEM, E_DEVICE. */
 int momenti_hash(momenti_plan* p, const void* series);
 
 /* Index traversal (Algorithm 1 rounds i = K..1, repetitions j = 1..L, with

@@ -87,6 +87,10 @@ constexpr int kMaxL = 256;
 constexpr double kFlatRel = 1e-8;      // sigma <= kFlatRel * |mu|: flat window
 
 // ---- index construction (k_hash.hip) ----
+// *first = index (f n + t) of the first non-finite series value, left as set
+// by the caller (~0) when there is none.
+hipError_t launch_first_nonfinite(const void* x, int dtype, int64_t total, unsigned long long* first,
+                                  hipStream_t s);
 hipError_t launch_stats(const void* x, int dtype, int64_t n, int64_t ns, int D, int w,
                         double* mu, double* isig, hipStream_t s);
 hipError_t launch_rsample(const void* x, int dtype, int64_t n, int D, int w, const int64_t* win,

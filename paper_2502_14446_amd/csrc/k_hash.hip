@@ -111,6 +111,36 @@ __global__ __launch_bounds__(kStatsThreads) void k_stats(const T* __restrict__ x
     }
 }
 
+// The first value of the series in [D][n] order that is NaN or infinite
+// (the method is defined on real values), or ~0 when all are finite. Each
+// thread visits its values in increasing index order and stops at its first
+// such value, so the minimum over threads is the first overall.
+template <typename T>
+__global__ __launch_bounds__(256) void k_first_nonfinite(const T* __restrict__ x, int64_t total,
+                                                        unsigned long long* __restrict__ first)
+{
+    unsigned long long mine = ~0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+        if (!isfinite(x[i])) {
+            mine = (unsigned long long)i;
+            break;
+        }
+    if (mine != ~0ull) atomicMin(first, mine);
+}
+
+hipError_t launch_first_nonfinite(const void* x, int dtype, int64_t total, unsigned long long* first,
+                                  hipStream_t s)
+{
+    const int64_t want = (total + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_first_nonfinite<double>, dim3(blocks), dim3(256), 0, s, (const double*)x, total, first);
+    else
+        hipLaunchKernelGGL(k_first_nonfinite<float>, dim3(blocks), dim3(256), 0, s, (const float*)x, total, first);
+    return hipGetLastError();
+}
+
 hipError_t launch_stats(const void* x, int dtype, int64_t n, int64_t ns, int D, int w, double* mu,
                         double* isig, hipStream_t s)
 {

@@ -775,6 +775,23 @@ int momenti_hash(momenti_plan* p, const void* series)
         }
         HIP_OK(hipMemcpyAsync(p->series, series, sbytes, hipMemcpyHostToDevice, p->st));
     }
+    // a new series replaces the index: until it is built the plan has none
+    p->hashed = false;
+    p->have_stats = false;
+    {
+        // every value must be finite (the definitions of section 3.1 are over
+        // real values); the statistics buffer's first word holds the answer
+        // before the statistics overwrite it
+        unsigned long long first = ~0ull;
+        unsigned long long* d_first = reinterpret_cast<unsigned long long*>(p->mu);
+        HIP_OK(hipMemcpyAsync(d_first, &first, sizeof first, hipMemcpyHostToDevice, p->st));
+        HIP_OK(launch_first_nonfinite(p->series, p->dtype, p->n * p->D, d_first, p->st));
+        HIP_OK(hipMemcpyAsync(&first, d_first, sizeof first, hipMemcpyDeviceToHost, p->st));
+        HIP_OK(hipStreamSynchronize(p->st));
+        if (first != ~0ull)
+            return fail(MOMENTI_E_ARG, "series[%lld][%lld] is not finite (NaN or infinity)",
+                        (long long)(first / (unsigned long long)p->n), (long long)(first % (unsigned long long)p->n));
+    }
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));

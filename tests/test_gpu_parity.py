@@ -571,6 +571,31 @@ def test_constant_series_collision_storm(orc):
     plan.close()
 
 
+def test_non_finite_series_is_refused():
+    # the definitions (section 3.1) are over real values: momenti_hash names
+    # the first NaN or infinite value, the plan is left without an index, and
+    # a finite series is taken again afterwards (device and host series)
+    s, p = synth.workload("tiny")
+    cases = [(np.nan, 2, 777, True), (np.inf, 0, s.n - 1, True), (-np.inf, 3, 0, True), (np.nan, 1, 5, False)]
+    for bad, f, t, on_dev in cases:
+        y = s.x.copy()
+        y[f, t] = bad
+        y[f, t + 1 if t + 1 < s.n else t - 1] = np.nan      # a later one is not the first
+        plan = mm.Plan(s.n, s.D, p["w"], "f64", p["mem_limit"], device_series=on_dev, seed=7, proj="f64")
+        src = torch.from_numpy(y).to("cuda") if on_dev else y
+        with pytest.raises(mm.MomentiError) as e:
+            plan.hash(src)
+        first = (f, min(t, t + 1 if t + 1 < s.n else t - 1))
+        assert e.value.code == mm.E_ARG and f"series[{first[0]}][{first[1]}]" in str(e.value), str(e.value)
+        with pytest.raises(mm.MomentiError) as e:
+            plan.search(p["d"], p["k"], p["delta"])
+        assert e.value.code == mm.E_STATE
+        plan.hash(torch.from_numpy(s.x.copy()).to("cuda") if on_dev else s.x)
+        got, rep, rc = plan.search(p["d"], p["k"], p["delta"])
+        assert rc in (mm.OK, mm.OK_FALLBACK) and len(got) == p["k"]
+        plan.close()
+
+
 def test_argument_errors_on_device():
     s, p = synth.workload("tiny")
     plan, _ = _plan(s, p, "f64", 1)
