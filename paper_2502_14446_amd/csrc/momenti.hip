@@ -1780,6 +1780,9 @@ static int exact_sweep(momenti_plan* p, int d, int k, momenti_motif* out, int32_
     const int64_t chunks = (p->ns - first + Lc - 1) / Lc;
     const int64_t items = groups * chunks;
     const double eps = (double)d * std::sqrt(1e-6 * (double)p->w);
+    // no pair is farther apart: a z-normalised window has norm sqrt(w) (a flat
+    // one is all zeros), so each dimension's distance is at most 2 sqrt(w)
+    const double dmax = 2.0 * d * std::sqrt((double)p->w);
     const double elem_x = p->dtype == MOMENTI_F64 ? 8.0 : 4.0;
 
     auto read_top = [&](int* topn, double* kth) -> int {
@@ -1896,7 +1899,9 @@ static int exact_sweep(momenti_plan* p, int d, int k, momenti_motif* out, int32_
             continue;
         }
         if ((rc = read_top(&topn, &kth))) return rc;
-        if (std::isinf(theta_min) || (topn >= k && kth < theta_min - eps)) {
+        // certified when the cut left no pair out (fewer than k picks exist
+        // then), or TOP's k-th pick lies below every pair it left out
+        if (std::isinf(theta_min) || theta_min - eps > dmax || (topn >= k && kth < theta_min - eps)) {
             const int got = std::min(topn, k);
             std::vector<VRec> tv(std::max(got, 1));
             if (got) HIP_OK(copy_sync(p, tv.data(), p->top, (size_t)got * sizeof(VRec), hipMemcpyDeviceToHost));
@@ -1904,8 +1909,9 @@ static int exact_sweep(momenti_plan* p, int d, int k, momenti_motif* out, int32_
             *n_out = got;
             return MOMENTI_OK;
         }
-        // not certified: widen the cut past TOP's k-th pick (or double it)
-        theta = topn >= k ? kth + 4.0 * eps : 2.0 * theta_min;
+        // not certified: widen the cut past TOP's k-th pick, or double it, at
+        // most to a cut that leaves no pair out
+        theta = topn >= k ? kth + 4.0 * eps : std::min(2.0 * theta_min, dmax + 2.0 * eps);
     }
     return fail(MOMENTI_E_DEVICE, "exact answer: the sweep did not certify its result");
 }

@@ -558,6 +558,30 @@ def test_fewer_pairs_than_k(orc):
     plan.close()
 
 
+@pytest.mark.skip(reason="k far above the non-overlapping pairs present makes the exact answer keep every "
+                         "non-trivial pair (8.7e6 here) in the pool, and the pool's single-work-group merge copies the "
+                         "whole pool per chunk of 1024 new records (quadratic): the search ran past 140 s on the GPU "
+                         "and is not run there again until the pool takes records in bulk")
+def test_largest_k_with_fewer_motifs(orc):
+    # k = 4096, the largest the ABI takes, on 4 185 windows that hold a few
+    # hundred non-overlapping pairs: TOP never fills, no step stops, and the
+    # exact answer comes from the device's diagonal sweep (n_s > 4096). With
+    # fewer than k picks no cut below the largest possible distance (2 d
+    # sqrt(w)) can certify it: the sweep widens its cut up to that bound and
+    # the pool grows until it holds every pair. It must equal O1's answer.
+    s = synth.make_series(4096, 1, 4200, 16, 0, 0, dtype="f64")
+    p = dict(w=16, mem_limit=8 << 30)
+    plan, _ = _plan(s, p, "f64", 3, K=4, L=4)
+    got, rep, rc = plan.search(1, 4096, 0.1)
+    plan.close()
+    ex = orc.topk_exact(s.x, 16, 1, 4096)
+    assert 100 < len(ex) < 4096
+    assert rc == mm.OK_FALLBACK
+    assert [(m["a"], m["b"]) for m in got] == [(m["a"], m["b"]) for m in ex]
+    for g, o in zip(got, ex):
+        assert g["dist_d"] == pytest.approx(o["dist_d"], rel=1e-9)
+
+
 def test_constant_series_collision_storm(orc):
     # every window is flat: all pairs collide everywhere, every distance is 0
     x = np.full((2, 160), 2.5)
