@@ -232,15 +232,15 @@ def batch_workload(seed: int, count: int = 512, n_lo: int = 10_000, n_hi: int = 
     return out
 
 
-# The many-series workloads: the survey's generator (k = 5 with two planted
-# motifs, D up to 64: most searches need very long traversals), and a variant
+# The many-series workloads: a fleet of independent series (k = 5 with two
+# planted motifs, D up to 64: most searches need very long traversals), and a variant
 # whose series can stop (k = planted motifs = 3, D in 5..16 so that d >= 2,
 # r at 6 times the estimate: with the estimate itself half of them do not
 # stop above the exact fallback or the work budget).
 BATCHES = {
     "batch64": dict(count=64, n_lo=10_000, n_hi=200_000, D_lo=5, D_hi=16, k=3, n_motifs=3, r_scale=6.0),
-    "batch64_survey": dict(count=64),
-    # the survey's generator at full size: 512 series, n log-uniform in
+    "batch64_k5": dict(count=64),
+    # the fleet at full size: 512 series, n log-uniform in
     # [1e4, 5e5], D in 3..64, w in {50, 100, 200}, d = ceil(D / 4), k = 5,
     # two planted motifs each; r at 6 times the estimate
     "batch512": dict(count=512, r_scale=6.0),
