@@ -357,9 +357,14 @@ def topk_batch(jobs, mem_limit: int = 8 << 30, workers: int = 4, dtype: str = "f
     out = (Motif * max(total, 1))()
     n_out = (C.c_int32 * max(len(jobs), 1))()
     status = (C.c_int32 * max(len(jobs), 1))()
+    not_run = -(1 << 30)
+    for q in range(len(jobs)):
+        status[q] = not_run
     reps = (Report * max(len(jobs), 1))()
     rc = lib().momenti_topk_batch(arr, len(jobs), mem_limit, C.byref(o), workers, out, n_out, status, reps)
-    if rc in (E_ARG,):
+    # an error before any job ran (bad arguments of the call) raises; a job's
+    # own error is left in its status, beside the other jobs' answers
+    if rc < 0 and all(status[q] == not_run for q in range(len(jobs))):
         _check(rc)
     res, off = [], 0
     for q, j in enumerate(jobs):

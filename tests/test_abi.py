@@ -86,6 +86,17 @@ def test_batch_argument_errors_are_reported_without_touching_a_gpu():
     assert b"job 1" in lib.momenti_last_error()
 
 
+def test_batch_binding_raises_for_errors_of_the_call():
+    # bad arguments of the call itself raise (no job ran); a job's own error
+    # would be returned in its status instead
+    import numpy as np
+    from paper_2502_14446_amd import momenti as mm
+    jobs = [dict(series=np.zeros((2, 100), dtype=np.float32), w=10, d=1, k=1, delta=0.1)]
+    with pytest.raises(mm.MomentiError) as e:
+        mm.topk_batch(jobs, workers=0)
+    assert e.value.code == mm.E_ARG and "workers" in str(e.value)
+
+
 def test_binding_refuses_to_run_without_the_library(monkeypatch):
     from paper_2502_14446_amd import momenti as mm
     monkeypatch.setattr(mm, "LIB_PATH", "/nonexistent/libmomenti.so")

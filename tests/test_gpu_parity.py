@@ -147,6 +147,23 @@ def test_batch_matches_one_series_at_a_time(on_device):
         assert got == ref   # indices, dims and FP64 distances bit for bit
 
 
+def test_batch_job_with_a_nan_fails_alone():
+    # a job whose series holds a NaN gets E_ARG in its status; the batch still
+    # answers every other job as a call of its own would
+    jobs = _batch_jobs()[:3]
+    bad = np.array(jobs[1]["series"], copy=True)
+    bad[0, 11] = np.nan
+    jobs[1] = dict(jobs[1], series=bad)
+    res, rc = mm.topk_batch(jobs, mem_limit=1 << 30, workers=2, seed=77)
+    assert rc == mm.E_ARG
+    assert res[1][2] == mm.E_ARG and res[1][0] == []
+    for q in (0, 2):
+        j = jobs[q]
+        got, rep, st = res[q]
+        ref, rrep, rrc = mm.topk(j["series"], j["w"], j["d"], j["k"], j["delta"], mem_limit=1 << 30, seed=77)
+        assert st == rrc and got == ref
+
+
 def test_work_budget_returns_partial_answer(orc):
     s, p = synth.workload("tiny")
     seed = synth.LSH_SEED["tiny"]
