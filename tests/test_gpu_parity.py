@@ -478,6 +478,8 @@ def test_end_to_end_close_motif_stops_like_the_oracle(orc):
     (4, 900, 30, 2, 1, 6, 1),      # a single repetition
     (2, 21, 20, 1, 1, 8, 10),      # n = w + 1: two windows, one trivial pair, nothing to find
     (2, 800, 24, 1, 2, 8, 256),    # the most repetitions: 16 + 16 half-functions, all 128 hash columns
+    (2, 400, 4, 1, 2, 8, 20),      # the shortest window: pairs 3 or more apart are not trivial
+    (3, 500, 5, 2, 3, 8, 20),      # an odd window: 2 (b - a) > 5
 ])
 def test_degenerate_shapes_match_oracle(orc, D, n, w, d, k, K, L):
     s = synth.make_series(70 + D + n, D, n, w, 1 if n >= 10 * w else 0, d, dtype="f64")
